@@ -1,0 +1,95 @@
+"""Planted mistakes in the oracle (CPU only): each plausible slip must make at least one pin fail.
+
+The mistakes are patched into ``oracle.reference`` for the duration of one test; the pins are the
+unmodified test functions of the other oracle test modules.
+"""
+import numpy as np
+import pytest
+
+import oracle.reference as R
+import tests.test_oracle_lb_ed as T_lb
+import tests.test_oracle_search as T_search
+import tests.test_oracle_summary as T_sum
+
+
+def _fails(fn, *args):
+    with pytest.raises(AssertionError):
+        fn(*args)
+
+
+def test_boundary_side_flip_is_caught(monkeypatch):
+    real = R.breakpoints_at_cardinality
+
+    def isax_left(paa_values, bits=8):
+        b = real(bits)
+        return np.searchsorted(b[1:-1], np.asarray(paa_values, np.float64), side="left").astype(np.uint8)
+
+    monkeypatch.setattr(R, "isax", isax_left)
+    monkeypatch.setattr(T_sum, "isax", isax_left)
+    _fails(T_sum.test_symbol_on_boundary_goes_up_and_extremes)
+
+
+def test_breakpoint_index_shift_is_caught(monkeypatch):
+    real = R.breakpoints_at_cardinality
+    monkeypatch.setattr(R, "breakpoints_at_cardinality",
+                        lambda bits: np.concatenate([real(bits)[1:], [np.inf]]))
+    _fails(T_sum.test_paper_word_example)
+
+
+def test_dropped_segment_length_factor_is_caught(monkeypatch):
+    real = R.lower_bound_sq
+    monkeypatch.setattr(T_lb, "lower_bound_sq", lambda q, s, L, bits=8: real(q, s, 1, bits))
+    _fails(T_lb.test_hand_worked_example)
+
+
+def test_lower_bound_branch_sign_is_caught(monkeypatch):
+    def bad_delta(qp, lo, hi):
+        d = np.zeros(np.broadcast(qp, lo).shape)
+        d = np.where(qp < lo, lo + qp, d)        # wrong sign in the BELOW branch
+        d = np.where(qp > hi, qp - hi, d)
+        return d
+    monkeypatch.setattr(R, "_delta", bad_delta)
+    _fails(T_lb.test_lb_branches_individually)
+
+
+def test_swapped_region_bounds_are_caught(monkeypatch):
+    real = R._delta
+    monkeypatch.setattr(R, "_delta", lambda qp, lo, hi: real(qp, hi, lo))
+    _fails(T_lb.test_hand_worked_example)
+
+
+def test_shifted_distance_index_is_caught(monkeypatch):
+    def bad_ed(q, X):
+        q = np.asarray(q, np.float32).astype(np.float64)
+        X = np.asarray(X, np.float32)
+        Xm = X[None, :] if X.ndim == 1 else X
+        acc = np.zeros(Xm.shape[0])
+        for j in range(Xm.shape[1]):
+            d = q[j] - Xm[:, (j + 1) % Xm.shape[1]].astype(np.float64)   # off-by-one column
+            acc = acc + d * d
+        return acc[0] if X.ndim == 1 else acc
+    monkeypatch.setattr(T_lb, "ed_sq", bad_ed)
+    _fails(T_lb.test_ed_against_library_routines)
+
+
+def test_root_key_bit_order_is_caught(monkeypatch):
+    def bad_root(sym8):
+        top = (np.asarray(sym8, np.uint8) >> 7).astype(np.uint32)
+        key = np.zeros(top.shape[:-1], np.uint32)
+        for s in range(16):
+            key = key | (top[..., s] << np.uint32(s))
+        return key
+    monkeypatch.setattr(T_sum, "root_key", bad_root)
+    _fails(T_sum.test_root_key_bit_order)
+
+
+def test_strict_tie_rule_is_caught(monkeypatch):
+    real_nn = R.nn_bruteforce
+
+    def last_index_nn(q, X):
+        d2 = R.ed_sq(q, X)
+        i = int(len(d2) - 1 - np.argmin(d2[::-1]))   # ties to the highest index
+        return i, float(d2[i]), float(np.sqrt(d2[i]))
+    monkeypatch.setattr(T_search, "nn_bruteforce", last_index_nn)
+    _fails(T_search.test_twin_ties_and_degenerate)
+    monkeypatch.setattr(T_search, "nn_bruteforce", real_nn)
