@@ -1,0 +1,193 @@
+/*
+ * paris.h — C ABI of the MI355X exact 1-NN search over iSAX summaries (ParIS+, arXiv 2009.00166).
+ *
+ * Problem (Section 2.1, "Similarity Search"): given a query series of length n and a collection
+ * of series of the same length, return the series of the collection with the smallest Euclidean
+ * distance to the query. Ties go to the lowest series index. The paper's ExactSearch returns
+ * only the best-so-far distance (Section 3.3.3); these calls return the index and the distance.
+ *
+ * Method: every series is summarised once (paris_build) into a 16-segment, 8-bit iSAX word
+ * (Section 2.2: PAA segment means quantised against 255 Gaussian boundaries). A query
+ * (paris_query_exact) takes an approximate-search seed as its first best-so-far distance
+ * (Section 3.3), scans the whole array of words with the iSAX lower bound and keeps the series
+ * the bound cannot prune (the LBC workers of Section 3.3.3), computes real distances of the
+ * survivors with early abandoning while an atomic minimum tightens the best-so-far (the RDC
+ * workers), and resolves the final comparison in float64.
+ *
+ * Conventions for every call:
+ *   - Return value: PARIS_OK (0) or a negative paris_status. No exception, abort or exit ever
+ *     crosses this boundary.
+ *   - "_dev" pointers are device (HBM) addresses on the current HIP device; others are host.
+ *   - hip_stream is a hipStream_t passed as void* (NULL = the default stream).
+ *   - Argument errors are detected on the host before anything is launched; outputs are then
+ *     left untouched.
+ *   - Series indices are 0-based positions in the collection array. n_series must be in
+ *     [1, 2^32 - 2]; length must be a positive multiple of 16.
+ *   - Floating-point data are IEEE float32, row-major [n_series][length], 16-byte aligned.
+ *     The library does not z-normalise; it searches the values as given.
+ */
+#ifndef PARIS_H
+#define PARIS_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum paris_status {
+    PARIS_OK = 0,
+    PARIS_EINVAL = -1,     /* bad argument, or NaN/Inf found in the data or the query      */
+    PARIS_ENOMEM = -2,     /* workspace smaller than paris_workspace_size()                  */
+    PARIS_ENODEV = -3,     /* no usable HIP device                                           */
+    PARIS_EHIP = -4,       /* a HIP runtime call failed; the handle must then be freed       */
+    PARIS_EOVERFLOW = -5,  /* a device buffer overflowed (cannot happen at default capacity) */
+    PARIS_ESTATE = -6      /* invalid or freed handle                                        */
+} paris_status;
+
+enum { PARIS_LEAF_ROOT16 = 0, PARIS_LEAF_EQUAL_COUNT = 1 };
+
+/* Index configuration. Start from paris_default_config(). */
+typedef struct paris_config {
+    int32_t segments;   /* w: must be 16 (Section 3 fixes w = 16)                              */
+    int32_t card_bits;  /* must be 8: 256 symbols, the maximum cardinality (Section 2.2)        */
+    int32_t leaf_mode;  /* PARIS_LEAF_ROOT16: leaves are the root subtrees, i.e. runs of equal
+                           first bits of the 16 symbols (Section 3, pipeline overview).
+                           PARIS_LEAF_EQUAL_COUNT: n_leaves equal slices of the key order.    */
+    int32_t n_leaves;   /* EQUAL_COUNT only: 1 .. 65536 (default 4096)                          */
+    int32_t seed_cap;   /* ROOT16 only: at most this many members of the query's subtree are
+                           scanned by the approximate search (default 2048). 0 disables the
+                           seed: the best-so-far starts at +inf (the answer is unchanged).     */
+    int32_t reserved[3];
+} paris_config;
+
+/* Per-query counters (paris_query_batch sums them over the batch). */
+typedef struct paris_stats {
+    int64_t lb_survivors;  /* series whose lower bound did not prune them                     */
+    int64_t refined;       /* survivors whose distance computation started                   */
+    int64_t abandoned;     /* of those, stopped early because the partial sum passed the BSF */
+    int64_t bsf_updates;   /* times the atomic best-so-far went down during refinement       */
+    int64_t resolved;      /* candidates re-scored in float64 for the final comparison       */
+    int64_t seed_index;    /* series found by the approximate search (-1 if none)            */
+    double  seed_dist;     /* its float32-computed distance (+inf if none)                   */
+    int64_t seed_lo, seed_hi;  /* sorted-position window scanned by the approximate search   */
+} paris_stats;
+
+typedef struct paris_index paris_index;  /* opaque, library-owned host handle */
+
+/* Device-buffer addresses inside a built index's workspace (for inspection and tests). */
+typedef struct paris_layout {
+    const uint8_t  *sax_dev;    /* uint8  [n_series][16]: iSAX word of series i at row i       */
+    const uint64_t *keys_dev;   /* uint64 [n_series]: leaf keys in ascending (key, index) order */
+    const uint32_t *perm_dev;   /* uint32 [n_series]: series index at each sorted position      */
+    const uint32_t *roff_dev;   /* uint32 [65537]: first sorted position of each root subtree  */
+    int64_t n_series;
+    int32_t length;
+    int32_t leaf_mode, n_leaves, seed_cap;
+} paris_layout;
+
+/* Query summaries as computed on the device (inspection and tests). */
+typedef struct paris_query_info {
+    double   paa[16];       /* segment means (float64, ascending sum, divided by L)          */
+    uint8_t  sym[16];       /* 8-bit iSAX symbols                                            */
+    uint32_t root;          /* 16-bit root key: first bit of every symbol, segment 0 = MSB   */
+    uint32_t pad;
+    uint64_t k64;           /* leaf key: bit planes 7..4 of the symbols, segment 0 first     */
+    int64_t  win_lo, win_hi;  /* approximate-search window (sorted positions)                */
+} paris_query_info;
+
+/* Fills *cfg with the defaults (16 segments, 8 bits, ROOT16, 4096 leaves, seed_cap 2048). */
+paris_status paris_default_config(paris_config *cfg);
+
+/* Bytes of device workspace paris_build needs for this collection shape (host-only call). */
+paris_status paris_workspace_size(int64_t n_series, int32_t length, const paris_config *cfg,
+                                  size_t *bytes);
+
+/*
+ * Summarise the collection and build the leaf order (Section 3.1, IndexBulkLoading: the iSAX
+ * word of the series at position p is stored at SAX[p]; root subtrees are the RecBufs). The
+ * grouping into subtrees is a stable sort by leaf key instead of locked buffer inserts.
+ *   series_dev      float32 [n_series][length], BORROWED: must stay alive and unmodified until
+ *                   paris_free. Every value must be finite (else PARIS_EINVAL).
+ *   workspace_dev   at least paris_workspace_size() bytes of device memory, 256-byte aligned,
+ *                   BORROWED for the life of the handle; the library owns its contents.
+ *   out             receives the handle (library-owned host memory; release with paris_free).
+ * Synchronous: returns after the build finished on hip_stream.
+ */
+paris_status paris_build(const float *series_dev, int64_t n_series, int32_t length,
+                         const paris_config *cfg, void *workspace_dev, size_t workspace_bytes,
+                         void *hip_stream, paris_index **out);
+
+/* Addresses and shape of a built index (host-only call). */
+paris_status paris_get_layout(const paris_index *idx, paris_layout *out);
+
+/*
+ * Exact 1-NN of one query (Section 3.3.3, ExactSearch with its LBC and RDC workers).
+ *   query_dev   float32 [length] on the device; must be finite (else PARIS_EINVAL).
+ *   nn_index    host out: index of the nearest series (lowest index among exact ties).
+ *   nn_dist     host out: its Euclidean distance, from the float64 squared distance
+ *               (ascending-order sum of float64 squared differences), correctly rounded sqrt.
+ *   stats       optional host out (may be NULL).
+ * Synchronous. One call in flight per handle.
+ */
+paris_status paris_query_exact(paris_index *idx, const float *query_dev, int64_t *nn_index,
+                               double *nn_dist, paris_stats *stats, void *hip_stream);
+
+/*
+ * Exact 1-NN of n_queries queries.
+ *   queries_dev   float32 [n_queries][length] on the device, finite.
+ *   nn_index_dev  int64 [n_queries] device out;  nn_dist_dev  float64 [n_queries] device out.
+ *   stats         optional host out, summed over the batch (may be NULL; forces a sync).
+ * Asynchronous on hip_stream when stats is NULL: outputs are valid after the stream is
+ * synchronised; a NaN/Inf query then yields index -1 and distance NaN for that query.
+ */
+paris_status paris_query_batch(paris_index *idx, const float *queries_dev, int64_t n_queries,
+                               int64_t *nn_index_dev, double *nn_dist_dev, paris_stats *stats,
+                               void *hip_stream);
+
+/*
+ * Query summaries as the device computes them (Section 2.2 on the query; Section 3.3.1 table):
+ *   info          host out (may be NULL).
+ *   table_dev     optional device out float32 [16][256]: per-segment lower-bound terms
+ *                 L * delta(q_s, c)^2, rounded toward zero (so their sum never exceeds the bound).
+ *   coarse_dev    optional device out float32 [16][32]: the same at 32 symbols (5-bit prefix);
+ *                 entry g is the minimum of the 8 entries c = 8g .. 8g+7.
+ * Synchronous.
+ */
+paris_status paris_query_info_get(paris_index *idx, const float *query_dev, paris_query_info *info,
+                                  float *table_dev, float *coarse_dev, void *hip_stream);
+
+/*
+ * The lower-bound scan alone (Section 3.3.3, LBC worker) against a caller-given threshold on
+ * the squared bound: every series whose float32 bound is <= threshold_sq is written, in no
+ * particular order, as (index, bound) to idx_dev[0..) / lb_dev[0..).
+ *   capacity      entries available in idx_dev / lb_dev.
+ *   count         host out: number of series that passed (may exceed capacity; then only
+ *                 capacity entries were written and PARIS_EOVERFLOW is returned).
+ * Synchronous.
+ */
+paris_status paris_lb_scan(paris_index *idx, const float *query_dev, float threshold_sq,
+                           uint32_t *idx_dev, float *lb_dev, int64_t capacity, int64_t *count,
+                           void *hip_stream);
+
+/*
+ * Per-phase device timing of paris_query_exact, with HIP events recorded on the call's stream
+ * around each kernel: [0] prepare, [1] approximate-search seed, [2] lower-bound scan,
+ * [3] refine, [4] resolve. paris_set_timing(idx, 1) enables it and zeroes the totals;
+ * paris_get_timing returns the summed milliseconds and the number of timed queries.
+ */
+paris_status paris_set_timing(paris_index *idx, int32_t enable);
+paris_status paris_get_timing(const paris_index *idx, double *ms_out5, int64_t *n_queries);
+
+/* Release the handle (the borrowed buffers are not touched). NULL is accepted. */
+paris_status paris_free(paris_index *idx);
+
+/* Static English text for a status code. */
+const char *paris_status_string(paris_status s);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PARIS_H */

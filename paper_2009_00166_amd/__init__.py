@@ -1,0 +1,208 @@
+"""MI355X-native exact 1-NN search over iSAX summaries (ParIS+, arXiv 2009.00166).
+
+Python face of libparis.so (include/paris.h). PyTorch provides device memory and the HIP
+stream; every step of the search runs in the library's HIP kernels. There is no CPU fallback:
+if the library is missing or no GPU is present, the calls raise.
+
+    import torch, paper_2009_00166_amd as paris
+    X = torch.from_numpy(series).cuda()        # float32 [N, n], z-normalised
+    index = paris.build(X)                      # iSAX summaries + leaf order on the GPU
+    i, d = index.query(q_dev)                   # exact 1-NN of one query
+    I, D = index.query_batch(Q_dev)             # exact 1-NN of many queries
+"""
+from __future__ import annotations
+
+import ctypes
+
+from ._binding import (LEAF_EQUAL_COUNT, LEAF_ROOT16, PARIS_OK, ParisConfig, ParisError,  # noqa: F401
+                       ParisLayout, ParisQueryInfo, ParisStats, check, load_library)
+
+__all__ = ["build", "Index", "ParisError", "LEAF_ROOT16", "LEAF_EQUAL_COUNT", "load_library"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream_ptr(stream=None):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _dev_ptr(t, dtype, ndim=None, what="tensor"):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{what} must be a CUDA (HIP) tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{what} must be {dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{what} must be contiguous")
+    if ndim is not None and t.dim() != ndim:
+        raise ValueError(f"{what} must have {ndim} dimensions")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def default_config(**kw) -> ParisConfig:
+    cfg = ParisConfig()
+    check(load_library().paris_default_config(ctypes.byref(cfg)), "paris_default_config")
+    for k, v in kw.items():
+        setattr(cfg, k, int(v))
+    return cfg
+
+
+def workspace_size(n_series: int, length: int, cfg: ParisConfig | None = None) -> int:
+    cfg = cfg or default_config()
+    out = ctypes.c_size_t(0)
+    check(load_library().paris_workspace_size(int(n_series), int(length), ctypes.byref(cfg),
+                                              ctypes.byref(out)), "paris_workspace_size")
+    return int(out.value)
+
+
+class Index:
+    """A built index. Borrows the series tensor and owns a workspace tensor."""
+
+    def __init__(self, series, cfg: ParisConfig | None = None, stream=None):
+        torch = _torch()
+        lib = load_library()
+        p = _dev_ptr(series, torch.float32, 2, "series")
+        n_series, length = series.shape
+        self.cfg = cfg or default_config()
+        nbytes = workspace_size(n_series, length, self.cfg)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=series.device)
+        self.series = series  # keep the borrowed collection alive
+        self.n_series, self.length = int(n_series), int(length)
+        self._h = ctypes.c_void_p()
+        check(lib.paris_build(p, n_series, length, ctypes.byref(self.cfg),
+                              ctypes.c_void_p(self.workspace.data_ptr()), nbytes, _stream_ptr(stream),
+                              ctypes.byref(self._h)), "paris_build")
+
+    # -- queries --------------------------------------------------------------------------
+    def query(self, q, stream=None, with_stats: bool = False):
+        """Exact 1-NN of one query (float32 [length] on the device): (index, distance[, stats])."""
+        torch = _torch()
+        qp = _dev_ptr(q, torch.float32, 1, "query")
+        if q.shape[0] != self.length:
+            raise ValueError("query length differs from the collection's")
+        idx = ctypes.c_int64(-1)
+        dist = ctypes.c_double(0.0)
+        st = ParisStats()
+        check(load_library().paris_query_exact(self._h, qp, ctypes.byref(idx), ctypes.byref(dist),
+                                               ctypes.byref(st) if with_stats else None,
+                                               _stream_ptr(stream)), "paris_query_exact")
+        if with_stats:
+            return int(idx.value), float(dist.value), st.as_dict()
+        return int(idx.value), float(dist.value)
+
+    def query_batch(self, Q, stream=None, with_stats: bool = False, out=None):
+        """Exact 1-NN of every row of Q (float32 [M, length] on the device).
+
+        Returns device tensors (int64 [M], float64 [M]); asynchronous unless ``with_stats``."""
+        torch = _torch()
+        qp = _dev_ptr(Q, torch.float32, 2, "queries")
+        if Q.shape[1] != self.length:
+            raise ValueError("query length differs from the collection's")
+        M = Q.shape[0]
+        if out is None:
+            I = torch.empty(M, dtype=torch.int64, device=Q.device)
+            D = torch.empty(M, dtype=torch.float64, device=Q.device)
+        else:
+            I, D = out
+        st = ParisStats()
+        check(load_library().paris_query_batch(self._h, qp, M, ctypes.c_void_p(I.data_ptr()),
+                                               ctypes.c_void_p(D.data_ptr()),
+                                               ctypes.byref(st) if with_stats else None,
+                                               _stream_ptr(stream)), "paris_query_batch")
+        if with_stats:
+            return I, D, st.as_dict()
+        return I, D
+
+    # -- inspection -----------------------------------------------------------------------
+    def layout(self) -> ParisLayout:
+        lay = ParisLayout()
+        check(load_library().paris_get_layout(self._h, ctypes.byref(lay)), "paris_get_layout")
+        return lay
+
+    def sax(self):
+        """uint8 [N, 16] device view of the iSAX words (row i = series i)."""
+        torch = _torch()
+        off = self.layout().sax_dev - self.workspace.data_ptr()
+        return self.workspace[off:off + 16 * self.n_series].view(self.n_series, 16)
+
+    def sorted_keys(self):
+        torch = _torch()
+        off = self.layout().keys_dev - self.workspace.data_ptr()
+        return self.workspace[off:off + 8 * self.n_series].view(torch.int64)
+
+    def sorted_positions(self):
+        torch = _torch()
+        off = self.layout().perm_dev - self.workspace.data_ptr()
+        return self.workspace[off:off + 4 * self.n_series].view(torch.int32)
+
+    def root_offsets(self):
+        torch = _torch()
+        off = self.layout().roff_dev - self.workspace.data_ptr()
+        return self.workspace[off:off + 4 * 65537].view(torch.int32)
+
+    def query_info(self, q, stream=None, tables: bool = False):
+        torch = _torch()
+        qp = _dev_ptr(q, torch.float32, 1, "query")
+        info = ParisQueryInfo()
+        t8 = t5 = None
+        if tables:
+            t8 = torch.empty((16, 256), dtype=torch.float32, device=q.device)
+            t5 = torch.empty((16, 32), dtype=torch.float32, device=q.device)
+        check(load_library().paris_query_info_get(
+            self._h, qp, ctypes.byref(info), ctypes.c_void_p(t8.data_ptr()) if tables else None,
+            ctypes.c_void_p(t5.data_ptr()) if tables else None, _stream_ptr(stream)), "paris_query_info_get")
+        d = {"paa": list(info.paa), "sym": list(info.sym), "root": int(info.root), "k64": int(info.k64),
+             "win_lo": int(info.win_lo), "win_hi": int(info.win_hi)}
+        if tables:
+            d["table"], d["coarse"] = t8, t5
+        return d
+
+    def lb_scan(self, q, threshold_sq: float, capacity: int | None = None, stream=None):
+        """(indices int32 [k], bounds float32 [k]) of every series whose bound is <= threshold."""
+        torch = _torch()
+        qp = _dev_ptr(q, torch.float32, 1, "query")
+        cap = self.n_series if capacity is None else int(capacity)
+        I = torch.empty(max(cap, 1), dtype=torch.int32, device=q.device)
+        B = torch.empty(max(cap, 1), dtype=torch.float32, device=q.device)
+        cnt = ctypes.c_int64(0)
+        st = load_library().paris_lb_scan(self._h, qp, ctypes.c_float(threshold_sq),
+                                          ctypes.c_void_p(I.data_ptr()), ctypes.c_void_p(B.data_ptr()),
+                                          cap, ctypes.byref(cnt), _stream_ptr(stream))
+        if st not in (PARIS_OK, -5):
+            check(st, "paris_lb_scan")
+        k = min(int(cnt.value), cap)
+        return I[:k], B[:k], int(cnt.value), st
+
+    def set_timing(self, enable: bool = True) -> None:
+        """Enable per-phase HIP-event timing of query() (and zero the totals)."""
+        check(load_library().paris_set_timing(self._h, 1 if enable else 0), "paris_set_timing")
+
+    def timing(self):
+        """(summed ms per phase [prepare, seed, lbscan, refine, resolve], timed queries)."""
+        ms = (ctypes.c_double * 5)()
+        n = ctypes.c_int64(0)
+        check(load_library().paris_get_timing(self._h, ms, ctypes.byref(n)), "paris_get_timing")
+        return list(ms), int(n.value)
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load_library().paris_free(self._h)
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def build(series, cfg: ParisConfig | None = None, stream=None, **cfg_kw) -> Index:
+    """Summarise a float32 [N, n] device tensor and build its index (synchronous)."""
+    if cfg is None:
+        cfg = default_config(**cfg_kw)
+    return Index(series, cfg, stream)

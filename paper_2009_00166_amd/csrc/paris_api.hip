@@ -1,0 +1,476 @@
+// Host side of the C ABI declared in include/paris.h: argument checks, workspace planning,
+// kernel sequencing and read-back. No exception or abort crosses the boundary.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <mutex>
+#include <new>
+#include <unordered_set>
+
+#include "paris.h"
+#include "paris_internal.h"
+
+using namespace paris;
+
+namespace {
+
+constexpr uint32_t kMagic = 0x50415249u;  // "PARI"
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
+
+// Workspace layout. The radix-sort scratch (alternate keys / positions / histograms) is only
+// needed during the build and aliases the survivor and completed-candidate buffers.
+struct Plan {
+    size_t hdr, sax, keys, perm, roff, qs, t8, t5, surv, done, total;
+    size_t keys_alt, perm_alt, hist;
+};
+
+bool make_plan(long long N, int n, Plan* p)
+{
+    (void)n;
+    size_t off = 0;
+    auto take = [&off](size_t bytes) { const size_t at = off; off = align_up(off + bytes); return at; };
+    p->hdr = take(256);
+    p->sax = take((size_t)N * 16);
+    p->keys = take((size_t)N * 8);
+    p->perm = take((size_t)N * 4);
+    p->roff = take(65537 * 4);
+    p->qs = take(sizeof(QState));
+    p->t8 = take(kSeg * kSym * 4);
+    p->t5 = take(kSeg * kCoarse * 4);
+    p->surv = take((size_t)N * 8);
+    p->done = take((size_t)N * 8);
+    p->total = off;
+    p->keys_alt = p->surv;  // 8N bytes
+    p->perm_alt = p->done;  // 4N bytes
+    p->hist = align_up(p->done + (size_t)N * 4);
+    if (p->hist + sort_hist_words(N) * 4 > p->total) {
+        // histogram does not fit behind the alternate positions: give it its own space
+        p->hist = p->total;
+        p->total = align_up(p->total + sort_hist_words(N) * 4);
+    }
+    return true;
+}
+
+bool config_ok(const paris_config* c)
+{
+    if (!c) return false;
+    if (c->segments != 16 || c->card_bits != 8) return false;
+    if (c->leaf_mode != PARIS_LEAF_ROOT16 && c->leaf_mode != PARIS_LEAF_EQUAL_COUNT) return false;
+    if (c->leaf_mode == PARIS_LEAF_EQUAL_COUNT && (c->n_leaves < 1 || c->n_leaves > 65536)) return false;
+    if (c->seed_cap < 0) return false;
+    return true;
+}
+
+bool shape_ok(long long N, int n)
+{
+    return N >= 1 && N <= 0xFFFFFFFELL && n >= 16 && n % 16 == 0 && n <= kMaxLength;
+}
+
+double gamma_k(int k)
+{
+    const double u = std::ldexp(1.0, -24);
+    return k * u / (1.0 - k * u);
+}
+
+// prune_rel: a series is dropped (bound or partial distance above bsf * (1 + prune_rel)) only
+// when its exact distance provably exceeds the exact nearest distance: covers the float32 error
+// of the best-so-far (gamma_{n+2}), of a partial distance (gamma_n) and of the 16-term bound sum
+// (gamma_16), twice over, plus slack for the rounded PAA of the bound.
+// band_rel: the exact nearest neighbour's float32 distance is within (1 + gamma)/(1 - gamma) of
+// the final float32 best, so everything within 4 gamma_{n+2} is re-scored in float64.
+Margins margins_for_length(int n)
+{
+    Margins m;
+    m.prune_rel = 2.0 * (gamma_k(n + 2) + gamma_k(n) + gamma_k(16)) + std::ldexp(1.0, -30);
+    m.band_rel = 4.0 * gamma_k(n + 2) + std::ldexp(1.0, -30);
+    return m;
+}
+
+paris_status device_ok()
+{
+    int count = 0;
+    if (hipGetDeviceCount(&count) != hipSuccess || count <= 0) return PARIS_ENODEV;
+    return PARIS_OK;
+}
+
+}  // namespace
+
+struct paris_index {
+    uint32_t magic;
+    int device;
+    const float* X;
+    long long N;
+    int n;
+    paris_config cfg;
+    uint8_t* ws;
+    size_t ws_bytes;
+    Plan plan;
+    QState* host_qs;   // pinned read-back buffer
+    Margins mg;
+    bool timing;
+    hipEvent_t ev[6];
+    double phase_ms[5];
+    long long timed_queries;
+};
+
+namespace {
+
+QueryArgs args_for(const paris_index* h)
+{
+    QueryArgs a;
+    uint8_t* ws = h->ws;
+    a.X = h->X;
+    a.N = h->N;
+    a.n = h->n;
+    a.sax = ws + h->plan.sax;
+    a.keys = reinterpret_cast<const unsigned long long*>(ws + h->plan.keys);
+    a.perm = reinterpret_cast<const uint32_t*>(ws + h->plan.perm);
+    a.roff = reinterpret_cast<const uint32_t*>(ws + h->plan.roff);
+    a.leaf_mode = h->cfg.leaf_mode;
+    a.n_leaves = h->cfg.n_leaves;
+    a.seed_cap = h->cfg.seed_cap;
+    a.qs = reinterpret_cast<QState*>(ws + h->plan.qs);
+    a.t8 = reinterpret_cast<float*>(ws + h->plan.t8);
+    a.t5 = reinterpret_cast<float*>(ws + h->plan.t5);
+    a.surv = reinterpret_cast<uint2*>(ws + h->plan.surv);
+    a.surv_cap = (uint32_t)h->N;
+    a.done = reinterpret_cast<uint2*>(ws + h->plan.done);
+    a.done_cap = (uint32_t)h->N;
+    a.mg = h->mg;
+    return a;
+}
+
+// Live handles: a freed or foreign pointer is rejected without being dereferenced.
+std::mutex g_live_mu;
+std::unordered_set<const paris_index*> g_live;
+
+bool handle_ok(const paris_index* h)
+{
+    if (!h) return false;
+    std::lock_guard<std::mutex> g(g_live_mu);
+    return g_live.count(h) != 0 && h->magic == kMagic;
+}
+
+#define HIP_TRY(expr)                                  \
+    do {                                               \
+        if ((expr) != hipSuccess) return PARIS_EHIP;   \
+    } while (0)
+
+paris_status run_query(paris_index* h, const float* q, hipStream_t st, long long* out_idx,
+                       double* out_dist, long long qi, bool timed)
+{
+    const QueryArgs a = args_for(h);
+    if (timed) HIP_TRY(hipEventRecord(h->ev[0], st));
+    HIP_TRY(launch_prepare(a, q, st));
+    if (timed) HIP_TRY(hipEventRecord(h->ev[1], st));
+    HIP_TRY(launch_seed(a, q, st));
+    if (timed) HIP_TRY(hipEventRecord(h->ev[2], st));
+    HIP_TRY(launch_lbscan(a, -1.f, st));
+    if (timed) HIP_TRY(hipEventRecord(h->ev[3], st));
+    HIP_TRY(launch_refine(a, q, st));
+    if (timed) HIP_TRY(hipEventRecord(h->ev[4], st));
+    HIP_TRY(launch_resolve(a, q, out_idx, out_dist, qi, st));
+    if (timed) HIP_TRY(hipEventRecord(h->ev[5], st));
+    return PARIS_OK;
+}
+
+// after the stream has been synchronised: add the five phase durations to the totals
+paris_status collect_timing(paris_index* h)
+{
+    for (int k = 0; k < 5; ++k) {
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, h->ev[k], h->ev[k + 1]));
+        h->phase_ms[k] += ms;
+    }
+    h->timed_queries += 1;
+    return PARIS_OK;
+}
+
+void fill_stats(const QState& s, paris_stats* o)
+{
+    o->lb_survivors = s.n_surv;
+    o->refined = s.n_refined;
+    o->abandoned = s.n_abandon;
+    o->bsf_updates = s.n_bsf_upd;
+    o->resolved = s.n_resolved;
+    if (s.seed_key == kBsfInit) {
+        o->seed_index = -1;
+        o->seed_dist = INFINITY;
+    } else {
+        uint32_t bits = (uint32_t)(s.seed_key >> 32);
+        float d2;
+        std::memcpy(&d2, &bits, 4);
+        o->seed_index = (int64_t)(uint32_t)(s.seed_key & 0xFFFFFFFFu);
+        o->seed_dist = std::sqrt((double)d2);
+    }
+    o->seed_lo = s.win_lo;
+    o->seed_hi = s.win_hi;
+}
+
+}  // namespace
+
+extern "C" {
+
+paris_status paris_default_config(paris_config* cfg)
+{
+    if (!cfg) return PARIS_EINVAL;
+    std::memset(cfg, 0, sizeof(*cfg));
+    cfg->segments = 16;
+    cfg->card_bits = 8;
+    cfg->leaf_mode = PARIS_LEAF_ROOT16;
+    cfg->n_leaves = 4096;
+    cfg->seed_cap = 2048;
+    return PARIS_OK;
+}
+
+paris_status paris_workspace_size(int64_t n_series, int32_t length, const paris_config* cfg, size_t* bytes)
+{
+    if (!bytes || !config_ok(cfg) || !shape_ok(n_series, length)) return PARIS_EINVAL;
+    Plan p;
+    make_plan(n_series, length, &p);
+    *bytes = p.total;
+    return PARIS_OK;
+}
+
+paris_status paris_build(const float* series_dev, int64_t n_series, int32_t length, const paris_config* cfg,
+                         void* workspace_dev, size_t workspace_bytes, void* hip_stream, paris_index** out)
+{
+    if (!out || !series_dev || !workspace_dev || !config_ok(cfg) || !shape_ok(n_series, length))
+        return PARIS_EINVAL;
+    if (reinterpret_cast<uintptr_t>(series_dev) % 16 != 0 ||
+        reinterpret_cast<uintptr_t>(workspace_dev) % kAlign != 0)
+        return PARIS_EINVAL;
+    Plan plan;
+    make_plan(n_series, length, &plan);
+    if (workspace_bytes < plan.total) return PARIS_ENOMEM;
+    paris_status ds = device_ok();
+    if (ds != PARIS_OK) return ds;
+
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    uint8_t* ws = static_cast<uint8_t*>(workspace_dev);
+    uint32_t* err = reinterpret_cast<uint32_t*>(ws + plan.hdr);
+    auto* keys = reinterpret_cast<unsigned long long*>(ws + plan.keys);
+    auto* perm = reinterpret_cast<uint32_t*>(ws + plan.perm);
+    HIP_TRY(hipMemsetAsync(err, 0, 256, st));
+    HIP_TRY(launch_summarise(series_dev, n_series, length, ws + plan.sax, keys, perm, err, st));
+    HIP_TRY(launch_sort_keys(keys, perm, reinterpret_cast<unsigned long long*>(ws + plan.keys_alt),
+                             reinterpret_cast<uint32_t*>(ws + plan.perm_alt),
+                             reinterpret_cast<uint32_t*>(ws + plan.hist), n_series, st));
+    HIP_TRY(launch_root_offsets(keys, n_series, reinterpret_cast<uint32_t*>(ws + plan.roff), st));
+    uint32_t herr = 0;
+    HIP_TRY(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (herr & kErrNonFinite) return PARIS_EINVAL;
+
+    paris_index* h = new (std::nothrow) paris_index();
+    if (!h) return PARIS_ENOMEM;
+    h->magic = kMagic;
+    if (hipGetDevice(&h->device) != hipSuccess) h->device = 0;
+    h->X = series_dev;
+    h->N = n_series;
+    h->n = length;
+    h->cfg = *cfg;
+    h->ws = ws;
+    h->ws_bytes = workspace_bytes;
+    h->plan = plan;
+    h->mg = margins_for_length(length);
+    h->timing = false;
+    for (int k = 0; k < 6; ++k) h->ev[k] = nullptr;
+    for (int k = 0; k < 5; ++k) h->phase_ms[k] = 0.0;
+    h->timed_queries = 0;
+    if (hipHostMalloc(reinterpret_cast<void**>(&h->host_qs), sizeof(QState), hipHostMallocDefault) != hipSuccess) {
+        h->magic = 0;
+        delete h;
+        return PARIS_EHIP;
+    }
+    {
+        std::lock_guard<std::mutex> g(g_live_mu);
+        g_live.insert(h);
+    }
+    *out = h;
+    return PARIS_OK;
+}
+
+paris_status paris_get_layout(const paris_index* h, paris_layout* o)
+{
+    if (!handle_ok(h)) return PARIS_ESTATE;
+    if (!o) return PARIS_EINVAL;
+    o->sax_dev = h->ws + h->plan.sax;
+    o->keys_dev = reinterpret_cast<const uint64_t*>(h->ws + h->plan.keys);
+    o->perm_dev = reinterpret_cast<const uint32_t*>(h->ws + h->plan.perm);
+    o->roff_dev = reinterpret_cast<const uint32_t*>(h->ws + h->plan.roff);
+    o->n_series = h->N;
+    o->length = h->n;
+    o->leaf_mode = h->cfg.leaf_mode;
+    o->n_leaves = h->cfg.n_leaves;
+    o->seed_cap = h->cfg.seed_cap;
+    return PARIS_OK;
+}
+
+paris_status paris_query_exact(paris_index* h, const float* query_dev, int64_t* nn_index, double* nn_dist,
+                               paris_stats* stats, void* hip_stream)
+{
+    if (!handle_ok(h)) return PARIS_ESTATE;
+    if (!query_dev || !nn_index || !nn_dist || reinterpret_cast<uintptr_t>(query_dev) % 16 != 0)
+        return PARIS_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    paris_status s = run_query(h, query_dev, st, nullptr, nullptr, 0, h->timing);
+    if (s != PARIS_OK) return s;
+    HIP_TRY(hipMemcpyAsync(h->host_qs, h->ws + h->plan.qs, sizeof(QState), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (h->timing) {
+        s = collect_timing(h);
+        if (s != PARIS_OK) return s;
+    }
+    const QState& q = *h->host_qs;
+    if (q.err & kErrNonFinite) return PARIS_EINVAL;
+    if (q.err & (kErrSurvOverflow | kErrDoneOverflow)) return PARIS_EOVERFLOW;
+    if (q.res_idx < 0) return PARIS_EINVAL;
+    *nn_index = q.res_idx;
+    *nn_dist = std::sqrt(q.res_d2);
+    if (stats) fill_stats(q, stats);
+    return PARIS_OK;
+}
+
+paris_status paris_query_batch(paris_index* h, const float* queries_dev, int64_t n_queries, int64_t* nn_index_dev,
+                               double* nn_dist_dev, paris_stats* stats, void* hip_stream)
+{
+    if (!handle_ok(h)) return PARIS_ESTATE;
+    if (!queries_dev || !nn_index_dev || !nn_dist_dev || n_queries < 0 ||
+        reinterpret_cast<uintptr_t>(queries_dev) % 16 != 0)
+        return PARIS_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    paris_stats agg;
+    std::memset(&agg, 0, sizeof(agg));
+    for (long long i = 0; i < n_queries; ++i) {
+        const float* q = queries_dev + i * (long long)h->n;
+        paris_status s = run_query(h, q, st, reinterpret_cast<long long*>(nn_index_dev), nn_dist_dev, i, false);
+        if (s != PARIS_OK) return s;
+        if (stats) {
+            HIP_TRY(hipMemcpyAsync(h->host_qs, h->ws + h->plan.qs, sizeof(QState), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            paris_stats one;
+            fill_stats(*h->host_qs, &one);
+            agg.lb_survivors += one.lb_survivors;
+            agg.refined += one.refined;
+            agg.abandoned += one.abandoned;
+            agg.bsf_updates += one.bsf_updates;
+            agg.resolved += one.resolved;
+        }
+    }
+    if (stats) {
+        agg.seed_index = -1;
+        agg.seed_dist = INFINITY;
+        *stats = agg;
+    }
+    return PARIS_OK;
+}
+
+paris_status paris_query_info_get(paris_index* h, const float* query_dev, paris_query_info* info, float* table_dev,
+                                  float* coarse_dev, void* hip_stream)
+{
+    if (!handle_ok(h)) return PARIS_ESTATE;
+    if (!query_dev || reinterpret_cast<uintptr_t>(query_dev) % 16 != 0) return PARIS_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    const QueryArgs a = args_for(h);
+    HIP_TRY(launch_prepare(a, query_dev, st));
+    if (table_dev) HIP_TRY(hipMemcpyAsync(table_dev, a.t8, kSeg * kSym * 4, hipMemcpyDeviceToDevice, st));
+    if (coarse_dev) HIP_TRY(hipMemcpyAsync(coarse_dev, a.t5, kSeg * kCoarse * 4, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(h->host_qs, a.qs, sizeof(QState), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const QState& q = *h->host_qs;
+    if (info) {
+        for (int s = 0; s < 16; ++s) { info->paa[s] = q.paa[s]; info->sym[s] = q.sym[s]; }
+        info->root = q.root;
+        info->pad = 0;
+        info->k64 = q.k64;
+        info->win_lo = q.win_lo;
+        info->win_hi = q.win_hi;
+    }
+    if (q.err & kErrNonFinite) return PARIS_EINVAL;
+    return PARIS_OK;
+}
+
+paris_status paris_lb_scan(paris_index* h, const float* query_dev, float threshold_sq, uint32_t* idx_dev,
+                           float* lb_dev, int64_t capacity, int64_t* count, void* hip_stream)
+{
+    if (!handle_ok(h)) return PARIS_ESTATE;
+    if (!query_dev || !count || capacity < 0 || (capacity > 0 && (!idx_dev || !lb_dev)) ||
+        !(threshold_sq >= 0.f) || reinterpret_cast<uintptr_t>(query_dev) % 16 != 0)
+        return PARIS_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    QueryArgs a = args_for(h);
+    HIP_TRY(launch_prepare(a, query_dev, st));
+    HIP_TRY(launch_lbscan(a, threshold_sq, st));
+    HIP_TRY(hipMemcpyAsync(h->host_qs, a.qs, sizeof(QState), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const QState& q = *h->host_qs;
+    if (q.err & kErrNonFinite) return PARIS_EINVAL;
+    const long long n = q.n_surv;
+    *count = n;
+    const long long k = n < capacity ? n : capacity;
+    if (k > 0) {
+        // survivors are (index, bound) pairs in the survivor buffer; split them for the caller
+        HIP_TRY(hipMemcpy2DAsync(idx_dev, 4, a.surv, 8, 4, (size_t)k, hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipMemcpy2DAsync(lb_dev, 4, reinterpret_cast<uint8_t*>(a.surv) + 4, 8, 4, (size_t)k,
+                                 hipMemcpyDeviceToDevice, st));
+        HIP_TRY(hipStreamSynchronize(st));
+    }
+    return n > capacity ? PARIS_EOVERFLOW : PARIS_OK;
+}
+
+paris_status paris_set_timing(paris_index* h, int32_t enable)
+{
+    if (!handle_ok(h)) return PARIS_ESTATE;
+    if (enable && !h->ev[0]) {
+        for (int k = 0; k < 6; ++k) HIP_TRY(hipEventCreate(&h->ev[k]));
+    }
+    h->timing = enable != 0;
+    for (int k = 0; k < 5; ++k) h->phase_ms[k] = 0.0;
+    h->timed_queries = 0;
+    return PARIS_OK;
+}
+
+paris_status paris_get_timing(const paris_index* h, double* ms_out5, int64_t* n_queries)
+{
+    if (!handle_ok(h)) return PARIS_ESTATE;
+    if (!ms_out5 || !n_queries) return PARIS_EINVAL;
+    for (int k = 0; k < 5; ++k) ms_out5[k] = h->phase_ms[k];
+    *n_queries = h->timed_queries;
+    return PARIS_OK;
+}
+
+paris_status paris_free(paris_index* h)
+{
+    if (!h) return PARIS_OK;
+    {
+        std::lock_guard<std::mutex> g(g_live_mu);
+        if (g_live.erase(h) == 0) return PARIS_ESTATE;
+    }
+    h->magic = 0;
+    if (h->host_qs) (void)hipHostFree(h->host_qs);
+    for (int k = 0; k < 6; ++k)
+        if (h->ev[k]) (void)hipEventDestroy(h->ev[k]);
+    delete h;
+    return PARIS_OK;
+}
+
+const char* paris_status_string(paris_status s)
+{
+    switch (s) {
+    case PARIS_OK: return "ok";
+    case PARIS_EINVAL: return "invalid argument or non-finite value";
+    case PARIS_ENOMEM: return "workspace too small";
+    case PARIS_ENODEV: return "no HIP device";
+    case PARIS_EHIP: return "HIP runtime error";
+    case PARIS_EOVERFLOW: return "device buffer overflow";
+    case PARIS_ESTATE: return "invalid handle";
+    }
+    return "unknown status";
+}
+
+}  // extern "C"

@@ -1,0 +1,89 @@
+// Internal declarations shared by the kernel and host translation units of libparis.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace paris {
+
+constexpr int kSeg = 16;           // w, segments per iSAX word
+constexpr int kSym = 256;          // 8-bit symbols
+constexpr int kCoarse = 32;        // 5-bit prefix alphabet of the coarse lower-bound table
+constexpr int kMaxLength = 2048;   // longest series the summarise kernel stages in LDS
+
+// Best-so-far key: float32 bits of the squared distance (non-negative, so the bit pattern
+// orders like the value) in the high word, series index in the low word. atomicMin on it keeps
+// the smallest distance and, among equal float32 distances, the lowest index.
+constexpr unsigned long long kBsfInit = (0x7F800000ull << 32) | 0xFFFFFFFFull;  // (+inf, max)
+
+enum ErrBits : uint32_t {
+    kErrNonFinite = 1u,      // NaN or Inf in the data or the query
+    kErrSurvOverflow = 2u,   // more LB survivors than capacity
+    kErrDoneOverflow = 4u,   // more completed candidates than capacity
+};
+
+// Per-query device state. Written by the prepare kernel, updated by the search kernels, read
+// back by the host after the resolve kernel.
+struct alignas(256) QState {
+    double paa[kSeg];
+    uint8_t sym[kSeg];
+    uint32_t root;
+    uint32_t pad0;
+    unsigned long long k64;
+    long long win_lo, win_hi;
+    unsigned long long bsf_key;
+    unsigned long long seed_key;
+    uint32_t n_surv, n_refined, n_abandon, n_bsf_upd, n_done, n_resolved;
+    uint32_t err;
+    uint32_t pad1;
+    long long res_idx;
+    double res_d2;
+};
+
+// Pruning margins, derived on the host from the series length (see margins_for_length).
+struct Margins {
+    double prune_rel;   // prune / abandon only when value > bsf * (1 + prune_rel)
+    double band_rel;    // float64 resolve of every candidate with d32 <= best32 * (1 + band_rel)
+};
+
+// ---- build kernels ----
+hipError_t launch_summarise(const float* X, long long N, int n, uint8_t* sax, unsigned long long* keys,
+                            uint32_t* perm, uint32_t* err, hipStream_t st);
+size_t sort_hist_words(long long N);
+hipError_t launch_sort_keys(unsigned long long* keys, uint32_t* perm, unsigned long long* keys_alt,
+                            uint32_t* perm_alt, uint32_t* hist, long long N, hipStream_t st);
+hipError_t launch_root_offsets(const unsigned long long* keys, long long N, uint32_t* roff,
+                               hipStream_t st);
+
+// ---- query kernels ----
+struct QueryArgs {
+    const float* X;
+    long long N;
+    int n;
+    const uint8_t* sax;
+    const unsigned long long* keys;
+    const uint32_t* perm;
+    const uint32_t* roff;
+    int leaf_mode, n_leaves, seed_cap;
+    QState* qs;
+    float* t8;        // [16][256]
+    float* t5;        // [16][32]
+    uint2* surv;      // (index, lb2 bits)
+    uint32_t surv_cap;
+    uint2* done;      // (index, d2 fp32 bits)
+    uint32_t done_cap;
+    Margins mg;
+};
+
+hipError_t launch_prepare(const QueryArgs& a, const float* q, hipStream_t st);
+hipError_t launch_seed(const QueryArgs& a, const float* q, hipStream_t st);
+// threshold_sq < 0: use the best-so-far in QState; otherwise a fixed threshold.
+hipError_t launch_lbscan(const QueryArgs& a, float threshold_sq, hipStream_t st);
+hipError_t launch_refine(const QueryArgs& a, const float* q, hipStream_t st);
+// out_idx / out_dist may be null; otherwise element qi receives the answer.
+hipError_t launch_resolve(const QueryArgs& a, const float* q, long long* out_idx, double* out_dist,
+                          long long qi, hipStream_t st);
+
+}  // namespace paris

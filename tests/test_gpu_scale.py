@@ -1,0 +1,76 @@
+"""GPU parity at the full collection size the benchmark times (10,000,000 x 256, launch
+configuration of the plain query path): sampled iSAX words, order properties of the whole leaf
+order, and exact answers for a sample of queries checked by the brute-force C oracle."""
+import math
+import time
+
+import numpy as np
+import pytest
+
+import synth
+
+torch = pytest.importorskip("torch")
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+N_FULL, LEN = 10_000_000, 256
+
+
+@pytest.fixture(scope="module")
+def full(oracle_native):
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2009_00166_amd as paris
+    t0 = time.time()
+    X = synth.random_walks(N_FULL, LEN, seed=0, threads=16)
+    print(f"[scale] generated {N_FULL}x{LEN} in {time.time() - t0:.1f}s", flush=True)
+    Xd = torch.from_numpy(X).cuda()
+    index = paris.build(Xd)
+    torch.cuda.synchronize()
+    print(f"[scale] built index at {time.time() - t0:.1f}s", flush=True)
+    yield dict(X=X, Xd=Xd, index=index)
+    index.close()
+
+
+def test_sampled_words_and_order(full, oracle_native):
+    X, index = full["X"], full["index"]
+    rng = np.random.default_rng(0)
+    rows = np.sort(rng.choice(N_FULL, 200_000, replace=False))
+    _, sym = oracle_native.summarise(X[rows])
+    sax = index.sax()
+    got = sax[torch.from_numpy(rows).cuda()].cpu().numpy()
+    assert np.array_equal(got, sym)
+    keys = index.sorted_keys()
+    ku = keys.cpu().numpy().view(np.uint64)
+    assert np.all(ku[1:] >= ku[:-1])
+    perm = index.sorted_positions().cpu().numpy().astype(np.int64)
+    assert np.array_equal(np.sort(perm), np.arange(N_FULL))
+    same = ku[1:] == ku[:-1]
+    assert np.all(perm[1:][same] > perm[:-1][same])          # stable: ties keep position order
+    from oracle import k64
+    sample = rng.choice(N_FULL, 50_000, replace=False)
+    _, s2 = oracle_native.summarise(X[perm[sample]])
+    assert np.array_equal(k64(s2), ku[sample])
+    roff = index.root_offsets().cpu().numpy().astype(np.int64)
+    assert roff[0] == 0 and roff[-1] == N_FULL and np.all(np.diff(roff) >= 0)
+    r = (ku >> np.uint64(48)).astype(np.int64)
+    assert np.array_equal(np.bincount(r, minlength=65536), np.diff(roff))
+
+
+def test_sampled_exact_answers(full, oracle_native):
+    X, index = full["X"], full["index"]
+    Q1, _, _ = synth.noisy_queries(X, 12, seed=0, sigma=0.1)
+    Q2, _, _ = synth.noisy_queries(X, 4, seed=1, sigma=(0.01, 0.5))
+    Q = np.concatenate([Q1, Q2])
+    t0 = time.time()
+    ri, rd, used = oracle_native.nn_many(Q, X, threads=16)
+    print(f"[scale] oracle brute force {Q.shape[0]} queries in {time.time() - t0:.1f}s on {used} threads",
+          flush=True)
+    Qd = torch.from_numpy(Q).cuda()
+    for m in range(Q.shape[0]):
+        i, d = index.query(Qd[m])
+        ref = math.sqrt(rd[m])
+        assert i == int(ri[m]), (m, i, int(ri[m]))
+        assert abs(d - ref) <= 1e-5 * ref
+    I, D = index.query_batch(Qd)
+    torch.cuda.synchronize()
+    assert np.array_equal(I.cpu().numpy(), ri)
