@@ -56,9 +56,12 @@ typedef struct paris_config {
                            first bits of the 16 symbols (Section 3, pipeline overview).
                            PARIS_LEAF_EQUAL_COUNT: n_leaves equal slices of the key order.    */
     int32_t n_leaves;   /* EQUAL_COUNT only: 1 .. 65536 (default 4096)                          */
-    int32_t seed_cap;   /* ROOT16 only: at most this many members of the query's subtree are
-                           scanned by the approximate search (default 2048). 0 disables the
-                           seed: the best-so-far starts at +inf (the answer is unchanged).     */
+    int32_t seed_cap;   /* ROOT16 only: the approximate search examines at most this many
+                           members of the query's subtree (default 16384), consecutive in key
+                           order and centred on the query's key; in every 512 of them the one
+                           with the smallest lower bound gets its real distance computed, and
+                           the smallest of those is the first best-so-far. 0 disables the seed:
+                           the best-so-far starts at +inf (the answer is unchanged).           */
     int32_t reserved[3];
 } paris_config;
 
@@ -71,7 +74,7 @@ typedef struct paris_stats {
     int64_t resolved;      /* candidates re-scored in float64 for the final comparison       */
     int64_t seed_index;    /* series found by the approximate search (-1 if none)            */
     double  seed_dist;     /* its float32-computed distance (+inf if none)                   */
-    int64_t seed_lo, seed_hi;  /* sorted-position window scanned by the approximate search   */
+    int64_t seed_lo, seed_hi;  /* sorted-position window examined by the approximate search  */
 } paris_stats;
 
 typedef struct paris_index paris_index;  /* opaque, library-owned host handle */
@@ -85,6 +88,8 @@ typedef struct paris_layout {
     int64_t n_series;
     int32_t length;
     int32_t leaf_mode, n_leaves, seed_cap;
+    int32_t scan_threads, scan_blocks_per_cu, scan_unroll;  /* lower-bound scan launch shape
+                                                               picked at build                */
 } paris_layout;
 
 /* Query summaries as computed on the device (inspection and tests). */
@@ -97,7 +102,7 @@ typedef struct paris_query_info {
     int64_t  win_lo, win_hi;  /* approximate-search window (sorted positions)                */
 } paris_query_info;
 
-/* Fills *cfg with the defaults (16 segments, 8 bits, ROOT16, 4096 leaves, seed_cap 2048). */
+/* Fills *cfg with the defaults (16 segments, 8 bits, ROOT16, 4096 leaves, seed_cap 16384). */
 paris_status paris_default_config(paris_config *cfg);
 
 /* Bytes of device workspace paris_build needs for this collection shape (host-only call). */
@@ -113,7 +118,8 @@ paris_status paris_workspace_size(int64_t n_series, int32_t length, const paris_
  *   workspace_dev   at least paris_workspace_size() bytes of device memory, 256-byte aligned,
  *                   BORROWED for the life of the handle; the library owns its contents.
  *   out             receives the handle (library-owned host memory; release with paris_free).
- * Synchronous: returns after the build finished on hip_stream.
+ * Synchronous: returns after the build finished on hip_stream (including a short timing of
+ * candidate launch shapes for the lower-bound scan).
  */
 paris_status paris_build(const float *series_dev, int64_t n_series, int32_t length,
                          const paris_config *cfg, void *workspace_dev, size_t workspace_bytes,
@@ -173,12 +179,13 @@ paris_status paris_lb_scan(paris_index *idx, const float *query_dev, float thres
 
 /*
  * Per-phase device timing of paris_query_exact, with HIP events recorded on the call's stream
- * around each kernel: [0] prepare, [1] approximate-search seed, [2] lower-bound scan,
- * [3] refine, [4] resolve. paris_set_timing(idx, 1) enables it and zeroes the totals;
- * paris_get_timing returns the summed milliseconds and the number of timed queries.
+ * around its three kernels: [0] query summaries + approximate-search seed, [1] lower-bound
+ * scan, [2] refinement + float64 resolve. paris_lb_scan adds its scan time to [1].
+ * paris_set_timing(idx, 1) enables it and zeroes the totals; paris_get_timing returns the
+ * summed milliseconds (ms_out3[3]) and the number of timed calls.
  */
 paris_status paris_set_timing(paris_index *idx, int32_t enable);
-paris_status paris_get_timing(const paris_index *idx, double *ms_out5, int64_t *n_queries);
+paris_status paris_get_timing(const paris_index *idx, double *ms_out3, int64_t *n_queries);
 
 /* Release the handle (the borrowed buffers are not touched). NULL is accepted. */
 paris_status paris_free(paris_index *idx);

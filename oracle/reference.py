@@ -210,7 +210,7 @@ def equal_count_bounds(N: int, n_leaves: int) -> np.ndarray:
 
 
 def seed_window(qs: QuerySummary, keys_sorted: np.ndarray, L: int, mode: str = "root16",
-                seed_cap: int = 2048, n_leaves: int = 4096, off: np.ndarray | None = None):
+                seed_cap: int = 16384, n_leaves: int = 4096, off: np.ndarray | None = None):
     """Sorted-position window [a, b) scanned by the approximate search (Section 3.3, first
     paragraph: descend to the leaf whose iSAX is most similar to the query's and take the
     minimum distance over that leaf's series as the first best-so-far).
@@ -254,6 +254,27 @@ def seed_window(qs: QuerySummary, keys_sorted: np.ndarray, L: int, mode: str = "
     return a, a + seed_cap
 
 
+SEED_CHUNK = 512
+
+
+def seed_candidates(qs: QuerySummary, members: np.ndarray, sym8: np.ndarray, L: int,
+                    chunk: int = SEED_CHUNK) -> np.ndarray:
+    """Members of the approximate-search window whose real distance is computed.
+
+    Reading: the paper computes the distance to every series of the leaf it reaches; leaves
+    here can hold tens of thousands of series, so the window is cut into runs of ``chunk``
+    consecutive sorted positions and in each run only the member with the smallest lower bound
+    (ties: lowest series index) is refined. The minimum real distance over these is the seed.
+    """
+    out = []
+    for a in range(0, len(members), chunk):
+        run = members[a:a + chunk]
+        lb = lower_bound_sq(qs.paa[None, :], sym8[run], L)
+        j = int(np.lexsort((run, lb))[0])
+        out.append(int(run[j]))
+    return np.array(out, dtype=np.int64)
+
+
 # --------------------------------------------------------------------------------------------
 # Exact search twin (Section 3.3.3: ExactSearch, LBC worker, RDC worker), serial
 # --------------------------------------------------------------------------------------------
@@ -269,12 +290,13 @@ class ExactStats:
 
 
 def exact_search(q: np.ndarray, X: np.ndarray, sym8: np.ndarray | None = None,
-                 mode: str = "root16", seed_cap: int = 2048, n_leaves: int = 4096,
+                 mode: str = "root16", seed_cap: int = 16384, n_leaves: int = 4096,
                  use_seed: bool = True):
     """Serial twin of ParIS+ exact search; returns ``(index, squared distance, ExactStats)``.
 
-    1. BSF <- approximate search (``seed_window``; min squared distance over its members, ties
-       to the lowest index), or +inf when ``use_seed`` is False.
+    1. BSF <- approximate search (``seed_window``, then ``seed_candidates``; min squared
+       distance over the candidates, ties to the lowest index), or +inf when ``use_seed`` is
+       False.
     2. LBC step: candidates = {i : LB^2_i <= BSF^2}. The paper keeps i when minDist < BSF;
        reading: prune only on ">", so a series tied with the BSF at a lower index survives.
     3. Candidates are processed in ascending (LB^2, i) (the paper sorts by file position for
@@ -300,8 +322,8 @@ def exact_search(q: np.ndarray, X: np.ndarray, sym8: np.ndarray | None = None,
     if use_seed and N > 0:
         perm, keys_sorted = sorted_order(sym8)
         a, b = seed_window(qs, keys_sorted, L, mode, seed_cap, n_leaves)
-        members = perm[a:b]
-        d2 = ed_sq(qf, X[members])
+        members = seed_candidates(qs, perm[a:b], sym8, L)
+        d2 = ed_sq(qf, X[members]) if len(members) else np.zeros(0)
         for m, d in zip(members, d2):
             if d < bsf or (d == bsf and m < bsf_i):
                 bsf, bsf_i = float(d), int(m)

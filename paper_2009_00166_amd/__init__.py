@@ -183,8 +183,8 @@ class Index:
         check(load_library().paris_set_timing(self._h, 1 if enable else 0), "paris_set_timing")
 
     def timing(self):
-        """(summed ms per phase [prepare, seed, lbscan, refine, resolve], timed queries)."""
-        ms = (ctypes.c_double * 5)()
+        """(summed ms per phase [prepare+seed, lbscan, refine+resolve], timed calls)."""
+        ms = (ctypes.c_double * 3)()
         n = ctypes.c_int64(0)
         check(load_library().paris_get_timing(self._h, ms, ctypes.byref(n)), "paris_get_timing")
         return list(ms), int(n.value)

@@ -35,7 +35,8 @@ class ParisLayout(ctypes.Structure):
                 ("perm_dev", ctypes.c_void_p), ("roff_dev", ctypes.c_void_p),
                 ("n_series", ctypes.c_int64), ("length", ctypes.c_int32),
                 ("leaf_mode", ctypes.c_int32), ("n_leaves", ctypes.c_int32),
-                ("seed_cap", ctypes.c_int32)]
+                ("seed_cap", ctypes.c_int32), ("scan_threads", ctypes.c_int32),
+                ("scan_blocks_per_cu", ctypes.c_int32), ("scan_unroll", ctypes.c_int32)]
 
 
 class ParisQueryInfo(ctypes.Structure):

@@ -1,9 +1,12 @@
 // Host side of the C ABI declared in include/paris.h: argument checks, workspace planning,
-// kernel sequencing and read-back. No exception or abort crosses the boundary.
+// kernel sequencing, launch-shape autotuning and read-back. No exception or abort crosses the
+// boundary.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
 #include <cstdint>
+#include <cstdio>
+#include <cstdlib>
 #include <cstring>
 #include <mutex>
 #include <new>
@@ -28,9 +31,8 @@ struct Plan {
     size_t keys_alt, perm_alt, hist;
 };
 
-bool make_plan(long long N, int n, Plan* p)
+void make_plan(long long N, Plan* p)
 {
-    (void)n;
     size_t off = 0;
     auto take = [&off](size_t bytes) { const size_t at = off; off = align_up(off + bytes); return at; };
     p->hdr = take(256);
@@ -52,7 +54,6 @@ bool make_plan(long long N, int n, Plan* p)
         p->hist = p->total;
         p->total = align_up(p->total + sort_hist_words(N) * 4);
     }
-    return true;
 }
 
 bool config_ok(const paris_config* c)
@@ -61,7 +62,7 @@ bool config_ok(const paris_config* c)
     if (c->segments != 16 || c->card_bits != 8) return false;
     if (c->leaf_mode != PARIS_LEAF_ROOT16 && c->leaf_mode != PARIS_LEAF_EQUAL_COUNT) return false;
     if (c->leaf_mode == PARIS_LEAF_EQUAL_COUNT && (c->n_leaves < 1 || c->n_leaves > 65536)) return false;
-    if (c->seed_cap < 0) return false;
+    if (c->seed_cap < 0 || c->seed_cap > (1 << 24)) return false;
     return true;
 }
 
@@ -110,10 +111,13 @@ struct paris_index {
     size_t ws_bytes;
     Plan plan;
     QState* host_qs;   // pinned read-back buffer
+    QResult* host_res;       // pinned, device-mapped: the query result lands here directly
+    QResult* host_res_dev;   // its device address
     Margins mg;
+    ScanShape scan;
     bool timing;
-    hipEvent_t ev[6];
-    double phase_ms[5];
+    hipEvent_t ev[4];
+    double phase_ms[3];
     long long timed_queries;
 };
 
@@ -141,6 +145,7 @@ QueryArgs args_for(const paris_index* h)
     a.done = reinterpret_cast<uint2*>(ws + h->plan.done);
     a.done_cap = (uint32_t)h->N;
     a.mg = h->mg;
+    a.host_res = nullptr;
     return a;
 }
 
@@ -161,27 +166,24 @@ bool handle_ok(const paris_index* h)
     } while (0)
 
 paris_status run_query(paris_index* h, const float* q, hipStream_t st, long long* out_idx,
-                       double* out_dist, long long qi, bool timed)
+                       double* out_dist, long long qi, bool timed, QResult* host_res = nullptr)
 {
-    const QueryArgs a = args_for(h);
+    QueryArgs a = args_for(h);
+    a.host_res = host_res;
     if (timed) HIP_TRY(hipEventRecord(h->ev[0], st));
-    HIP_TRY(launch_prepare(a, q, st));
+    HIP_TRY(launch_prepare_seed(a, q, st));
     if (timed) HIP_TRY(hipEventRecord(h->ev[1], st));
-    HIP_TRY(launch_seed(a, q, st));
+    HIP_TRY(launch_lbscan(a, -1.f, h->scan, st));
     if (timed) HIP_TRY(hipEventRecord(h->ev[2], st));
-    HIP_TRY(launch_lbscan(a, -1.f, st));
+    HIP_TRY(launch_refine_resolve(a, q, out_idx, out_dist, qi, st));
     if (timed) HIP_TRY(hipEventRecord(h->ev[3], st));
-    HIP_TRY(launch_refine(a, q, st));
-    if (timed) HIP_TRY(hipEventRecord(h->ev[4], st));
-    HIP_TRY(launch_resolve(a, q, out_idx, out_dist, qi, st));
-    if (timed) HIP_TRY(hipEventRecord(h->ev[5], st));
     return PARIS_OK;
 }
 
-// after the stream has been synchronised: add the five phase durations to the totals
+// after the stream has been synchronised: add the three phase durations to the totals
 paris_status collect_timing(paris_index* h)
 {
-    for (int k = 0; k < 5; ++k) {
+    for (int k = 0; k < 3; ++k) {
         float ms = 0.f;
         HIP_TRY(hipEventElapsedTime(&ms, h->ev[k], h->ev[k + 1]));
         h->phase_ms[k] += ms;
@@ -190,25 +192,73 @@ paris_status collect_timing(paris_index* h)
     return PARIS_OK;
 }
 
-void fill_stats(const QState& s, paris_stats* o)
+void fill_stats(const QResult& r, paris_stats* o)
 {
-    o->lb_survivors = s.n_surv;
-    o->refined = s.n_refined;
-    o->abandoned = s.n_abandon;
-    o->bsf_updates = s.n_bsf_upd;
-    o->resolved = s.n_resolved;
-    if (s.seed_key == kBsfInit) {
+    o->lb_survivors = r.n_surv;
+    o->refined = r.n_refined;
+    o->abandoned = r.n_abandon;
+    o->bsf_updates = r.n_bsf_upd;
+    o->resolved = r.n_resolved;
+    if (r.seed_key == kBsfInit) {
         o->seed_index = -1;
         o->seed_dist = INFINITY;
     } else {
-        uint32_t bits = (uint32_t)(s.seed_key >> 32);
+        uint32_t bits = (uint32_t)(r.seed_key >> 32);
         float d2;
         std::memcpy(&d2, &bits, 4);
-        o->seed_index = (int64_t)(uint32_t)(s.seed_key & 0xFFFFFFFFu);
+        o->seed_index = (int64_t)(uint32_t)(r.seed_key & 0xFFFFFFFFu);
         o->seed_dist = std::sqrt((double)d2);
     }
-    o->seed_lo = s.win_lo;
-    o->seed_hi = s.win_hi;
+    o->seed_lo = r.win_lo;
+    o->seed_hi = r.win_hi;
+}
+
+// Launch-shape autotuner for the lower-bound scan: every candidate shape scans the whole SAX
+// array at a zero threshold (the series' own word as the query: nothing but that row survives),
+// timed with HIP events; the fastest median wins. PARIS_SCAN_SHAPE="threads,blocks_per_cu"
+// overrides the choice.
+paris_status tune_scan(paris_index* h, hipStream_t st)
+{
+    const char* env = std::getenv("PARIS_SCAN_SHAPE");
+    if (env) {
+        int t = 0, b = 0, u = 4;
+        const int got = std::sscanf(env, "%d,%d,%d", &t, &b, &u);
+        if (got >= 2 && (t == 256 || t == 512) && b >= 1 && b <= 32 && (u == 2 || u == 4 || u == 8)) {
+            h->scan = ScanShape{t, b, u};
+            return PARIS_OK;
+        }
+    }
+    const ScanShape cands[] = {{256, 4, 4}, {256, 8, 4}, {512, 2, 4}, {512, 4, 4}, {256, 4, 8},
+                               {512, 2, 8}, {256, 8, 2}, {512, 4, 2}};
+    const QueryArgs a = args_for(h);
+    HIP_TRY(launch_prepare_seed(a, h->X, st));  // tables of series 0
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best = 1e30f;
+    ScanShape pick = cands[3];
+    for (const ScanShape& s : cands) {
+        float t[3];
+        for (int r = 0; r < 4; ++r) {
+            HIP_TRY(hipEventRecord(e0, st));
+            HIP_TRY(launch_lbscan(a, 0.f, s, st));
+            HIP_TRY(hipEventRecord(e1, st));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (r > 0) t[r - 1] = ms;  // first run warms up
+        }
+        const float lo = std::fmin(t[0], std::fmin(t[1], t[2]));
+        const float hi = std::fmax(t[0], std::fmax(t[1], t[2]));
+        const float med = t[0] + t[1] + t[2] - lo - hi;
+        if (med < best) { best = med; pick = s; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->scan = pick;
+    HIP_TRY(launch_reset(a, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return PARIS_OK;
 }
 
 }  // namespace
@@ -223,7 +273,7 @@ paris_status paris_default_config(paris_config* cfg)
     cfg->card_bits = 8;
     cfg->leaf_mode = PARIS_LEAF_ROOT16;
     cfg->n_leaves = 4096;
-    cfg->seed_cap = 2048;
+    cfg->seed_cap = 16384;
     return PARIS_OK;
 }
 
@@ -231,7 +281,7 @@ paris_status paris_workspace_size(int64_t n_series, int32_t length, const paris_
 {
     if (!bytes || !config_ok(cfg) || !shape_ok(n_series, length)) return PARIS_EINVAL;
     Plan p;
-    make_plan(n_series, length, &p);
+    make_plan(n_series, &p);
     *bytes = p.total;
     return PARIS_OK;
 }
@@ -245,7 +295,7 @@ paris_status paris_build(const float* series_dev, int64_t n_series, int32_t leng
         reinterpret_cast<uintptr_t>(workspace_dev) % kAlign != 0)
         return PARIS_EINVAL;
     Plan plan;
-    make_plan(n_series, length, &plan);
+    make_plan(n_series, &plan);
     if (workspace_bytes < plan.total) return PARIS_ENOMEM;
     paris_status ds = device_ok();
     if (ds != PARIS_OK) return ds;
@@ -278,14 +328,31 @@ paris_status paris_build(const float* series_dev, int64_t n_series, int32_t leng
     h->ws_bytes = workspace_bytes;
     h->plan = plan;
     h->mg = margins_for_length(length);
+    h->scan = ScanShape{512, 4, 4};
     h->timing = false;
-    for (int k = 0; k < 6; ++k) h->ev[k] = nullptr;
-    for (int k = 0; k < 5; ++k) h->phase_ms[k] = 0.0;
+    for (int k = 0; k < 4; ++k) h->ev[k] = nullptr;
+    for (int k = 0; k < 3; ++k) h->phase_ms[k] = 0.0;
     h->timed_queries = 0;
-    if (hipHostMalloc(reinterpret_cast<void**>(&h->host_qs), sizeof(QState), hipHostMallocDefault) != hipSuccess) {
-        h->magic = 0;
+    h->host_qs = nullptr;
+    h->host_res = nullptr;
+    h->host_res_dev = nullptr;
+    if (hipHostMalloc(reinterpret_cast<void**>(&h->host_qs), sizeof(QState), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&h->host_res), sizeof(QResult), hipHostMallocMapped) != hipSuccess ||
+        hipHostGetDevicePointer(reinterpret_cast<void**>(&h->host_res_dev), h->host_res, 0) != hipSuccess) {
+        if (h->host_qs) (void)hipHostFree(h->host_qs);
+        if (h->host_res) (void)hipHostFree(h->host_res);
         delete h;
         return PARIS_EHIP;
+    }
+    const QueryArgs a = args_for(h);
+    paris_status ts = PARIS_OK;
+    if (launch_reset(a, st) != hipSuccess) ts = PARIS_EHIP;
+    if (ts == PARIS_OK) ts = tune_scan(h, st);
+    if (ts != PARIS_OK) {
+        (void)hipHostFree(h->host_qs);
+        (void)hipHostFree(h->host_res);
+        delete h;
+        return ts;
     }
     {
         std::lock_guard<std::mutex> g(g_live_mu);
@@ -308,6 +375,9 @@ paris_status paris_get_layout(const paris_index* h, paris_layout* o)
     o->leaf_mode = h->cfg.leaf_mode;
     o->n_leaves = h->cfg.n_leaves;
     o->seed_cap = h->cfg.seed_cap;
+    o->scan_threads = h->scan.threads;
+    o->scan_blocks_per_cu = h->scan.per_cu;
+    o->scan_unroll = h->scan.unroll;
     return PARIS_OK;
 }
 
@@ -318,21 +388,22 @@ paris_status paris_query_exact(paris_index* h, const float* query_dev, int64_t* 
     if (!query_dev || !nn_index || !nn_dist || reinterpret_cast<uintptr_t>(query_dev) % 16 != 0)
         return PARIS_EINVAL;
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
-    paris_status s = run_query(h, query_dev, st, nullptr, nullptr, 0, h->timing);
+    h->host_res->idx = -2;  // overwritten by the resolve
+    paris_status s = run_query(h, query_dev, st, nullptr, nullptr, 0, h->timing, h->host_res_dev);
     if (s != PARIS_OK) return s;
-    HIP_TRY(hipMemcpyAsync(h->host_qs, h->ws + h->plan.qs, sizeof(QState), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (h->timing) {
         s = collect_timing(h);
         if (s != PARIS_OK) return s;
     }
-    const QState& q = *h->host_qs;
-    if (q.err & kErrNonFinite) return PARIS_EINVAL;
-    if (q.err & (kErrSurvOverflow | kErrDoneOverflow)) return PARIS_EOVERFLOW;
-    if (q.res_idx < 0) return PARIS_EINVAL;
-    *nn_index = q.res_idx;
-    *nn_dist = std::sqrt(q.res_d2);
-    if (stats) fill_stats(q, stats);
+    const QResult r = *h->host_res;
+    if (r.idx == -2) return PARIS_EHIP;
+    if (r.err & kErrNonFinite) return PARIS_EINVAL;
+    if (r.err & (kErrSurvOverflow | kErrDoneOverflow)) return PARIS_EOVERFLOW;
+    if (r.idx < 0) return PARIS_EINVAL;
+    *nn_index = r.idx;
+    *nn_dist = std::sqrt(r.d2);
+    if (stats) fill_stats(r, stats);
     return PARIS_OK;
 }
 
@@ -351,10 +422,11 @@ paris_status paris_query_batch(paris_index* h, const float* queries_dev, int64_t
         paris_status s = run_query(h, q, st, reinterpret_cast<long long*>(nn_index_dev), nn_dist_dev, i, false);
         if (s != PARIS_OK) return s;
         if (stats) {
-            HIP_TRY(hipMemcpyAsync(h->host_qs, h->ws + h->plan.qs, sizeof(QState), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipMemcpyAsync(&h->host_qs->res, &reinterpret_cast<QState*>(h->ws + h->plan.qs)->res,
+                                   sizeof(QResult), hipMemcpyDeviceToHost, st));
             HIP_TRY(hipStreamSynchronize(st));
             paris_stats one;
-            fill_stats(*h->host_qs, &one);
+            fill_stats(h->host_qs->res, &one);
             agg.lb_survivors += one.lb_survivors;
             agg.refined += one.refined;
             agg.abandoned += one.abandoned;
@@ -377,10 +449,11 @@ paris_status paris_query_info_get(paris_index* h, const float* query_dev, paris_
     if (!query_dev || reinterpret_cast<uintptr_t>(query_dev) % 16 != 0) return PARIS_EINVAL;
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     const QueryArgs a = args_for(h);
-    HIP_TRY(launch_prepare(a, query_dev, st));
+    HIP_TRY(launch_prepare_seed(a, query_dev, st));
     if (table_dev) HIP_TRY(hipMemcpyAsync(table_dev, a.t8, kSeg * kSym * 4, hipMemcpyDeviceToDevice, st));
     if (coarse_dev) HIP_TRY(hipMemcpyAsync(coarse_dev, a.t5, kSeg * kCoarse * 4, hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipMemcpyAsync(h->host_qs, a.qs, sizeof(QState), hipMemcpyDeviceToHost, st));
+    HIP_TRY(launch_reset(a, st));
     HIP_TRY(hipStreamSynchronize(st));
     const QState& q = *h->host_qs;
     if (info) {
@@ -404,22 +477,32 @@ paris_status paris_lb_scan(paris_index* h, const float* query_dev, float thresho
         return PARIS_EINVAL;
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     QueryArgs a = args_for(h);
-    HIP_TRY(launch_prepare(a, query_dev, st));
-    HIP_TRY(launch_lbscan(a, threshold_sq, st));
+    HIP_TRY(launch_prepare_seed(a, query_dev, st));
+    if (h->timing) HIP_TRY(hipEventRecord(h->ev[1], st));
+    HIP_TRY(launch_lbscan(a, threshold_sq, h->scan, st));
+    if (h->timing) HIP_TRY(hipEventRecord(h->ev[2], st));
     HIP_TRY(hipMemcpyAsync(h->host_qs, a.qs, sizeof(QState), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     const QState& q = *h->host_qs;
-    if (q.err & kErrNonFinite) return PARIS_EINVAL;
     const long long n = q.n_surv;
-    *count = n;
+    const uint32_t qerr = q.err;
+    if (h->timing) {  // the scan alone is added to phase [1]
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, h->ev[1], h->ev[2]));
+        h->phase_ms[1] += ms;
+        h->timed_queries += 1;
+    }
     const long long k = n < capacity ? n : capacity;
     if (k > 0) {
         // survivors are (index, bound) pairs in the survivor buffer; split them for the caller
         HIP_TRY(hipMemcpy2DAsync(idx_dev, 4, a.surv, 8, 4, (size_t)k, hipMemcpyDeviceToDevice, st));
         HIP_TRY(hipMemcpy2DAsync(lb_dev, 4, reinterpret_cast<uint8_t*>(a.surv) + 4, 8, 4, (size_t)k,
                                  hipMemcpyDeviceToDevice, st));
-        HIP_TRY(hipStreamSynchronize(st));
     }
+    HIP_TRY(launch_reset(a, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    if (qerr & kErrNonFinite) return PARIS_EINVAL;
+    *count = n;
     return n > capacity ? PARIS_EOVERFLOW : PARIS_OK;
 }
 
@@ -427,19 +510,19 @@ paris_status paris_set_timing(paris_index* h, int32_t enable)
 {
     if (!handle_ok(h)) return PARIS_ESTATE;
     if (enable && !h->ev[0]) {
-        for (int k = 0; k < 6; ++k) HIP_TRY(hipEventCreate(&h->ev[k]));
+        for (int k = 0; k < 4; ++k) HIP_TRY(hipEventCreate(&h->ev[k]));
     }
     h->timing = enable != 0;
-    for (int k = 0; k < 5; ++k) h->phase_ms[k] = 0.0;
+    for (int k = 0; k < 3; ++k) h->phase_ms[k] = 0.0;
     h->timed_queries = 0;
     return PARIS_OK;
 }
 
-paris_status paris_get_timing(const paris_index* h, double* ms_out5, int64_t* n_queries)
+paris_status paris_get_timing(const paris_index* h, double* ms_out3, int64_t* n_queries)
 {
     if (!handle_ok(h)) return PARIS_ESTATE;
-    if (!ms_out5 || !n_queries) return PARIS_EINVAL;
-    for (int k = 0; k < 5; ++k) ms_out5[k] = h->phase_ms[k];
+    if (!ms_out3 || !n_queries) return PARIS_EINVAL;
+    for (int k = 0; k < 3; ++k) ms_out3[k] = h->phase_ms[k];
     *n_queries = h->timed_queries;
     return PARIS_OK;
 }
@@ -453,7 +536,8 @@ paris_status paris_free(paris_index* h)
     }
     h->magic = 0;
     if (h->host_qs) (void)hipHostFree(h->host_qs);
-    for (int k = 0; k < 6; ++k)
+    if (h->host_res) (void)hipHostFree(h->host_res);
+    for (int k = 0; k < 4; ++k)
         if (h->ev[k]) (void)hipEventDestroy(h->ev[k]);
     delete h;
     return PARIS_OK;

@@ -131,7 +131,7 @@ constexpr int kTile = 4096;  // 256 threads x 16 rounds
 
 static long long num_tiles(long long N) { return (N + kTile - 1) / kTile; }
 
-size_t sort_hist_words(long long N) { return (size_t)num_tiles(N) * 256; }
+size_t sort_hist_words(long long N) { return (size_t)num_tiles(N) * 256 + 256; }
 
 __global__ __launch_bounds__(256) void k_rs_hist(const unsigned long long* __restrict__ keys, long long N,
                                                  int shift, uint32_t* __restrict__ hist, long long ntiles)
@@ -149,28 +149,51 @@ __global__ __launch_bounds__(256) void k_rs_hist(const unsigned long long* __res
     hist[(long long)threadIdx.x * ntiles + blockIdx.x] = h[threadIdx.x];
 }
 
-__global__ __launch_bounds__(1024) void k_rs_scan(uint32_t* __restrict__ a, long long total)
+// Exclusive scan of the digit-major histogram in two launches: the total of every digit row,
+// then each row scanned by its own block starting from the sum of the rows before it.
+__device__ __forceinline__ uint32_t block_sum_256(uint32_t v, uint32_t* red)
 {
-    __shared__ uint32_t part[1024];
-    const int tid = threadIdx.x;
-    const long long per = (total + 1023) / 1024;
-    const long long lo = tid * per;
-    const long long hi = (lo + per < total) ? lo + per : total;
-    uint32_t sum = 0;
-    for (long long i = lo; i < hi; ++i) sum += a[i];
-    part[tid] = sum;
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
     __syncthreads();
-    for (int off = 1; off < 1024; off <<= 1) {  // inclusive Hillis-Steele scan
-        const uint32_t v = tid >= off ? part[tid - off] : 0u;
+    const uint32_t s = red[0] + red[1] + red[2] + red[3];
+    __syncthreads();
+    return s;
+}
+
+__global__ __launch_bounds__(256) void k_rs_rowsum(const uint32_t* __restrict__ hist, long long ntiles,
+                                                   uint32_t* __restrict__ totals)
+{
+    __shared__ uint32_t red[4];
+    const uint32_t* row = hist + (long long)blockIdx.x * ntiles;
+    uint32_t s = 0;
+    for (long long t = threadIdx.x; t < ntiles; t += 256) s += row[t];
+    s = block_sum_256(s, red);
+    if (threadIdx.x == 0) totals[blockIdx.x] = s;
+}
+
+__global__ __launch_bounds__(256) void k_rs_rowscan(uint32_t* __restrict__ hist, long long ntiles,
+                                                    const uint32_t* __restrict__ totals)
+{
+    __shared__ uint32_t red[4];
+    __shared__ uint32_t part[256];
+    const int tid = threadIdx.x, d = blockIdx.x;
+    uint32_t carry = block_sum_256(tid < d ? totals[tid] : 0u, red);  // rows before this one
+    uint32_t* row = hist + (long long)d * ntiles;
+    for (long long c = 0; c < ntiles; c += 256) {
+        const long long t = c + tid;
+        const uint32_t v = t < ntiles ? row[t] : 0u;
+        part[tid] = v;
         __syncthreads();
-        part[tid] += v;
+        for (int off = 1; off < 256; off <<= 1) {  // inclusive Hillis-Steele scan
+            const uint32_t o = tid >= off ? part[tid - off] : 0u;
+            __syncthreads();
+            part[tid] += o;
+            __syncthreads();
+        }
+        if (t < ntiles) row[t] = carry + part[tid] - v;
+        carry += part[255];
         __syncthreads();
-    }
-    uint32_t run = part[tid] - sum;
-    for (long long i = lo; i < hi; ++i) {
-        const uint32_t v = a[i];
-        a[i] = run;
-        run += v;
     }
 }
 
@@ -226,7 +249,8 @@ hipError_t launch_sort_keys(unsigned long long* keys, uint32_t* perm, unsigned l
     for (int pass = 0; pass < 8; ++pass) {  // even pass count: the result ends in keys / perm
         const int shift = 8 * pass;
         k_rs_hist<<<(unsigned)nt, 256, 0, st>>>(ka, N, shift, hist, nt);
-        k_rs_scan<<<1, 1024, 0, st>>>(hist, nt * 256);
+        k_rs_rowsum<<<256, 256, 0, st>>>(hist, nt, hist + nt * 256);
+        k_rs_rowscan<<<256, 256, 0, st>>>(hist, nt, hist + nt * 256);
         k_rs_scatter<<<(unsigned)nt, 256, 0, st>>>(ka, va, kb, vb, N, shift, hist, nt);
         hipError_t e = hipGetLastError();
         if (e != hipSuccess) return e;

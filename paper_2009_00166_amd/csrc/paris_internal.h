@@ -12,6 +12,9 @@ constexpr int kSeg = 16;           // w, segments per iSAX word
 constexpr int kSym = 256;          // 8-bit symbols
 constexpr int kCoarse = 32;        // 5-bit prefix alphabet of the coarse lower-bound table
 constexpr int kMaxLength = 2048;   // longest series the summarise kernel stages in LDS
+constexpr int kSeedChunk = 512;    // sorted positions per seed block: its smallest bound is refined
+constexpr int kResolveList = 256;  // in-band candidates resolved block-cooperatively
+constexpr int kRefineBlocks = 128; // refine grid (16 lane groups of 16 lanes per block)
 
 // Best-so-far key: float32 bits of the squared distance (non-negative, so the bit pattern
 // orders like the value) in the high word, series index in the low word. atomicMin on it keeps
@@ -24,22 +27,35 @@ enum ErrBits : uint32_t {
     kErrDoneOverflow = 4u,   // more completed candidates than capacity
 };
 
-// Per-query device state. Written by the prepare kernel, updated by the search kernels, read
-// back by the host after the resolve kernel.
+// Result of one query, written by the last kernel of the query.
+struct QResult {
+    long long idx;            // -1 if none (non-finite query)
+    double d2;                // float64 squared distance
+    unsigned long long seed_key;
+    long long win_lo, win_hi;
+    uint32_t n_surv, n_refined, n_abandon, n_bsf_upd, n_resolved, err;
+};
+
+// Per-query device state. The last kernel of every query snapshots the result and leaves the
+// working fields reset for the next query (so no kernel has to clear them before the seed's
+// atomics); the build initialises them.
 struct alignas(256) QState {
+    // summaries of the current query (written by block 0 of the prepare kernel)
     double paa[kSeg];
     uint8_t sym[kSeg];
     uint32_t root;
     uint32_t pad0;
     unsigned long long k64;
     long long win_lo, win_hi;
+    // working fields (reset after every query)
     unsigned long long bsf_key;
     unsigned long long seed_key;
-    uint32_t n_surv, n_refined, n_abandon, n_bsf_upd, n_done, n_resolved;
+    unsigned long long head_key;   // (fine bound bits, index) of the survivor with the smallest bound
+    uint32_t n_surv, n_refined, n_abandon, n_bsf_upd, n_done;
     uint32_t err;
+    uint32_t blocks_done;
     uint32_t pad1;
-    long long res_idx;
-    double res_d2;
+    QResult res;
 };
 
 // Pruning margins, derived on the host from the series length (see margins_for_length).
@@ -75,15 +91,26 @@ struct QueryArgs {
     uint2* done;      // (index, d2 fp32 bits)
     uint32_t done_cap;
     Margins mg;
+    QResult* host_res;  // pinned host memory mapped for the device (may be null): the result is
+                        // also stored there, so the host needs no copy after synchronising
 };
 
-hipError_t launch_prepare(const QueryArgs& a, const float* q, hipStream_t st);
-hipError_t launch_seed(const QueryArgs& a, const float* q, hipStream_t st);
+// Launch shape of the lower-bound scan (chosen by the autotuner on first use).
+struct ScanShape {
+    int threads;   // 256 or 512
+    int per_cu;    // blocks per compute unit
+    int unroll;    // words per lane loaded ahead: 2, 4 or 8
+};
+
+hipError_t launch_reset(const QueryArgs& a, hipStream_t st);
+// query summaries, tables, window, and the lower-bound-guided approximate-search seed
+hipError_t launch_prepare_seed(const QueryArgs& a, const float* q, hipStream_t st);
 // threshold_sq < 0: use the best-so-far in QState; otherwise a fixed threshold.
-hipError_t launch_lbscan(const QueryArgs& a, float threshold_sq, hipStream_t st);
-hipError_t launch_refine(const QueryArgs& a, const float* q, hipStream_t st);
-// out_idx / out_dist may be null; otherwise element qi receives the answer.
-hipError_t launch_resolve(const QueryArgs& a, const float* q, long long* out_idx, double* out_dist,
-                          long long qi, hipStream_t st);
+hipError_t launch_lbscan(const QueryArgs& a, float threshold_sq, ScanShape shape, hipStream_t st);
+// refinement; its last block resolves in float64, writes the result (and element qi of
+// out_idx / out_dist when they are not null) and resets the state for the next query.
+hipError_t launch_refine_resolve(const QueryArgs& a, const float* q, long long* out_idx, double* out_dist,
+                                 long long qi, hipStream_t st);
+int seed_grid(const QueryArgs& a);
 
 }  // namespace paris

@@ -1,5 +1,6 @@
-// Query-side kernels of the exact 1-NN search (Section 3.3): prepare, approximate-search seed,
-// lower-bound scan (LBC workers), early-abandoning refinement (RDC workers), float64 resolve.
+// Query-side kernels of the exact 1-NN search (Section 3.3): prepare + approximate-search seed,
+// lower-bound scan (LBC workers), early-abandoning refinement (RDC workers) with the float64
+// resolve in its last block.
 #include "paris_internal.h"
 
 namespace paris {
@@ -27,7 +28,7 @@ __device__ __forceinline__ float prune_threshold(float bsf, double rel)
     return __double2float_ru((double)bsf * (1.0 + rel) + 1e-25);
 }
 
-// all-reduce of a float over the 16 lanes of a lane group (butterfly: identical on all lanes)
+// all-reduce over 16-lane groups / whole waves (butterfly: bit-identical result on all lanes)
 __device__ __forceinline__ float group16_sum(float v)
 {
     v += __shfl_xor(v, 8, 16);
@@ -37,11 +38,77 @@ __device__ __forceinline__ float group16_sum(float v)
     return v;
 }
 
+__device__ __forceinline__ float wave_sum(float v)
+{
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    return v;
+}
+
+__device__ __forceinline__ uint32_t word_at(const uint4 w, int k)
+{
+    return k == 0 ? w.x : k == 1 ? w.y : k == 2 ? w.z : w.w;
+}
+
+// fine bound: sum over the 16 segments of T8[s][sym_s]
+__device__ __forceinline__ float fine_lb(const uint4 w, const float* __restrict__ t8)
+{
+    float part[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t x = word_at(w, k);
+        const float a = t8[(4 * k + 0) * 256 + (x & 255)];
+        const float b = t8[(4 * k + 1) * 256 + ((x >> 8) & 255)];
+        const float c = t8[(4 * k + 2) * 256 + ((x >> 16) & 255)];
+        const float d = t8[(4 * k + 3) * 256 + (x >> 24)];
+        part[k] = (a + b) + (c + d);
+    }
+    return (part[0] + part[1]) + (part[2] + part[3]);
+}
+
+// coarse bound: sum over the 16 segments of T5[s][sym_s >> 3]
+__device__ __forceinline__ float coarse_lb(const uint4 w, const float* __restrict__ t5)
+{
+    float part[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t x = word_at(w, k);
+        const float a = t5[(4 * k + 0) * 32 + ((x >> 3) & 31)];
+        const float b = t5[(4 * k + 1) * 32 + ((x >> 11) & 31)];
+        const float c = t5[(4 * k + 2) * 32 + ((x >> 19) & 31)];
+        const float d = t5[(4 * k + 3) * 32 + ((x >> 27) & 31)];
+        part[k] = (a + b) + (c + d);
+    }
+    return (part[0] + part[1]) + (part[2] + part[3]);
+}
+
+__device__ __forceinline__ void reset_state(QState* qs)
+{
+    qs->bsf_key = kBsfInit;
+    qs->seed_key = kBsfInit;
+    qs->head_key = ~0ull;
+    qs->n_surv = qs->n_refined = qs->n_abandon = qs->n_bsf_upd = qs->n_done = 0;
+    qs->err = 0;
+    qs->blocks_done = 0;
+}
+
+__global__ void k_reset(QState* qs)
+{
+    if (threadIdx.x == 0) reset_state(qs);
+}
+
+hipError_t launch_reset(const QueryArgs& a, hipStream_t st)
+{
+    k_reset<<<1, 64, 0, st>>>(a.qs);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------------------------------
-// prepare (one 256-thread block): query PAA and symbols (same arithmetic as the build), root and
-// leaf keys, the lower-bound tables, the approximate-search window, and a fresh search state.
-//   T8[s][c] = L * delta(q_s, region c)^2 in float64, rounded toward zero to float32;
-//   T5[s][g] = min_{k<8} T8[s][8g+k] = the same term at 32 symbols (5-bit prefix).
+// prepare + seed. Every block computes the query summaries (same arithmetic as the build), the
+// table T8[s][c] = L * delta(q_s, region c)^2 (float64, rounded toward zero to float32) in LDS,
+// and the approximate-search window (sorted positions). Block 0 also publishes T8, the coarse
+// table T5[s][g] = min_{k<8} T8[s][8g+k] and the summaries. Then block b takes window chunk b
+// (kSeedChunk sorted positions), finds the member with the smallest fine bound, computes its
+// float32 squared distance with one wave and folds it into the best-so-far (atomicMin).
 // ------------------------------------------------------------------------------------------
 // Lower bound of key in sorted keys[a, b) found by the whole block with 256-way splits.
 __device__ long long block_lower_bound(const unsigned long long* __restrict__ keys, long long a, long long b,
@@ -71,7 +138,7 @@ __device__ long long block_lower_bound(const unsigned long long* __restrict__ ke
     }
 }
 
-__global__ __launch_bounds__(256) void k_prepare(QueryArgs A, const float* __restrict__ q)
+__global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* __restrict__ q)
 {
     extern __shared__ float qv[];
     __shared__ double beta[257];
@@ -84,8 +151,9 @@ __global__ __launch_bounds__(256) void k_prepare(QueryArgs A, const float* __res
     __shared__ int s_cnt;
     __shared__ double red_lb[256];
     __shared__ int red_r[256];
+    __shared__ unsigned long long red_key[4];
 
-    const int tid = threadIdx.x;
+    const int tid = threadIdx.x, lane = tid & 63;
     const int n = A.n, L = n >> 4;
     if (tid == 0) { s_bad = 0; beta[0] = -__builtin_inf(); beta[256] = __builtin_inf(); }
     if (tid >= 1) beta[tid] = c_beta[tid];
@@ -107,8 +175,6 @@ __global__ __launch_bounds__(256) void k_prepare(QueryArgs A, const float* __res
         }
         qpaa[tid] = m;
         qsym[tid] = c;
-        A.qs->paa[tid] = m;
-        A.qs->sym[tid] = (uint8_t)c;
         if (bad) atomicOr(&s_bad, 1u);
     }
     __syncthreads();
@@ -125,21 +191,24 @@ __global__ __launch_bounds__(256) void k_prepare(QueryArgs A, const float* __res
         double d = 0.0;
         if (x < lo) d = lo - x;          // query mean BELOW the region
         else if (x > hi) d = x - hi;     // ABOVE the region
-        const double v = (double)L * (d * d);
-        const float f = __double2float_rz(v);
-        t8[e] = f;
-        A.t8[e] = f;
+        t8[e] = __double2float_rz((double)L * (d * d));
     }
     __syncthreads();
-    for (int e = tid; e < kSeg * kCoarse; e += 256) {
-        const int s = e >> 5, g = e & 31;
-        const float* p = t8 + s * kSym + g * 8;
-        float m = p[0];
-        for (int k = 1; k < 8; ++k) m = fminf(m, p[k]);
-        A.t5[e] = m;
+    if (blockIdx.x == 0) {
+        for (int e = tid; e < kSeg * kSym; e += 256) A.t8[e] = t8[e];
+        for (int e = tid; e < kSeg * kCoarse; e += 256) {
+            const float* p = t8 + (e >> 5) * kSym + (e & 31) * 8;
+            float m = p[0];
+            for (int k = 1; k < 8; ++k) m = fminf(m, p[k]);
+            A.t5[e] = m;
+        }
+        if (tid < kSeg) {
+            A.qs->paa[tid] = qpaa[tid];
+            A.qs->sym[tid] = (uint8_t)qsym[tid];
+        }
     }
 
-    // approximate-search window (sorted positions)
+    // approximate-search window (sorted positions), computed by every block
     long long lo = 0, hi = 0;
     const unsigned long long kq = s_k64;
     if (A.leaf_mode == 0) {
@@ -149,7 +218,6 @@ __global__ __launch_bounds__(256) void k_prepare(QueryArgs A, const float* __res
             hi = A.roff[R + 1];
             if (lo == hi) {
                 // empty subtree: the non-empty one with the smallest cardinality-2 lower bound
-                // L * sum over segments whose top bit differs from the query's of q_s^2
                 double best = __builtin_inf();
                 int br = 0x7FFFFFFF;
                 for (int r = tid * 256; r < tid * 256 + 256; ++r) {
@@ -202,113 +270,120 @@ __global__ __launch_bounds__(256) void k_prepare(QueryArgs A, const float* __res
         lo = ell * N / nl;
         hi = (ell + 1) * N / nl;
     }
-    if (tid == 0) {
+    if (blockIdx.x == 0 && tid == 0) {
         QState* qs = A.qs;
         qs->root = s_root;
         qs->k64 = kq;
         qs->win_lo = lo;
         qs->win_hi = hi;
-        qs->bsf_key = kBsfInit;
-        qs->seed_key = kBsfInit;
-        qs->n_surv = qs->n_refined = qs->n_abandon = qs->n_bsf_upd = qs->n_done = qs->n_resolved = 0;
-        qs->err = s_bad ? (uint32_t)kErrNonFinite : 0u;
-        qs->res_idx = -1;
-        qs->res_d2 = __builtin_inf();
+        if (s_bad) atomicOr(&qs->err, (uint32_t)kErrNonFinite);
     }
-}
 
-hipError_t launch_prepare(const QueryArgs& a, const float* q, hipStream_t st)
-{
-    k_prepare<<<1, 256, (size_t)a.n * sizeof(float), st>>>(a, q);
-    return hipGetLastError();
-}
-
-// ------------------------------------------------------------------------------------------
-// seed: float32 squared distance from the query to every member of the approximate-search
-// window (16 lanes per member), folded into the best-so-far key with atomicMin.
-// ------------------------------------------------------------------------------------------
-__device__ __forceinline__ float ed2_group16(const float* __restrict__ row, const float* __restrict__ q,
-                                             int nv, int l)
-{
-    const float4* r4 = reinterpret_cast<const float4*>(row);
-    const float4* q4 = reinterpret_cast<const float4*>(q);
-    float acc = 0.f;
-    for (int v = l; v < nv; v += 16) {
-        const float4 a = r4[v], b = q4[v];
-        const float dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z, dw = b.w - a.w;
-        acc += (dx * dx + dy * dy) + (dz * dz + dw * dw);
-    }
-    return group16_sum(acc);
-}
-
-__global__ __launch_bounds__(256) void k_seed(QueryArgs A, const float* __restrict__ q)
-{
-    const long long lo = A.qs->win_lo, hi = A.qs->win_hi;
-    const int l = threadIdx.x & 15;
-    const long long grp = ((long long)blockIdx.x * 256 + threadIdx.x) >> 4;
-    const long long ngrp = (long long)gridDim.x * 16;
-    const int nv = A.n >> 2;
-    for (long long p = lo + grp; p < hi; p += ngrp) {
+    // seed: the smallest fine bound of this block's chunk, then its real distance
+    const long long c0 = lo + (long long)blockIdx.x * kSeedChunk;
+    if (c0 >= hi || s_bad) return;  // uniform across the block
+    const long long c1 = (c0 + kSeedChunk < hi) ? c0 + kSeedChunk : hi;
+    unsigned long long best = ~0ull;  // (lb bits, row)
+    for (long long p = c0 + tid; p < c1; p += 256) {
         const uint32_t row = A.perm[p];
-        const float d = ed2_group16(A.X + (long long)row * A.n, q, nv, l);
-        if (l == 0) atomicMin(&A.qs->bsf_key, pack_key(d, row));
+        const uint4 w = reinterpret_cast<const uint4*>(A.sax)[row];
+        const float lb = fine_lb(w, t8);
+        const unsigned long long k = pack_key(lb, row);
+        best = k < best ? k : best;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+        const unsigned long long o = __shfl_xor(best, off);
+        best = o < best ? o : best;
+    }
+    if (lane == 0) red_key[tid >> 6] = best;
+    __syncthreads();
+    if (tid < 64) {
+        best = red_key[0];
+        for (int k = 1; k < 4; ++k) best = red_key[k] < best ? red_key[k] : best;
+        const uint32_t row = (uint32_t)(best & 0xFFFFFFFFu);
+        const float4* r4 = reinterpret_cast<const float4*>(A.X + (long long)row * n);
+        const float4* q4 = reinterpret_cast<const float4*>(qv);
+        float acc = 0.f;
+        for (int v = lane; v < (n >> 2); v += 64) {
+            const float4 a = r4[v], b = q4[v];
+            const float dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z, dw = b.w - a.w;
+            acc += (dx * dx + dy * dy) + (dz * dz + dw * dw);
+        }
+        acc = wave_sum(acc);
+        if (lane == 0) atomicMin(&A.qs->bsf_key, pack_key(acc, row));
     }
 }
 
-hipError_t launch_seed(const QueryArgs& a, const float* q, hipStream_t st)
+int seed_grid(const QueryArgs& a)
 {
-    k_seed<<<128, 256, 0, st>>>(a, q);
+    long long win = 0;
+    if (a.leaf_mode == 0) win = a.seed_cap;
+    else win = (a.N + a.n_leaves - 1) / a.n_leaves;
+    long long g = (win + kSeedChunk - 1) / kSeedChunk;
+    return (int)(g < 1 ? 1 : g);
+}
+
+hipError_t launch_prepare_seed(const QueryArgs& a, const float* q, hipStream_t st)
+{
+    k_prepare_seed<<<seed_grid(a), 256, (size_t)a.n * sizeof(float), st>>>(a, q);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------------------------
-// lbscan (LBC workers): one 16-byte iSAX word per lane per step.
+// lbscan (LBC workers): one 16-byte iSAX word per lane per step, U steps loaded ahead into
+// registers (the next group is fetched while the current one is evaluated).
 //   coarse bound: sum over s of T5[s][sym_s >> 3] from LDS. All lanes of a wave read table s at
-//   the same time, and table s is 32 consecutive words, so every LDS read is conflict-free
+//   the same time and table s is 32 consecutive words, so every LDS read is conflict-free
 //   (distinct banks or broadcasts) whatever the symbols are;
-//   fine bound (only for lanes the coarse bound did not prune): sum of T8[s][sym_s] from the
-//   L1/L2-resident global table;
+//   fine bound (only lanes the coarse bound did not prune): sum of T8[s][sym_s], also in LDS;
 //   survivors (fine bound <= threshold) are appended with one atomicAdd per wave: ballot, then
 //   each lane's rank among the set lanes below it (mbcnt).
 // ------------------------------------------------------------------------------------------
-__device__ __forceinline__ float coarse_lb(const uint4 w, const float* __restrict__ t5)
+// Survivors are staged per block in LDS (one LDS atomic per wave) and flushed to the global
+// list with one global atomic per flush: a single global counter hit by every wave with a
+// survivor serialises the scan when survivors are many.
+__device__ __forceinline__ void flush_survivors(const QueryArgs& A, uint2* sbuf, uint32_t* scount,
+                                                uint32_t* sbase)
 {
-    float part[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const uint32_t x = (k == 0) ? w.x : (k == 1) ? w.y : (k == 2) ? w.z : w.w;
-        const float a = t5[(4 * k + 0) * 32 + ((x >> 3) & 31)];
-        const float b = t5[(4 * k + 1) * 32 + ((x >> 11) & 31)];
-        const float c = t5[(4 * k + 2) * 32 + ((x >> 19) & 31)];
-        const float d = t5[(4 * k + 3) * 32 + ((x >> 27) & 31)];
-        part[k] = (a + b) + (c + d);
-    }
-    return (part[0] + part[1]) + (part[2] + part[3]);
+    const uint32_t cnt = *scount;
+    if (threadIdx.x == 0) *sbase = cnt ? atomicAdd(&A.qs->n_surv, cnt) : 0u;
+    __syncthreads();
+    const uint32_t b = *sbase;
+    for (uint32_t k = threadIdx.x; k < cnt; k += blockDim.x)
+        if (b + k < A.surv_cap) A.surv[b + k] = sbuf[k];
+    __syncthreads();
+    if (threadIdx.x == 0) *scount = 0;
+    __syncthreads();
 }
 
-__device__ __forceinline__ float fine_lb(const uint4 w, const float* __restrict__ t8)
-{
-    float part[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const uint32_t x = (k == 0) ? w.x : (k == 1) ? w.y : (k == 2) ? w.z : w.w;
-        const float a = t8[(4 * k + 0) * 256 + (x & 255)];
-        const float b = t8[(4 * k + 1) * 256 + ((x >> 8) & 255)];
-        const float c = t8[(4 * k + 2) * 256 + ((x >> 16) & 255)];
-        const float d = t8[(4 * k + 3) * 256 + (x >> 24)];
-        part[k] = (a + b) + (c + d);
-    }
-    return (part[0] + part[1]) + (part[2] + part[3]);
-}
-
-constexpr int kScanUnroll = 4;
-
-__global__ __launch_bounds__(256) void k_lbscan(QueryArgs A, float fixed_thr)
+template <int U, int BS>
+__global__ __launch_bounds__(BS) void k_lbscan(QueryArgs A, float fixed_thr)
 {
     __shared__ float t5[kSeg * kCoarse];
+    __shared__ float t8[kSeg * kSym];
+    __shared__ uint2 sbuf[2 * BS * U];
+    __shared__ uint32_t scount, sbase;
+    __shared__ unsigned long long shead;
     const int tid = threadIdx.x, lane = tid & 63;
-    t5[tid] = A.t5[tid];
-    t5[tid + 256] = A.t5[tid + 256];
+    constexpr int bs = BS;
+    const uint4* __restrict__ sax = reinterpret_cast<const uint4*>(A.sax);
+    const long long N = A.N;
+    const long long stride = (long long)gridDim.x * bs;
+    long long base = (long long)blockIdx.x * bs;
+    if (tid == 0) { scount = 0; shead = ~0ull; }
+
+    uint4 nxt[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {  // first words are in flight while the tables load
+        const long long i = base + u * stride + tid;
+        nxt[u] = (i < N) ? sax[i] : make_uint4(0, 0, 0, 0);
+    }
+    for (int e = tid; e < kSeg * kCoarse; e += bs) t5[e] = A.t5[e];
+    {
+        const float4* s8 = reinterpret_cast<const float4*>(A.t8);
+        float4* d8 = reinterpret_cast<float4*>(t8);
+        for (int e = tid; e < kSeg * kSym / 4; e += bs) d8[e] = s8[e];
+    }
     float thr;
     if (fixed_thr >= 0.f) {
         thr = fixed_thr;
@@ -318,175 +393,168 @@ __global__ __launch_bounds__(256) void k_lbscan(QueryArgs A, float fixed_thr)
         if (blockIdx.x == 0 && tid == 0) A.qs->seed_key = key;
     }
     __syncthreads();
-    const uint4* __restrict__ sax = reinterpret_cast<const uint4*>(A.sax);
-    const long long N = A.N;
-    const long long stride = (long long)gridDim.x * 256;
-    for (long long base = (long long)blockIdx.x * 256; base < N; base += stride * kScanUnroll) {
-        uint4 w[kScanUnroll];
+
+    for (; base < N; base += stride * U) {
+        uint4 cur[U];
 #pragma unroll
-        for (int u = 0; u < kScanUnroll; ++u) {
-            const long long i = base + u * stride + tid;
-            w[u] = (i < N) ? sax[i] : make_uint4(0, 0, 0, 0);
+        for (int u = 0; u < U; ++u) cur[u] = nxt[u];
+        const long long nb = base + stride * U;
+        if (nb < N) {
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const long long i = nb + u * stride + tid;
+                nxt[u] = (i < N) ? sax[i] : make_uint4(0, 0, 0, 0);
+            }
         }
+        unsigned long long mhead = ~0ull;
 #pragma unroll
-        for (int u = 0; u < kScanUnroll; ++u) {
+        for (int u = 0; u < U; ++u) {
             const long long i = base + u * stride + tid;
-            const float lb5 = coarse_lb(w[u], t5);
+            const float lb5 = coarse_lb(cur[u], t5);
             bool pass = (i < N) && (lb5 <= thr);
             float lb8 = 0.f;
             if (pass) {
-                lb8 = fine_lb(w[u], A.t8);
+                lb8 = fine_lb(cur[u], t8);
                 pass = lb8 <= thr;
             }
             const unsigned long long m = __ballot(pass);
-            if (m) {
+            if (m) {  // at most BS * U appends per outer step: the buffer holds two steps
                 const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
                 const int leader = __ffsll((long long)m) - 1;
                 uint32_t basepos = 0;
-                if (lane == leader) basepos = atomicAdd(&A.qs->n_surv, (uint32_t)__popcll(m));
+                if (lane == leader) basepos = atomicAdd(&scount, (uint32_t)__popcll(m));
                 basepos = __shfl(basepos, leader);
                 if (pass) {
-                    const uint32_t pos = basepos + rank;
-                    if (pos < A.surv_cap) A.surv[pos] = make_uint2((uint32_t)i, __float_as_uint(lb8));
+                    sbuf[basepos + rank] = make_uint2((uint32_t)i, __float_as_uint(lb8));
+                    const unsigned long long hk = pack_key(lb8, (uint32_t)i);
+                    mhead = hk < mhead ? hk : mhead;
                 }
             }
         }
+        if (mhead != ~0ull) atomicMin(&shead, mhead);
+        __syncthreads();
+        if (scount >= (uint32_t)(bs * U)) flush_survivors(A, sbuf, &scount, &sbase);
     }
+    __syncthreads();
+    if (scount) flush_survivors(A, sbuf, &scount, &sbase);
+    if (tid == 0 && shead != ~0ull) atomicMin(&A.qs->head_key, shead);
 }
 
-static int g_scan_grid = 0;
-
-hipError_t launch_lbscan(const QueryArgs& a, float threshold_sq, hipStream_t st)
+template <int U, int BS>
+static hipError_t launch_scan_t(const QueryArgs& a, float thr, int per_cu, int cus, hipStream_t st)
 {
-    if (g_scan_grid == 0) {
-        int dev = 0, cus = 256;
+    const long long need = (a.N + (long long)BS * U - 1) / ((long long)BS * U);
+    long long grid = (long long)cus * (per_cu > 0 ? per_cu : 4);
+    if (grid > need) grid = need;
+    if (grid < 1) grid = 1;
+    k_lbscan<U, BS><<<(unsigned)grid, BS, 0, st>>>(a, thr);
+    return hipGetLastError();
+}
+
+hipError_t launch_lbscan(const QueryArgs& a, float threshold_sq, ScanShape shape, hipStream_t st)
+{
+    static int cus = 0;
+    if (cus == 0) {
+        int dev = 0;
         if (hipGetDevice(&dev) != hipSuccess ||
             hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
             cus = 256;
-        g_scan_grid = cus * 8;
     }
-    const long long need = (a.N + 256LL * kScanUnroll - 1) / (256LL * kScanUnroll);
-    const int grid = (int)(need < g_scan_grid ? need : g_scan_grid);
-    k_lbscan<<<grid > 0 ? grid : 1, 256, 0, st>>>(a, threshold_sq);
-    return hipGetLastError();
+    const bool wide = shape.threads == 512;
+    if (shape.unroll == 8)
+        return wide ? launch_scan_t<8, 512>(a, threshold_sq, shape.per_cu, cus, st)
+                    : launch_scan_t<8, 256>(a, threshold_sq, shape.per_cu, cus, st);
+    if (shape.unroll == 2)
+        return wide ? launch_scan_t<2, 512>(a, threshold_sq, shape.per_cu, cus, st)
+                    : launch_scan_t<2, 256>(a, threshold_sq, shape.per_cu, cus, st);
+    return wide ? launch_scan_t<4, 512>(a, threshold_sq, shape.per_cu, cus, st)
+                : launch_scan_t<4, 256>(a, threshold_sq, shape.per_cu, cus, st);
 }
 
 // ------------------------------------------------------------------------------------------
-// refine (RDC workers): 16 lanes per survivor, 64 points (16 float4) per step. Before starting,
-// the survivor's bound is checked again against the current best-so-far; after every step the
-// partial float32 sum is compared with it (early abandoning). A completed distance is folded
-// into the best-so-far with atomicMin and, when it lies within the resolve band of the current
-// best, recorded for the float64 resolve.
+// refine (RDC workers): 16 lanes per survivor, 64 points (16 float4) per step, the next step's
+// loads issued before the current step is reduced. Before starting, the survivor's bound is
+// checked again against the current best-so-far; after every step the partial float32 sum is
+// compared with it (early abandoning). A completed distance is folded into the best-so-far with
+// atomicMin and, when within the resolve band of the current best, recorded for the resolve.
+//
+// resolve (the last block to finish): every recorded candidate within the band of the final
+// float32 best is re-scored in float64 with the fixed operation order (ascending j:
+// d = q_j - x_j; t = d * d; acc = acc + t; the library is built with -ffp-contract=off). The
+// block computes the n terms in parallel into LDS and one thread adds them in ascending order.
+// The smallest (squared distance, index) is the answer.
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_refine(QueryArgs A, const float* __restrict__ q)
+__device__ __forceinline__ float sqdiff4(const float4 a, const float4 b)
 {
-    const int tid = threadIdx.x, l = tid & 15, lane = tid & 63;
-    const uint32_t count = min(A.qs->n_surv, A.surv_cap);
-    const uint32_t grp = (blockIdx.x * 256u + tid) >> 4;
-    const uint32_t ngrp = gridDim.x * 16u;
-    const int nv = A.n >> 2;
-    const float4* q4 = reinterpret_cast<const float4*>(q);
-    uint32_t refined = 0, abandoned = 0;
-    for (uint32_t c = grp; c < count; c += ngrp) {
-        const uint2 e = A.surv[c];
-        const float lb = __uint_as_float(e.y);
-        unsigned long long key = 0;
-        if (l == 0) key = load_key(&A.qs->bsf_key);
-        key = __shfl(key, lane & ~15);
-        float thr = prune_threshold(key_dist(key), A.mg.prune_rel);
-        if (lb > thr) continue;
-        ++refined;
-        const float4* r4 = reinterpret_cast<const float4*>(A.X + (long long)e.x * A.n);
-        float acc = 0.f;
-        bool ab = false;
-        for (int v0 = 0; v0 < nv; v0 += 16) {
-            const int v = v0 + l;
-            float part = 0.f;
-            if (v < nv) {
-                const float4 a = r4[v], b = q4[v];
-                const float dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z, dw = b.w - a.w;
-                part = (dx * dx + dy * dy) + (dz * dz + dw * dw);
-            }
-            acc += group16_sum(part);
-            if (acc > thr) { ab = true; break; }
-            if (l == 0) key = load_key(&A.qs->bsf_key);
-            key = __shfl(key, lane & ~15);
-            thr = prune_threshold(key_dist(key), A.mg.prune_rel);
-        }
-        if (ab) { ++abandoned; continue; }
-        if (l == 0) {
-            const unsigned long long mine = pack_key(acc, e.x);
-            const unsigned long long old = atomicMin(&A.qs->bsf_key, mine);
-            if (mine < old) atomicAdd(&A.qs->n_bsf_upd, 1u);
-            const unsigned long long now = mine < old ? mine : old;
-            if ((double)acc <= (double)key_dist(now) * (1.0 + A.mg.band_rel) + 1e-25) {
-                const uint32_t pos = atomicAdd(&A.qs->n_done, 1u);
-                if (pos < A.done_cap) A.done[pos] = make_uint2(e.x, __float_as_uint(acc));
-            }
-        }
-    }
-    // per-wave counter aggregation (only lane 0 of each group counted)
-    uint32_t r = (l == 0) ? refined : 0u, ab = (l == 0) ? abandoned : 0u;
-    for (int off = 32; off > 0; off >>= 1) {
-        r += __shfl_xor(r, off);
-        ab += __shfl_xor(ab, off);
-    }
-    if (lane == 0) {
-        if (r) atomicAdd(&A.qs->n_refined, r);
-        if (ab) atomicAdd(&A.qs->n_abandon, ab);
-    }
+    const float dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z, dw = b.w - a.w;
+    return (dx * dx + dy * dy) + (dz * dz + dw * dw);
 }
 
-hipError_t launch_refine(const QueryArgs& a, const float* q, hipStream_t st)
+__device__ void resolve_block(const QueryArgs& A, const float* __restrict__ q, long long* out_idx,
+                              double* out_dist, long long qi)
 {
-    k_refine<<<512, 256, 0, st>>>(a, q);
-    return hipGetLastError();
-}
-
-// ------------------------------------------------------------------------------------------
-// resolve (one block): every recorded candidate within the band of the final float32 best is
-// re-scored in float64 with the fixed operation order (ascending j: d = q_j - x_j; t = d * d;
-// acc = acc + t; no contraction, the library is built with -ffp-contract=off); the answer is
-// the smallest float64 squared distance, ties to the lowest index.
-// ------------------------------------------------------------------------------------------
-__device__ double ed2_f64(const float* __restrict__ row, const float* __restrict__ q, int n)
-{
-    double acc = 0.0;
-    for (int j = 0; j < n; ++j) {
-        const double d = (double)q[j] - (double)row[j];
-        const double t = d * d;
-        acc = acc + t;
-    }
-    return acc;
-}
-
-__global__ __launch_bounds__(256) void k_resolve(QueryArgs A, const float* __restrict__ q, long long* out_idx,
-                                                 double* out_dist, long long qi)
-{
+    __shared__ double terms[kMaxLength];
+    __shared__ uint2 cand[kResolveList];
+    __shared__ uint32_t ncand, nres;
     __shared__ double rd[256];
     __shared__ long long ri[256];
-    __shared__ uint32_t rcount;
-    const int tid = threadIdx.x;
-    if (tid == 0) rcount = 0;
-    const unsigned long long key = A.qs->bsf_key;
+    const int tid = threadIdx.x, n = A.n;
+    QState* qs = A.qs;
+    const unsigned long long key = load_key(&qs->bsf_key);
     const double band = (double)key_dist(key) * (1.0 + A.mg.band_rel) + 1e-25;
-    const uint32_t count = min(A.qs->n_done, A.done_cap);
-    double bd = __builtin_inf();
-    long long bi = 0x7FFFFFFFFFFFFFFFll;
-    uint32_t nres = 0;
+    const uint32_t ndone = __hip_atomic_load(&qs->n_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t count = min(ndone, A.done_cap);
+    if (tid == 0) { ncand = 0; nres = 0; }
     __syncthreads();
     for (uint32_t e = tid; e < count; e += 256) {
         const uint2 v = A.done[e];
         if ((double)__uint_as_float(v.y) <= band) {
-            const double d = ed2_f64(A.X + (long long)v.x * A.n, q, A.n);
-            ++nres;
-            if (d < bd || (d == bd && (long long)v.x < bi)) { bd = d; bi = v.x; }
+            const uint32_t p = atomicAdd(&ncand, 1u);
+            if (p < kResolveList) cand[p] = v;
         }
+    }
+    __syncthreads();
+    double bd = __builtin_inf();
+    long long bi = 0x7FFFFFFFFFFFFFFFll;
+    if (ncand <= kResolveList) {
+        for (uint32_t c = 0; c < ncand; ++c) {
+            const uint32_t row = cand[c].x;
+            const float* x = A.X + (long long)row * n;
+            for (int j = tid; j < n; j += 256) {
+                const double d = (double)q[j] - (double)x[j];
+                terms[j] = d * d;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                double acc = 0.0;
+#pragma unroll 16
+                for (int j = 0; j < n; ++j) acc = acc + terms[j];
+                if (acc < bd || (acc == bd && (long long)row < bi)) { bd = acc; bi = row; }
+            }
+            __syncthreads();
+        }
+        if (tid == 0) nres = ncand;
+    } else {
+        // many exact ties: one thread per candidate
+        uint32_t mine = 0;
+        for (uint32_t e = tid; e < count; e += 256) {
+            const uint2 v = A.done[e];
+            if ((double)__uint_as_float(v.y) > band) continue;
+            const float* x = A.X + (long long)v.x * n;
+            double acc = 0.0;
+            for (int j = 0; j < n; ++j) {
+                const double d = (double)q[j] - (double)x[j];
+                const double t = d * d;
+                acc = acc + t;
+            }
+            ++mine;
+            if (acc < bd || (acc == bd && (long long)v.x < bi)) { bd = acc; bi = v.x; }
+        }
+        if (mine) atomicAdd(&nres, mine);
     }
     rd[tid] = bd;
     ri[tid] = bi;
-    if (nres) atomicAdd(&rcount, nres);
     __syncthreads();
     for (int off = 128; off > 0; off >>= 1) {
         if (tid < off) {
@@ -497,24 +565,137 @@ __global__ __launch_bounds__(256) void k_resolve(QueryArgs A, const float* __res
         __syncthreads();
     }
     if (tid == 0) {
-        QState* qs = A.qs;
-        const bool found = ri[0] != 0x7FFFFFFFFFFFFFFFll && qs->err == 0u;
-        if (A.qs->n_surv > A.surv_cap) qs->err |= kErrSurvOverflow;
-        if (A.qs->n_done > A.done_cap) qs->err |= kErrDoneOverflow;
-        qs->res_idx = found ? ri[0] : -1;
-        qs->res_d2 = found ? rd[0] : __builtin_nan("");
-        qs->n_resolved = rcount;
+        uint32_t err = qs->err;
+        if (qs->n_surv > A.surv_cap) err |= kErrSurvOverflow;
+        if (ndone > A.done_cap) err |= kErrDoneOverflow;
+        const bool found = ri[0] != 0x7FFFFFFFFFFFFFFFll && (err & kErrNonFinite) == 0u;
+        QResult& r = qs->res;
+        r.idx = found ? ri[0] : -1;
+        r.d2 = found ? rd[0] : __builtin_nan("");
+        r.seed_key = qs->seed_key;
+        r.win_lo = qs->win_lo;
+        r.win_hi = qs->win_hi;
+        r.n_surv = qs->n_surv;
+        r.n_refined = qs->n_refined;
+        r.n_abandon = qs->n_abandon;
+        r.n_bsf_upd = qs->n_bsf_upd;
+        r.n_resolved = nres;
+        r.err = err;
+        if (A.host_res) *A.host_res = r;
         if (out_idx) {
-            out_idx[qi] = found ? ri[0] : -1;
+            out_idx[qi] = r.idx;
             out_dist[qi] = found ? sqrt(rd[0]) : __builtin_nan("");
         }
+        reset_state(qs);
     }
 }
 
-hipError_t launch_resolve(const QueryArgs& a, const float* q, long long* out_idx, double* out_dist,
-                          long long qi, hipStream_t st)
+__global__ __launch_bounds__(256) void k_refine_resolve(QueryArgs A, const float* __restrict__ q,
+                                                        long long* out_idx, double* out_dist, long long qi)
 {
-    k_resolve<<<1, 256, 0, st>>>(a, q, out_idx, out_dist, qi);
+    __shared__ bool s_last;
+    const int tid = threadIdx.x, l = tid & 15, lane = tid & 63;
+    const uint32_t count = min(A.qs->n_surv, A.surv_cap);
+    const uint32_t grp = (blockIdx.x * 256u + tid) >> 4;
+    const uint32_t ngrp = gridDim.x * 16u;
+    const int nv = A.n >> 2;
+    const float4* q4 = reinterpret_cast<const float4*>(q);
+    uint32_t refined = 0, abandoned = 0;
+    bool wrote = false;
+    // More survivors than lane groups: every group first computes the distance of the survivor
+    // with the smallest bound (usually the answer), so its own threshold starts there instead of
+    // waiting for other groups' atomicMin; group 0 also publishes it.
+    float local_best = __builtin_inff();
+    if (count > ngrp) {
+        const unsigned long long hk = A.qs->head_key;
+        if (hk != ~0ull) {
+            const uint32_t hrow = (uint32_t)(hk & 0xFFFFFFFFu);
+            const float4* h4 = reinterpret_cast<const float4*>(A.X + (long long)hrow * A.n);
+            float part = 0.f;
+            for (int v = l; v < nv; v += 16) part += sqdiff4(h4[v], q4[v]);
+            local_best = group16_sum(part);
+            if (grp == 0 && l == 0) {
+                const unsigned long long mine = pack_key(local_best, hrow);
+                const unsigned long long old = atomicMin(&A.qs->bsf_key, mine);
+                if (mine < old) atomicAdd(&A.qs->n_bsf_upd, 1u);
+                const unsigned long long now = mine < old ? mine : old;
+                if ((double)local_best <= (double)key_dist(now) * (1.0 + A.mg.band_rel) + 1e-25) {
+                    const uint32_t pos = atomicAdd(&A.qs->n_done, 1u);
+                    if (pos < A.done_cap) A.done[pos] = make_uint2(hrow, __float_as_uint(local_best));
+                    wrote = true;
+                }
+            }
+        }
+    }
+    for (uint32_t c = grp; c < count; c += ngrp) {
+        const uint2 e = A.surv[c];
+        const float lb = __uint_as_float(e.y);
+        unsigned long long key = 0;
+        if (l == 0) key = load_key(&A.qs->bsf_key);
+        key = __shfl(key, lane & ~15);
+        float thr = prune_threshold(fminf(key_dist(key), local_best), A.mg.prune_rel);
+        if (lb > thr) continue;  // re-check against the current best (uniform in the group)
+        ++refined;
+        const float4* r4 = reinterpret_cast<const float4*>(A.X + (long long)e.x * A.n);
+        float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
+        if (l < nv) { a = r4[l]; b = q4[l]; }
+        float acc = 0.f;
+        bool ab = false;
+        for (int v0 = 0; v0 < nv; v0 += 16) {
+            const int vn = v0 + 16 + l;
+            float4 an = make_float4(0.f, 0.f, 0.f, 0.f), bn = an;
+            if (vn < nv) { an = r4[vn]; bn = q4[vn]; }   // next step in flight
+            const float part = (v0 + l < nv) ? sqdiff4(a, b) : 0.f;
+            acc += group16_sum(part);
+            if (acc > thr) { ab = true; break; }
+            a = an;
+            b = bn;
+            if (l == 0) key = load_key(&A.qs->bsf_key);
+            key = __shfl(key, lane & ~15);
+            thr = prune_threshold(fminf(key_dist(key), local_best), A.mg.prune_rel);
+        }
+        if (ab) { ++abandoned; continue; }
+        if (l == 0) {
+            const unsigned long long mine = pack_key(acc, e.x);
+            const unsigned long long old = atomicMin(&A.qs->bsf_key, mine);
+            if (mine < old) atomicAdd(&A.qs->n_bsf_upd, 1u);
+            const unsigned long long now = mine < old ? mine : old;
+            if ((double)acc <= (double)key_dist(now) * (1.0 + A.mg.band_rel) + 1e-25) {
+                const uint32_t pos = atomicAdd(&A.qs->n_done, 1u);
+                if (pos < A.done_cap) A.done[pos] = make_uint2(e.x, __float_as_uint(acc));
+                wrote = true;
+            }
+        }
+    }
+    uint32_t r = (l == 0) ? refined : 0u, ab = (l == 0) ? abandoned : 0u;
+    for (int off = 32; off > 0; off >>= 1) {
+        r += __shfl_xor(r, off);
+        ab += __shfl_xor(ab, off);
+    }
+    if (lane == 0) {
+        if (r) atomicAdd(&A.qs->n_refined, r);
+        if (ab) atomicAdd(&A.qs->n_abandon, ab);
+    }
+    // The last block to finish resolves. Only blocks that stored candidates need a release
+    // fence (a device-scope fence writes back this XCD's L2, which is costly when every block
+    // does it); the counters above are device-scope atomics.
+    __shared__ int s_wrote;
+    if (tid == 0) s_wrote = 0;
+    __syncthreads();
+    if (wrote) s_wrote = 1;
+    __syncthreads();
+    if (s_wrote) __threadfence();
+    if (tid == 0) s_last = atomicAdd(&A.qs->blocks_done, 1u) == gridDim.x - 1;
+    __syncthreads();
+    if (!s_last) return;
+    __threadfence();
+    resolve_block(A, q, out_idx, out_dist, qi);
+}
+
+hipError_t launch_refine_resolve(const QueryArgs& a, const float* q, long long* out_idx, double* out_dist,
+                                 long long qi, hipStream_t st)
+{
+    k_refine_resolve<<<kRefineBlocks, 256, 0, st>>>(a, q, out_idx, out_dist, qi);
     return hipGetLastError();
 }
 

@@ -30,7 +30,7 @@ def test_library_exports_every_declared_symbol():
 
 def test_default_config_and_workspace_size():
     cfg = paris.default_config()
-    assert (cfg.segments, cfg.card_bits, cfg.leaf_mode, cfg.n_leaves, cfg.seed_cap) == (16, 8, 0, 4096, 2048)
+    assert (cfg.segments, cfg.card_bits, cfg.leaf_mode, cfg.n_leaves, cfg.seed_cap) == (16, 8, 0, 4096, 16384)
     small = paris.workspace_size(1000, 256, cfg)
     big = paris.workspace_size(10_000_000, 256, cfg)
     assert big > 10_000_000 * 44 and small > 1000 * 44

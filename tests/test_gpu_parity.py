@@ -112,7 +112,7 @@ def test_query_summaries_tables_and_window(small):
         assert np.array_equal(np.array(info["paa"]).view(np.uint64), qs.paa.view(np.uint64))
         assert np.array_equal(np.array(info["sym"], np.uint8), qs.sym)
         assert info["root"] == qs.root and info["k64"] == qs.k64
-        a, b = seed_window(qs, ks, 16, "root16", seed_cap=2048, off=off)
+        a, b = seed_window(qs, ks, 16, "root16", seed_cap=16384, off=off)
         assert (info["win_lo"], info["win_hi"]) == (a, b)
         t8 = info["table"].cpu().numpy().astype(np.float64)
         ref = lb_table(qs.paa, 16)
@@ -203,13 +203,20 @@ def test_seed_disabled_and_equal_count_give_same_answers(small):
 def test_seed_is_a_true_distance_in_its_window(small):
     idx = small["index"]
     perm, _ = sorted_order(small["sym"])
+    from oracle import ed_sq, seed_candidates
     for m in range(0, 100, 11):
+        q = small["Q"][m]
         i, d, st = idx.query(small["Qd"][m], with_stats=True)
         members = perm[st["seed_lo"]:st["seed_hi"]]
         assert st["seed_index"] in set(members.tolist())
-        ref = math.sqrt(float(np.min(__import__("oracle").ed_sq(small["Q"][m], small["X"][members]))))
+        own = math.sqrt(float(ed_sq(q, small["X"][st["seed_index"]])))
+        assert abs(st["seed_dist"] - own) <= 1e-5 * own + 1e-6       # a true distance
+        window_min = math.sqrt(float(np.min(ed_sq(q, small["X"][members]))))
+        assert st["seed_dist"] >= window_min * (1 - 1e-5) and st["seed_dist"] >= d * (1 - 1e-5)
+        # the oracle's reading of the seed (smallest bound per 512-run) reaches the same distance
+        cand = seed_candidates(query_summary(q), members, small["sym"], 16)
+        ref = math.sqrt(float(np.min(ed_sq(q, small["X"][cand]))))
         assert abs(st["seed_dist"] - ref) <= 1e-4 * ref + 1e-6
-        assert st["seed_dist"] >= d * (1 - 1e-4)
 
 
 def test_ties_duplicates_and_degenerate_sizes(oracle_native):
