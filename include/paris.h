@@ -144,13 +144,41 @@ paris_status paris_query_exact(paris_index *idx, const float *query_dev, int64_t
  * Exact 1-NN of n_queries queries.
  *   queries_dev   float32 [n_queries][length] on the device, finite.
  *   nn_index_dev  int64 [n_queries] device out;  nn_dist_dev  float64 [n_queries] device out.
- *   stats         optional host out, summed over the batch (may be NULL; forces a sync).
- * Asynchronous on hip_stream when stats is NULL: outputs are valid after the stream is
- * synchronised; a NaN/Inf query then yields index -1 and distance NaN for that query.
+ *   stats         optional host out, summed over the batch (may be NULL).
+ * With a batch workspace attached (paris_batch_attach) and length <= 256, the queries go in
+ * chunks of max_batch through the batched pipeline (one HIP graph per chunk): per-query seeds,
+ * the bfloat16 MFMA distance screen with a certified margin over every (query, series) pair,
+ * float32 re-scoring of its survivors and the float64 resolve; each chunk is synchronised
+ * once, and a query whose candidate or resolve buffers overflow is answered by the per-query
+ * path. Without one, the queries run one after another through the per-query kernels and the
+ * call is asynchronous unless stats is requested. A NaN/Inf query yields index -1 and distance
+ * NaN. stats for the batched pipeline: lb_survivors = refined = screen survivors,
+ * resolved = queries answered on the per-query fallback path.
  */
 paris_status paris_query_batch(paris_index *idx, const float *queries_dev, int64_t n_queries,
                                int64_t *nn_index_dev, double *nn_dist_dev, paris_stats *stats,
                                void *hip_stream);
+
+/*
+ * Batched pipeline resources (the batched pattern of the paper's worker pools: many queries,
+ * one launch). paris_batch_workspace_size gives the bytes for chunks of up to max_batch queries
+ * (1 .. 65536): a bfloat16 copy of the collection [N][roundup(length, 32)], its norms, the
+ * query buffers, per-query states and a candidate list of 4096 * max_batch entries.
+ * paris_batch_attach borrows that device memory (256-byte aligned) for the life of the handle
+ * (or until the next attach), converts the collection, times the screen's tile shapes and
+ * captures the pipeline into a HIP graph. Synchronous on hip_stream.
+ */
+paris_status paris_batch_workspace_size(const paris_index *idx, int32_t max_batch, size_t *bytes);
+paris_status paris_batch_attach(paris_index *idx, void *workspace_dev, size_t workspace_bytes,
+                                int32_t max_batch, void *hip_stream);
+
+/*
+ * The screen's float32 dot products of bfloat16 query and series rows, for inspection and
+ * tests: dots_dev float32 [n_queries][n_series] (device out) receives q~ . x~ as accumulated
+ * by the MFMA screen kernel. Needs an attached batch workspace; n_queries <= max_batch.
+ */
+paris_status paris_screen_dots(paris_index *idx, const float *queries_dev, int32_t n_queries,
+                               float *dots_dev, void *hip_stream);
 
 /*
  * Query summaries as the device computes them (Section 2.2 on the query; Section 3.3.1 table):

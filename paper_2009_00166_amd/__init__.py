@@ -178,6 +178,30 @@ class Index:
         k = min(int(cnt.value), cap)
         return I[:k], B[:k], int(cnt.value), st
 
+    # -- batched pipeline -----------------------------------------------------------------
+    def attach_batch(self, max_batch: int = 4096, stream=None) -> int:
+        """Allocate (torch) and attach the batched-pipeline workspace; returns its bytes."""
+        torch = _torch()
+        lib = load_library()
+        nbytes = ctypes.c_size_t(0)
+        check(lib.paris_batch_workspace_size(self._h, int(max_batch), ctypes.byref(nbytes)),
+              "paris_batch_workspace_size")
+        ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.series.device)
+        check(lib.paris_batch_attach(self._h, ctypes.c_void_p(ws.data_ptr()), int(nbytes.value),
+                                     int(max_batch), _stream_ptr(stream)), "paris_batch_attach")
+        self.batch_workspace = ws
+        self.max_batch = int(max_batch)
+        return int(nbytes.value)
+
+    def screen_dots(self, Q, stream=None):
+        """float32 [M, N] dot products of the bfloat16 rows, as accumulated by the screen."""
+        torch = _torch()
+        qp = _dev_ptr(Q, torch.float32, 2, "queries")
+        out = torch.empty((Q.shape[0], self.n_series), dtype=torch.float32, device=Q.device)
+        check(load_library().paris_screen_dots(self._h, qp, int(Q.shape[0]), ctypes.c_void_p(out.data_ptr()),
+                                               _stream_ptr(stream)), "paris_screen_dots")
+        return out
+
     def set_timing(self, enable: bool = True) -> None:
         """Enable per-phase HIP-event timing of query() (and zero the totals)."""
         check(load_library().paris_set_timing(self._h, 1 if enable else 0), "paris_set_timing")

@@ -59,6 +59,9 @@ SIGNATURES = [
     ("paris_query_batch", ctypes.c_int, [_P, _P, _I64, _P, _P, ctypes.POINTER(ParisStats), _P]),
     ("paris_query_info_get", ctypes.c_int, [_P, _P, ctypes.POINTER(ParisQueryInfo), _P, _P, _P]),
     ("paris_lb_scan", ctypes.c_int, [_P, _P, _F32, _P, _P, _I64, ctypes.POINTER(ctypes.c_int64), _P]),
+    ("paris_batch_workspace_size", ctypes.c_int, [_P, _I32, ctypes.POINTER(ctypes.c_size_t)]),
+    ("paris_batch_attach", ctypes.c_int, [_P, _P, ctypes.c_size_t, _I32, _P]),
+    ("paris_screen_dots", ctypes.c_int, [_P, _P, _I32, _P, _P]),
     ("paris_set_timing", ctypes.c_int, [_P, _I32]),
     ("paris_get_timing", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     ("paris_free", ctypes.c_int, [_P]),

@@ -91,6 +91,21 @@ Margins margins_for_length(int n)
     return m;
 }
 
+// Relative margin c of the bfloat16 screen, |d~^2 - d^2| <= c (qn + xn): bfloat16 rounding of
+// both operands (2 u_b + u_b^2, u_b = 2^-8), the MFMA's float32 accumulation over np + 16 terms
+// (unit roundoff taken as 2^-23 so truncating accumulation is covered), the float32 norms
+// (gamma_n), and the float32 evaluation of the folded test; inflated by 5%.
+float screen_margin(int n, int np)
+{
+    const double ub = std::ldexp(1.0, -8);
+    const double u23 = std::ldexp(1.0, -23);
+    const double u24 = std::ldexp(1.0, -24);
+    auto gam = [](int k, double u) { return k * u / (1.0 - k * u); };
+    const double c = (2.0 * ub + ub * ub) + 2.0 * gam(np + 16, u23) * (1.0 + ub) * (1.0 + ub) +
+                     2.0 * gam(n, u24) + 16.0 * u24;
+    return (float)(1.05 * c + 32.0 * u24);
+}
+
 paris_status device_ok()
 {
     int count = 0;
@@ -119,6 +134,24 @@ struct paris_index {
     hipEvent_t ev[4];
     double phase_ms[3];
     long long timed_queries;
+    // batched path (paris_batch_attach)
+    uint8_t* bws;
+    size_t bws_bytes;
+    int max_batch;
+    int np;
+    bool screen_ok;
+    struct {
+        size_t hdr, xb, xn, qin, qb, bq, cand, oidx, odist, fb, total;
+        uint32_t cand_cap;
+    } bp;
+    ScreenShape screen;
+    float c_screen;
+    double seed_rel;
+    hipGraph_t graph;
+    hipGraphExec_t graph_exec;
+    BatchHdr* host_hdr;   // pinned read-back of the batch header
+    uint32_t* host_fb;    // pinned read-back of the fallback list
+    long long batch_candidates;
 };
 
 namespace {
@@ -237,9 +270,10 @@ paris_status tune_scan(paris_index* h, hipStream_t st)
     HIP_TRY(hipEventCreate(&e1));
     float best = 1e30f;
     ScanShape pick = cands[3];
+    constexpr int kReps = 9;
     for (const ScanShape& s : cands) {
-        float t[3];
-        for (int r = 0; r < 4; ++r) {
+        float t[kReps];
+        for (int r = 0; r <= kReps; ++r) {
             HIP_TRY(hipEventRecord(e0, st));
             HIP_TRY(launch_lbscan(a, 0.f, s, st));
             HIP_TRY(hipEventRecord(e1, st));
@@ -248,9 +282,9 @@ paris_status tune_scan(paris_index* h, hipStream_t st)
             HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
             if (r > 0) t[r - 1] = ms;  // first run warms up
         }
-        const float lo = std::fmin(t[0], std::fmin(t[1], t[2]));
-        const float hi = std::fmax(t[0], std::fmax(t[1], t[2]));
-        const float med = t[0] + t[1] + t[2] - lo - hi;
+        for (int i = 1; i < kReps; ++i)  // insertion sort for the median
+            for (int j = i; j > 0 && t[j] < t[j - 1]; --j) { const float x = t[j]; t[j] = t[j - 1]; t[j - 1] = x; }
+        const float med = t[kReps / 2];
         if (med < best) { best = med; pick = s; }
     }
     (void)hipEventDestroy(e0);
@@ -261,9 +295,271 @@ paris_status tune_scan(paris_index* h, hipStream_t st)
     return PARIS_OK;
 }
 
+// ---- batched path ------------------------------------------------------------------------
+void make_batch_plan(paris_index* h, int max_batch)
+{
+    size_t off = 0;
+    auto take = [&off](size_t bytes) { const size_t at = off; off = align_up(off + bytes); return at; };
+    const size_t N = (size_t)h->N, M = (size_t)max_batch;
+    h->bp.hdr = take(256);
+    h->bp.xb = take(N * h->np * 2);
+    h->bp.xn = take(N * 4);
+    h->bp.qin = take(M * h->n * 4);
+    h->bp.qb = take(M * h->np * 2);
+    h->bp.bq = take(M * sizeof(BQuery));
+    const size_t cap = M * 4096 < (size_t)0xFFFFFFF0u ? M * 4096 : (size_t)0xFFFFFFF0u;
+    h->bp.cand_cap = (uint32_t)cap;
+    h->bp.cand = take(cap * 8);
+    h->bp.oidx = take(M * 8);
+    h->bp.odist = take(M * 8);
+    h->bp.fb = take(M * 4);
+    h->bp.total = off;
+}
+
+bool batch_screen_usable(const paris_index* h)
+{
+    return h->bws != nullptr && h->screen_ok && (h->cfg.seed_cap > 0 || h->cfg.leaf_mode == PARIS_LEAF_EQUAL_COUNT);
+}
+
+BatchHdr* bhdr(paris_index* h) { return reinterpret_cast<BatchHdr*>(h->bws + h->bp.hdr); }
+BQuery* bqs(paris_index* h) { return reinterpret_cast<BQuery*>(h->bws + h->bp.bq); }
+
+ScreenArgs screen_args(paris_index* h, int m, float* dump)
+{
+    ScreenArgs s;
+    s.Xb = reinterpret_cast<const uint16_t*>(h->bws + h->bp.xb);
+    s.xn = reinterpret_cast<const float*>(h->bws + h->bp.xn);
+    s.N = h->N;
+    s.Qb = reinterpret_cast<const uint16_t*>(h->bws + h->bp.qb);
+    s.bq = bqs(h);
+    s.M = m;
+    s.cand = reinterpret_cast<uint2*>(h->bws + h->bp.cand);
+    s.cand_cap = h->bp.cand_cap;
+    s.hdr = bhdr(h);
+    s.c_screen = h->c_screen;
+    s.dump = dump;
+    return s;
+}
+
+RescoreArgs rescore_args(paris_index* h, int m)
+{
+    RescoreArgs r;
+    r.X = h->X;
+    r.Q = reinterpret_cast<const float*>(h->bws + h->bp.qin);
+    r.n = h->n;
+    r.M = m;
+    r.bq = bqs(h);
+    r.cand = reinterpret_cast<const uint2*>(h->bws + h->bp.cand);
+    r.cand_cap = h->bp.cand_cap;
+    r.hdr = bhdr(h);
+    r.prune_rel = h->mg.prune_rel;
+    r.band_rel = h->mg.band_rel;
+    r.fallback = reinterpret_cast<uint32_t*>(h->bws + h->bp.fb);
+    return r;
+}
+
+// The batch pipeline on queries already copied to the internal query buffer: reset, seeds,
+// screen thresholds, the MFMA screen, float32 re-score, float64 resolve.
+paris_status launch_batch_pipeline(paris_index* h, int m, hipStream_t st)
+{
+    const QueryArgs a = args_for(h);
+    SeedBatch sb;
+    sb.Q = reinterpret_cast<const float*>(h->bws + h->bp.qin);
+    sb.bq = bqs(h);
+    sb.qb = reinterpret_cast<uint16_t*>(h->bws + h->bp.qb);
+    sb.np = h->np;
+    HIP_TRY(launch_batch_init(bqs(h), m, bhdr(h), st));
+    HIP_TRY(launch_prepare_seed_batch(a, sb, m, st));
+    HIP_TRY(launch_batch_thresholds(bqs(h), m, h->c_screen, h->seed_rel, st));
+    HIP_TRY(launch_screen(screen_args(h, m, nullptr), h->np, h->screen, st));
+    const RescoreArgs r = rescore_args(h, m);
+    HIP_TRY(launch_rescore(r, st));
+    HIP_TRY(launch_batch_resolve(r, reinterpret_cast<long long*>(h->bws + h->bp.oidx),
+                                 reinterpret_cast<double*>(h->bws + h->bp.odist), st));
+    return PARIS_OK;
+}
+
+// Capture the full-size pipeline once into a HIP graph (on a private stream).
+paris_status capture_batch_graph(paris_index* h)
+{
+    hipStream_t cs = nullptr;
+    HIP_TRY(hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    paris_status s = PARIS_OK;
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) s = PARIS_EHIP;
+    if (s == PARIS_OK) {
+        paris_status ls = launch_batch_pipeline(h, h->max_batch, cs);
+        hipGraph_t g = nullptr;
+        if (hipStreamEndCapture(cs, &g) != hipSuccess || ls != PARIS_OK) s = PARIS_EHIP;
+        if (s == PARIS_OK && hipGraphInstantiate(&h->graph_exec, g, nullptr, nullptr, 0) != hipSuccess)
+            s = PARIS_EHIP;
+        if (s == PARIS_OK) h->graph = g;
+        else if (g) (void)hipGraphDestroy(g);
+    }
+    (void)hipStreamDestroy(cs);
+    return s;
+}
+
+paris_status run_batch_chunk(paris_index* h, const float* queries, long long q0, int m, long long* out_idx,
+                             double* out_dist, hipStream_t st, long long* cands, long long* fallbacks)
+{
+    const size_t qbytes = (size_t)m * h->n * 4;
+    HIP_TRY(hipMemcpyAsync(h->bws + h->bp.qin, queries + q0 * h->n, qbytes, hipMemcpyDeviceToDevice, st));
+    if (m == h->max_batch && h->graph_exec) {
+        HIP_TRY(hipGraphLaunch(h->graph_exec, st));
+    } else {
+        paris_status s = launch_batch_pipeline(h, m, st);
+        if (s != PARIS_OK) return s;
+    }
+    HIP_TRY(hipMemcpyAsync(out_idx + q0, h->bws + h->bp.oidx, (size_t)m * 8, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(out_dist + q0, h->bws + h->bp.odist, (size_t)m * 8, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(hipMemcpyAsync(h->host_hdr, bhdr(h), sizeof(BatchHdr), hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    const BatchHdr hd = *h->host_hdr;
+    *cands += hd.n_cand;
+    if (hd.n_fallback) {
+        // queries whose screen candidates or resolve band overflowed: the per-query path
+        HIP_TRY(hipMemcpyAsync(h->host_fb, h->bws + h->bp.fb, (size_t)hd.n_fallback * 4, hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        for (uint32_t k = 0; k < hd.n_fallback; ++k) {
+            const long long qi = q0 + h->host_fb[k];
+            paris_status s = run_query(h, queries + qi * h->n, st, out_idx, out_dist, qi, false);
+            if (s != PARIS_OK) return s;
+        }
+        *fallbacks += hd.n_fallback;
+    }
+    return PARIS_OK;
+}
+
+// Screen autotuner: the query-tile height (32 or 64 rows) with every threshold at +inf (no
+// candidate), timed over full-size batches; the median of three runs decides.
+paris_status tune_screen(paris_index* h, hipStream_t st)
+{
+    const char* env = std::getenv("PARIS_SCREEN_QT");
+    int cus = 256, dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        cus = 256;
+    h->screen.grid = cus;
+    if (env && (std::atoi(env) == 32 || std::atoi(env) == 64)) {
+        h->screen.qt = std::atoi(env);
+        return PARIS_OK;
+    }
+    const int m = h->max_batch;
+    HIP_TRY(hipMemsetAsync(h->bws + h->bp.qb, 0, (size_t)m * h->np * 2, st));
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    float best = 1e30f;
+    int pick = 64;
+    for (int qt : {32, 64}) {
+        ScreenShape sh{qt, cus};
+        float t[3];
+        for (int r = 0; r < 4; ++r) {
+            HIP_TRY(launch_batch_init(bqs(h), m, bhdr(h), st));  // thresholds +inf
+            HIP_TRY(hipEventRecord(e0, st));
+            HIP_TRY(launch_screen(screen_args(h, m, nullptr), h->np, sh, st));
+            HIP_TRY(hipEventRecord(e1, st));
+            HIP_TRY(hipEventSynchronize(e1));
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, e0, e1));
+            if (r > 0) t[r - 1] = ms;
+        }
+        const float lo = std::fmin(t[0], std::fmin(t[1], t[2])), hi = std::fmax(t[0], std::fmax(t[1], t[2]));
+        const float med = t[0] + t[1] + t[2] - lo - hi;
+        if (med < best) { best = med; pick = qt; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->screen.qt = pick;
+    return PARIS_OK;
+}
+
+void release_batch(paris_index* h)
+{
+    if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+    if (h->graph) (void)hipGraphDestroy(h->graph);
+    if (h->host_hdr) (void)hipHostFree(h->host_hdr);
+    if (h->host_fb) (void)hipHostFree(h->host_fb);
+    h->graph_exec = nullptr;
+    h->graph = nullptr;
+    h->host_hdr = nullptr;
+    h->host_fb = nullptr;
+    h->bws = nullptr;
+    h->screen_ok = false;
+}
+
 }  // namespace
 
 extern "C" {
+
+paris_status paris_batch_workspace_size(const paris_index* h, int32_t max_batch, size_t* bytes)
+{
+    if (!handle_ok(h)) return PARIS_ESTATE;
+    if (!bytes || max_batch < 1 || max_batch > 65536) return PARIS_EINVAL;
+    paris_index tmp = *h;
+    make_batch_plan(&tmp, max_batch);
+    *bytes = tmp.bp.total;
+    return PARIS_OK;
+}
+
+paris_status paris_batch_attach(paris_index* h, void* workspace_dev, size_t workspace_bytes, int32_t max_batch,
+                                void* hip_stream)
+{
+    if (!handle_ok(h)) return PARIS_ESTATE;
+    if (!workspace_dev || max_batch < 1 || max_batch > 65536 ||
+        reinterpret_cast<uintptr_t>(workspace_dev) % kAlign != 0)
+        return PARIS_EINVAL;
+    paris_index tmp = *h;
+    make_batch_plan(&tmp, max_batch);
+    if (workspace_bytes < tmp.bp.total) return PARIS_ENOMEM;
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    release_batch(h);
+    h->bp = tmp.bp;
+    h->bws = static_cast<uint8_t*>(workspace_dev);
+    h->bws_bytes = workspace_bytes;
+    h->max_batch = max_batch;
+    if (hipHostMalloc(reinterpret_cast<void**>(&h->host_hdr), sizeof(BatchHdr), hipHostMallocDefault) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&h->host_fb), (size_t)max_batch * 4, hipHostMallocDefault) != hipSuccess) {
+        release_batch(h);
+        return PARIS_EHIP;
+    }
+    // the screen keeps a query tile's k-steps in registers: lengths up to 256
+    h->screen_ok = h->np <= 256;
+    if (!h->screen_ok) return PARIS_OK;  // batches then use the per-query path
+    paris_status s = PARIS_OK;
+    if (launch_to_bf16(h->X, h->N, h->n, h->np, reinterpret_cast<uint16_t*>(h->bws + h->bp.xb),
+                       reinterpret_cast<float*>(h->bws + h->bp.xn), st) != hipSuccess)
+        s = PARIS_EHIP;
+    if (s == PARIS_OK) s = tune_screen(h, st);
+    if (s == PARIS_OK && hipStreamSynchronize(st) != hipSuccess) s = PARIS_EHIP;
+    if (s == PARIS_OK && std::getenv("PARIS_NO_GRAPH") == nullptr) s = capture_batch_graph(h);
+    if (s != PARIS_OK) release_batch(h);
+    return s;
+}
+
+paris_status paris_screen_dots(paris_index* h, const float* queries_dev, int32_t n_queries, float* dots_dev,
+                               void* hip_stream)
+{
+    if (!handle_ok(h)) return PARIS_ESTATE;
+    if (!h->bws || !h->screen_ok) return PARIS_ESTATE;
+    if (!queries_dev || !dots_dev || n_queries < 1 || n_queries > h->max_batch ||
+        reinterpret_cast<uintptr_t>(queries_dev) % 16 != 0)
+        return PARIS_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    const int m = n_queries;
+    const QueryArgs a = args_for(h);
+    SeedBatch sb;
+    sb.Q = reinterpret_cast<const float*>(h->bws + h->bp.qin);
+    sb.bq = bqs(h);
+    sb.qb = reinterpret_cast<uint16_t*>(h->bws + h->bp.qb);
+    sb.np = h->np;
+    HIP_TRY(hipMemcpyAsync(h->bws + h->bp.qin, queries_dev, (size_t)m * h->n * 4, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(launch_batch_init(bqs(h), m, bhdr(h), st));
+    HIP_TRY(launch_prepare_seed_batch(a, sb, m, st));  // bfloat16 queries and norms (thresholds stay +inf)
+    HIP_TRY(launch_screen(screen_args(h, m, dots_dev), h->np, h->screen, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return PARIS_OK;
+}
 
 paris_status paris_default_config(paris_config* cfg)
 {
@@ -336,6 +632,21 @@ paris_status paris_build(const float* series_dev, int64_t n_series, int32_t leng
     h->host_qs = nullptr;
     h->host_res = nullptr;
     h->host_res_dev = nullptr;
+    h->bws = nullptr;
+    h->bws_bytes = 0;
+    h->max_batch = 0;
+    h->np = (length + 31) / 32 * 32;
+    h->screen_ok = false;
+    std::memset(&h->bp, 0, sizeof(h->bp));
+    h->screen = ScreenShape{64, 0};
+    h->c_screen = screen_margin(length, h->np);
+    // the seed series' exact squared distance is at most d32 (1 + g) / (1 - g) < d32 (1 + 3 g)
+    h->seed_rel = 3.0 * gamma_k(length + 2) + std::ldexp(1.0, -30);
+    h->graph = nullptr;
+    h->graph_exec = nullptr;
+    h->host_hdr = nullptr;
+    h->host_fb = nullptr;
+    h->batch_candidates = 0;
     if (hipHostMalloc(reinterpret_cast<void**>(&h->host_qs), sizeof(QState), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&h->host_res), sizeof(QResult), hipHostMallocMapped) != hipSuccess ||
         hipHostGetDevicePointer(reinterpret_cast<void**>(&h->host_res_dev), h->host_res, 0) != hipSuccess) {
@@ -417,6 +728,25 @@ paris_status paris_query_batch(paris_index* h, const float* queries_dev, int64_t
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     paris_stats agg;
     std::memset(&agg, 0, sizeof(agg));
+    if (batch_screen_usable(h)) {
+        long long cands = 0, fallbacks = 0;
+        for (long long q0 = 0; q0 < n_queries; q0 += h->max_batch) {
+            const int m = (int)((n_queries - q0) < h->max_batch ? (n_queries - q0) : h->max_batch);
+            paris_status s = run_batch_chunk(h, queries_dev, q0, m, reinterpret_cast<long long*>(nn_index_dev),
+                                             nn_dist_dev, st, &cands, &fallbacks);
+            if (s != PARIS_OK) return s;
+        }
+        h->batch_candidates += cands;
+        if (stats) {
+            agg.lb_survivors = cands;
+            agg.refined = cands;
+            agg.resolved = fallbacks;
+            agg.seed_index = -1;
+            agg.seed_dist = INFINITY;
+            *stats = agg;
+        }
+        return PARIS_OK;
+    }
     for (long long i = 0; i < n_queries; ++i) {
         const float* q = queries_dev + i * (long long)h->n;
         paris_status s = run_query(h, q, st, reinterpret_cast<long long*>(nn_index_dev), nn_dist_dev, i, false);
@@ -535,6 +865,7 @@ paris_status paris_free(paris_index* h)
         if (g_live.erase(h) == 0) return PARIS_ESTATE;
     }
     h->magic = 0;
+    release_batch(h);
     if (h->host_qs) (void)hipHostFree(h->host_qs);
     if (h->host_res) (void)hipHostFree(h->host_res);
     for (int k = 0; k < 4; ++k)

@@ -1,0 +1,423 @@
+// Batched exact 1-NN (many queries per launch): per-query lower-bound-guided seeds, a dense
+// bfloat16 MFMA screen of every (query, series) pair with a certified error margin, float32
+// re-scoring of the screen's survivors with early abandoning, and the float64 resolve.
+//
+// Screen. The squared distance is ||q||^2 + ||x||^2 - 2 q.x; q.x over all pairs is a dense
+// contraction (queries x dimensions x series) computed with v_mfma_f32_16x16x32_bf16 on
+// round-to-nearest bfloat16 copies of q and x, float32 accumulation. With u_b = 2^-8 the
+// bfloat16 products are within (2 u_b + u_b^2) sum_j |q_j x_j| <= (2 u_b + u_b^2)(qn + xn)/2 of
+// q.x; the float32 accumulation and the float32 norms add gamma-terms of the same form. So
+// |d~^2 - d^2| <= E = c (qn + xn) with c set on the host (screen_margin). A series is kept for
+// query q iff d~^2 - E <= U_q, where U_q is an upper bound on the nearest squared distance (the
+// seed's distance, rounded up). The nearest neighbour and every series tied with it always pass.
+// The test is folded into per-row and per-column constants: keep iff
+//     dot >= a_q + b_x,  a_q = ((1 - c) qn - U_q) / 2,  b_x = (1 - c) xn / 2
+// (both rounded down, c inflated for the float32 evaluation of the test itself).
+#include "paris_internal.h"
+
+namespace paris {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ uint16_t to_bf16(float f)
+{
+    const uint32_t b = __float_as_uint(f);
+    return (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+}
+
+__device__ __forceinline__ float key_dist_b(unsigned long long k) { return __uint_as_float((uint32_t)(k >> 32)); }
+
+__device__ __forceinline__ unsigned long long pack_key_b(float d2, uint32_t idx)
+{
+    return ((unsigned long long)__float_as_uint(d2) << 32) | idx;
+}
+
+// ------------------------------------------------------------------------------------------
+// Collection -> zero-padded bfloat16 rows [N][np] and float32 squared norms (one wave per row).
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_to_bf16(const float* __restrict__ X, long long N, int n, int np,
+                                                 uint16_t* __restrict__ Xb, float* __restrict__ xn)
+{
+    const int lane = threadIdx.x & 63;
+    const long long wave = ((long long)blockIdx.x * 256 + threadIdx.x) >> 6;
+    const long long nw = (long long)gridDim.x * 4;
+    for (long long i = wave; i < N; i += nw) {
+        const float* row = X + i * n;
+        uint16_t* out = Xb + i * np;
+        float sq = 0.f;
+        for (int j = lane; j < np; j += 64) {
+            const float v = j < n ? row[j] : 0.f;
+            out[j] = to_bf16(v);
+            sq += v * v;
+        }
+        for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off);
+        if (lane == 0) xn[i] = sq;
+    }
+}
+
+hipError_t launch_to_bf16(const float* X, long long N, int n, int np, uint16_t* Xb, float* xn, hipStream_t st)
+{
+    long long blocks = (N + 3) / 4;
+    if (blocks > 65536) blocks = 65536;
+    k_to_bf16<<<(unsigned)blocks, 256, 0, st>>>(X, N, n, np, Xb, xn);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Per-batch reset (a fill kernel, so the sequence can be captured in a graph).
+// ------------------------------------------------------------------------------------------
+__global__ void k_batch_init(BQuery* __restrict__ bq, int M, BatchHdr* __restrict__ hdr)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < M) {
+        BQuery& b = bq[q];
+        b.bsf_key = kBsfInit;
+        b.qn = 0.f;
+        b.a = __builtin_inff();
+        b.n_band = 0;
+        b.err = 0;
+        b.n_cand = 0;
+    }
+    if (q == 0) {
+        hdr->next_item = 0;
+        hdr->n_cand = 0;
+        hdr->n_fallback = 0;
+        hdr->flags = 0;
+    }
+}
+
+// Screen threshold constant of every query from its seed (U_q = seed distance rounded up).
+__global__ void k_batch_thresholds(BQuery* __restrict__ bq, int M, float c_screen, double seed_rel)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= M) return;
+    BQuery& b = bq[q];
+    if (b.err || b.bsf_key == kBsfInit) { b.a = __builtin_inff(); return; }  // nothing to screen
+    const double U = (double)key_dist_b(b.bsf_key) * (1.0 + seed_rel) + 1e-20;
+    const double a = ((1.0 - (double)c_screen) * (double)b.qn - U) * 0.5;
+    b.a = __double2float_rd(a);
+}
+
+// ------------------------------------------------------------------------------------------
+// The screen. Persistent blocks of 4 waves take series tiles of 256 (64 per wave) from an
+// atomic work counter. A wave keeps its 64 series' bfloat16 fragments (np/32 k-steps) in
+// registers for the whole item and streams every query tile (QT queries, double-buffered in
+// LDS, rows padded by 16 bytes so the 16 rows read by a quarter-wave hit distinct banks)
+// through v_mfma_f32_16x16x32_bf16: per k-step QT/16 x 4 MFMAs. Operand layout (16x16x32):
+// lane l holds row/column (l % 16) and the 8 k-elements 8 (l / 16) .. +7 of the k-step, for
+// both A (queries) and B (series); the accumulator of lane l holds rows 4 (l / 16) + r,
+// r = 0..3, of column l % 16. Survivors are rare: a lane ORs its pass tests and only a wave
+// with a pass takes the append path.
+// ------------------------------------------------------------------------------------------
+template <int KS, int QT>
+__global__ __launch_bounds__(256, 1) void k_screen(ScreenArgs S)
+{
+    constexpr int NP = KS * 32;
+    constexpr int RS = NP + 8;          // LDS row stride (bfloat16 elements)
+    constexpr int QS = QT / 16;         // query subtiles per tile
+    constexpr int V8 = NP / 8;          // 16-byte vectors per row
+    constexpr int STAGE = (QT * V8 + 255) / 256;
+    __shared__ __attribute__((aligned(16))) uint16_t qtile[2][QT * RS];
+    __shared__ __attribute__((aligned(16))) float qa[2][QT];
+    __shared__ long long s_item;
+
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    const int col = l & 15, kg = l >> 4;
+    const int M = S.M;
+    const long long N = S.N;
+    const int n_qt = (M + QT - 1) / QT;
+    const long long n_items = (N + 255) / 256;
+
+    auto stage_load = [&](int t, uint4* pre, float& pa) {
+#pragma unroll
+        for (int s = 0; s < STAGE; ++s) {
+            const int e = tid + s * 256;
+            const int row = e / V8, v = e - row * V8;
+            const int q = t * QT + row;
+            pre[s] = (e < QT * V8 && q < M)
+                         ? *reinterpret_cast<const uint4*>(S.Qb + (long long)q * NP + v * 8)
+                         : make_uint4(0, 0, 0, 0);
+        }
+        if (tid < QT) {
+            const int q = t * QT + tid;
+            pa = q < M ? S.bq[q].a : __builtin_inff();
+        }
+    };
+    auto stage_store = [&](int buf, const uint4* pre, float pa) {
+#pragma unroll
+        for (int s = 0; s < STAGE; ++s) {
+            const int e = tid + s * 256;
+            if (e < QT * V8) {
+                const int row = e / V8, v = e - row * V8;
+                *reinterpret_cast<uint4*>(&qtile[buf][row * RS + v * 8]) = pre[s];
+            }
+        }
+        if (tid < QT) qa[buf][tid] = pa;
+    };
+
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) s_item = (long long)atomicAdd(&S.hdr->next_item, 1u);
+        __syncthreads();
+        const long long item = s_item;
+        if (item >= n_items) break;  // uniform: every wave reaches this exit
+        const long long xb0 = item * 256 + w * 64;
+
+        bf16x8 bfr[4][KS];
+        float bx[4];
+#pragma unroll
+        for (int sub = 0; sub < 4; ++sub) {
+            const long long x = xb0 + sub * 16 + col;
+            const bool ok = x < N;
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                if (ok) bfr[sub][ks] = *reinterpret_cast<const bf16x8*>(S.Xb + x * NP + ks * 32 + kg * 8);
+                else bfr[sub][ks] = bf16x8{};
+            }
+            bx[sub] = ok ? __double2float_rd((1.0 - (double)S.c_screen) * (double)S.xn[x] * 0.5)
+                         : __builtin_inff();
+        }
+
+        {
+            uint4 pre[STAGE];
+            float pa = 0.f;
+            stage_load(0, pre, pa);
+            stage_store(0, pre, pa);
+        }
+        __syncthreads();
+
+        for (int t = 0; t < n_qt; ++t) {
+            const int buf = t & 1;
+            uint4 pre[STAGE];
+            float pa = 0.f;
+            const bool more = t + 1 < n_qt;
+            if (more) stage_load(t + 1, pre, pa);  // in flight during the MFMAs
+
+            f32x4 acc[QS][4];
+#pragma unroll
+            for (int qs = 0; qs < QS; ++qs)
+#pragma unroll
+                for (int sub = 0; sub < 4; ++sub) acc[qs][sub] = f32x4{0.f, 0.f, 0.f, 0.f};
+            const uint16_t* tb = qtile[buf];
+#pragma unroll
+            for (int ks = 0; ks < KS; ++ks) {
+                bf16x8 a[QS];
+#pragma unroll
+                for (int qs = 0; qs < QS; ++qs)
+                    a[qs] = *reinterpret_cast<const bf16x8*>(tb + (qs * 16 + col) * RS + ks * 32 + kg * 8);
+#pragma unroll
+                for (int qs = 0; qs < QS; ++qs)
+#pragma unroll
+                    for (int sub = 0; sub < 4; ++sub)
+                        acc[qs][sub] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[qs], bfr[sub][ks], acc[qs][sub],
+                                                                               0, 0, 0);
+            }
+
+            bool hit = false;
+#pragma unroll
+            for (int qs = 0; qs < QS; ++qs) {
+                const f32x4 av = *reinterpret_cast<const f32x4*>(&qa[buf][qs * 16 + kg * 4]);
+#pragma unroll
+                for (int sub = 0; sub < 4; ++sub)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) hit |= (acc[qs][sub][r] - bx[sub]) >= av[r];
+            }
+            if (S.dump) {
+#pragma unroll
+                for (int qs = 0; qs < QS; ++qs)
+#pragma unroll
+                    for (int sub = 0; sub < 4; ++sub)
+#pragma unroll
+                        for (int r = 0; r < 4; ++r) {
+                            const int q = t * QT + qs * 16 + kg * 4 + r;
+                            const long long x = xb0 + sub * 16 + col;
+                            if (q < M && x < N) S.dump[(long long)q * N + x] = acc[qs][sub][r];
+                        }
+            }
+            if (__ballot(hit)) {
+                if (hit) {
+#pragma unroll
+                    for (int qs = 0; qs < QS; ++qs) {
+                        const f32x4 av = *reinterpret_cast<const f32x4*>(&qa[buf][qs * 16 + kg * 4]);
+#pragma unroll
+                        for (int sub = 0; sub < 4; ++sub)
+#pragma unroll
+                            for (int r = 0; r < 4; ++r) {
+                                if ((acc[qs][sub][r] - bx[sub]) >= av[r]) {
+                                    const int q = t * QT + qs * 16 + kg * 4 + r;
+                                    const long long x = xb0 + sub * 16 + col;
+                                    if (q < M && x < N) {
+                                        const uint32_t pos = atomicAdd(&S.hdr->n_cand, 1u);
+                                        if (pos < S.cand_cap) S.cand[pos] = make_uint2((uint32_t)q, (uint32_t)x);
+                                    }
+                                }
+                            }
+                    }
+                }
+            }
+            if (more) stage_store(buf ^ 1, pre, pa);
+            __syncthreads();
+        }
+    }
+}
+
+template <int KS, int QT>
+static hipError_t launch_screen_t(const ScreenArgs& s, int grid, hipStream_t st)
+{
+    k_screen<KS, QT><<<grid, 256, 0, st>>>(s);
+    return hipGetLastError();
+}
+
+hipError_t launch_screen(const ScreenArgs& s, int np, ScreenShape shape, hipStream_t st)
+{
+    const int ks = np / 32;
+    const int grid = shape.grid > 0 ? shape.grid : 512;
+    const bool q64 = shape.qt == 64;
+    switch (ks) {
+    case 1: return q64 ? launch_screen_t<1, 64>(s, grid, st) : launch_screen_t<1, 32>(s, grid, st);
+    case 2: return q64 ? launch_screen_t<2, 64>(s, grid, st) : launch_screen_t<2, 32>(s, grid, st);
+    case 3: return q64 ? launch_screen_t<3, 64>(s, grid, st) : launch_screen_t<3, 32>(s, grid, st);
+    case 4: return q64 ? launch_screen_t<4, 64>(s, grid, st) : launch_screen_t<4, 32>(s, grid, st);
+    case 5: return q64 ? launch_screen_t<5, 64>(s, grid, st) : launch_screen_t<5, 32>(s, grid, st);
+    case 6: return q64 ? launch_screen_t<6, 64>(s, grid, st) : launch_screen_t<6, 32>(s, grid, st);
+    case 7: return q64 ? launch_screen_t<7, 64>(s, grid, st) : launch_screen_t<7, 32>(s, grid, st);
+    case 8: return q64 ? launch_screen_t<8, 64>(s, grid, st) : launch_screen_t<8, 32>(s, grid, st);
+    default: return hipErrorInvalidValue;
+    }
+}
+
+// ------------------------------------------------------------------------------------------
+// Re-score: float32 squared distance of every screen candidate (16 lanes per candidate, 64
+// points per step, early abandoning against the query's best-so-far), atomicMin into the
+// query's key, and the resolve band list.
+// ------------------------------------------------------------------------------------------
+__device__ __forceinline__ float group16_sum_b(float v)
+{
+    v += __shfl_xor(v, 8, 16);
+    v += __shfl_xor(v, 4, 16);
+    v += __shfl_xor(v, 2, 16);
+    v += __shfl_xor(v, 1, 16);
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_rescore(RescoreArgs R)
+{
+    const int tid = threadIdx.x, l = tid & 15, lane = tid & 63;
+    const uint32_t count = min(R.hdr->n_cand, R.cand_cap);
+    const uint32_t grp = (blockIdx.x * 256u + tid) >> 4;
+    const uint32_t ngrp = gridDim.x * 16u;
+    const int n = R.n, nv = n >> 2;
+    for (uint32_t c = grp; c < count; c += ngrp) {
+        const uint2 e = R.cand[c];
+        BQuery& b = R.bq[e.x];
+        unsigned long long key = 0;
+        if (l == 0) key = __hip_atomic_load(&b.bsf_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        key = __shfl(key, lane & ~15);
+        float thr = __double2float_ru((double)key_dist_b(key) * (1.0 + R.prune_rel) + 1e-25);
+        const float4* r4 = reinterpret_cast<const float4*>(R.X + (long long)e.y * n);
+        const float4* q4 = reinterpret_cast<const float4*>(R.Q + (long long)e.x * n);
+        float acc = 0.f;
+        bool ab = false;
+        for (int v0 = 0; v0 < nv; v0 += 16) {
+            const int v = v0 + l;
+            float part = 0.f;
+            if (v < nv) {
+                const float4 a = r4[v], bq = q4[v];
+                const float dx = bq.x - a.x, dy = bq.y - a.y, dz = bq.z - a.z, dw = bq.w - a.w;
+                part = (dx * dx + dy * dy) + (dz * dz + dw * dw);
+            }
+            acc += group16_sum_b(part);
+            if (acc > thr) { ab = true; break; }
+        }
+        if (ab || l != 0) continue;
+        const unsigned long long mine = pack_key_b(acc, e.y);
+        const unsigned long long old = atomicMin(&b.bsf_key, mine);
+        const unsigned long long now = mine < old ? mine : old;
+        if ((double)acc <= (double)key_dist_b(now) * (1.0 + R.band_rel) + 1e-25) {
+            const uint32_t pos = atomicAdd(&b.n_band, 1u);
+            if (pos < kBandCap) b.band[pos] = make_uint2(e.y, __float_as_uint(acc));
+        }
+    }
+}
+
+hipError_t launch_rescore(const RescoreArgs& r, hipStream_t st)
+{
+    k_rescore<<<512, 256, 0, st>>>(r);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Resolve: one wave per query. Every band entry within band_rel of the final float32 best is
+// re-scored in float64 with the fixed operation order (terms in parallel, one lane adds them in
+// ascending j); the smallest (squared distance, index) is written out. A query whose band list
+// overflowed is handed back to the host (fallback list) and answered by the per-query path.
+// ------------------------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_batch_resolve(RescoreArgs R, long long* __restrict__ out_idx,
+                                                       double* __restrict__ out_dist)
+{
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int q = blockIdx.x * 4 + w;
+    if (q >= R.M) return;  // wave-uniform
+    BQuery& b = R.bq[q];
+    const int n = R.n;
+    if (b.err) {
+        if (lane == 0) { out_idx[q] = -1; out_dist[q] = __builtin_nan(""); }
+        return;
+    }
+    if (b.n_band > (uint32_t)kBandCap || R.hdr->n_cand > R.cand_cap) {
+        if (lane == 0) {
+            out_idx[q] = -2;
+            const uint32_t p = atomicAdd(&R.hdr->n_fallback, 1u);
+            R.fallback[p] = (uint32_t)q;
+        }
+        return;
+    }
+    const unsigned long long key = b.bsf_key;
+    const double band = (double)key_dist_b(key) * (1.0 + R.band_rel) + 1e-25;
+    double bd = __builtin_inf();
+    long long bi = -1;
+    const float* qv = R.Q + (long long)q * n;
+    if (lane != 0) return;
+    for (uint32_t e = 0; e < b.n_band; ++e) {
+        const uint2 v = b.band[e];
+        if ((double)__uint_as_float(v.y) > band) continue;
+        const float* x = R.X + (long long)v.x * n;
+        double acc = 0.0;
+#pragma unroll 8
+        for (int j = 0; j < n; ++j) {
+            const double d = (double)qv[j] - (double)x[j];
+            const double t = d * d;
+            acc = acc + t;
+        }
+        if (acc < bd || (acc == bd && (long long)v.x < bi)) { bd = acc; bi = v.x; }
+    }
+    if (bi < 0) {  // no completed candidate (cannot happen with a seed): per-query path
+        out_idx[q] = -2;
+        const uint32_t p = atomicAdd(&R.hdr->n_fallback, 1u);
+        R.fallback[p] = (uint32_t)q;
+    } else {
+        out_idx[q] = bi;
+        out_dist[q] = sqrt(bd);
+    }
+}
+
+hipError_t launch_batch_resolve(const RescoreArgs& r, long long* out_idx, double* out_dist, hipStream_t st)
+{
+    k_batch_resolve<<<(r.M + 3) / 4, 256, 0, st>>>(r, out_idx, out_dist);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_init(BQuery* bq, int M, BatchHdr* hdr, hipStream_t st)
+{
+    k_batch_init<<<(M + 255) / 256, 256, 0, st>>>(bq, M, hdr);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_thresholds(BQuery* bq, int M, float c_screen, double seed_rel, hipStream_t st)
+{
+    k_batch_thresholds<<<(M + 255) / 256, 256, 0, st>>>(bq, M, c_screen, seed_rel);
+    return hipGetLastError();
+}
+
+}  // namespace paris

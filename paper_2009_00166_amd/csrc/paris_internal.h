@@ -95,6 +95,74 @@ struct QueryArgs {
                         // also stored there, so the host needs no copy after synchronising
 };
 
+// ---- batched path ----
+constexpr int kBandCap = 4;        // float64-resolve candidates kept per query in a batch
+
+// Per-query state of a batch (64 bytes).
+struct alignas(64) BQuery {
+    unsigned long long bsf_key;    // (float32 bits of ED^2, index), atomicMin
+    float qn;                      // float32 squared norm of the query
+    float a;                       // screen threshold constant (see k_screen)
+    uint32_t n_band;               // entries appended to band[] (may exceed kBandCap)
+    uint32_t err;                  // kErrNonFinite
+    uint32_t n_cand;               // screen candidates of this query
+    uint32_t pad;
+    uint2 band[kBandCap];          // (index, ED^2 float32 bits) within the resolve band
+};
+
+// Batch-mode arguments of the prepare+seed kernel (bq == nullptr: the plain path).
+struct SeedBatch {
+    const float* Q;       // [M][n] float32 queries
+    BQuery* bq;           // [M]
+    uint16_t* qb;         // [M][np] bfloat16 copies, zero padded
+    int np;               // n rounded up to a multiple of 32
+};
+
+struct BatchHdr {
+    uint32_t next_item;    // screen work counter (series tiles of 256)
+    uint32_t n_cand;       // screen candidates appended (may exceed the capacity)
+    uint32_t n_fallback;   // queries handed back to the per-query path
+    uint32_t flags;
+};
+
+struct ScreenArgs {
+    const uint16_t* Xb;    // [N][np] bfloat16 collection
+    const float* xn;       // [N] float32 squared norms
+    long long N;
+    const uint16_t* Qb;    // [M][np] bfloat16 queries
+    BQuery* bq;
+    int M;
+    uint2* cand;           // (query, series)
+    uint32_t cand_cap;
+    BatchHdr* hdr;
+    float c_screen;        // relative margin c of E = c (qn + xn)
+    float* dump;           // optional [M][N] float32 dot products (tests)
+};
+
+struct RescoreArgs {
+    const float* X;
+    const float* Q;        // [M][n] float32 queries
+    int n, M;
+    BQuery* bq;
+    const uint2* cand;
+    uint32_t cand_cap;
+    BatchHdr* hdr;
+    double prune_rel, band_rel;
+    uint32_t* fallback;    // [M] queries to answer on the per-query path
+};
+
+struct ScreenShape {
+    int qt;     // queries per LDS tile: 32 or 64
+    int grid;   // persistent blocks
+};
+
+hipError_t launch_to_bf16(const float* X, long long N, int n, int np, uint16_t* Xb, float* xn, hipStream_t st);
+hipError_t launch_batch_init(BQuery* bq, int M, BatchHdr* hdr, hipStream_t st);
+hipError_t launch_batch_thresholds(BQuery* bq, int M, float c_screen, double seed_rel, hipStream_t st);
+hipError_t launch_screen(const ScreenArgs& s, int np, ScreenShape shape, hipStream_t st);
+hipError_t launch_rescore(const RescoreArgs& r, hipStream_t st);
+hipError_t launch_batch_resolve(const RescoreArgs& r, long long* out_idx, double* out_dist, hipStream_t st);
+
 // Launch shape of the lower-bound scan (chosen by the autotuner on first use).
 struct ScanShape {
     int threads;   // 256 or 512
@@ -105,6 +173,7 @@ struct ScanShape {
 hipError_t launch_reset(const QueryArgs& a, hipStream_t st);
 // query summaries, tables, window, and the lower-bound-guided approximate-search seed
 hipError_t launch_prepare_seed(const QueryArgs& a, const float* q, hipStream_t st);
+hipError_t launch_prepare_seed_batch(const QueryArgs& a, const SeedBatch& b, int n_queries, hipStream_t st);
 // threshold_sq < 0: use the best-so-far in QState; otherwise a fixed threshold.
 hipError_t launch_lbscan(const QueryArgs& a, float threshold_sq, ScanShape shape, hipStream_t st);
 // refinement; its last block resolves in float64, writes the result (and element qi of

@@ -138,8 +138,18 @@ __device__ long long block_lower_bound(const unsigned long long* __restrict__ ke
     }
 }
 
-__global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* __restrict__ q)
+// bfloat16 of a float32, round to nearest even (finite inputs)
+__device__ __forceinline__ uint16_t bf16_rne(float f)
 {
+    const uint32_t b = __float_as_uint(f);
+    return (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
+}
+
+__global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* __restrict__ q_plain, SeedBatch B)
+{
+    const bool batch = B.bq != nullptr;
+    const float* __restrict__ q = batch ? B.Q + (long long)blockIdx.y * A.n : q_plain;
+    unsigned long long* bsf = batch ? &B.bq[blockIdx.y].bsf_key : &A.qs->bsf_key;
     extern __shared__ float qv[];
     __shared__ double beta[257];
     __shared__ double qpaa[kSeg];
@@ -194,7 +204,26 @@ __global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* 
         t8[e] = __double2float_rz((double)L * (d * d));
     }
     __syncthreads();
-    if (blockIdx.x == 0) {
+    if (batch && blockIdx.x == 0) {
+        // bfloat16 copy of the query (zero padded to np) and its float32 squared norm
+        uint16_t* qb = B.qb + (long long)blockIdx.y * B.np;
+        float sq = 0.f;
+        for (int j = tid; j < B.np; j += 256) {
+            const float v = j < n ? qv[j] : 0.f;
+            qb[j] = bf16_rne(v);
+            sq += v * v;
+        }
+        sq = wave_sum(sq);
+        if (lane == 0) red_lb[tid >> 6] = (double)sq;
+        __syncthreads();
+        if (tid == 0) {
+            BQuery& bq = B.bq[blockIdx.y];
+            bq.qn = (float)red_lb[0] + (float)red_lb[1] + (float)red_lb[2] + (float)red_lb[3];
+            if (s_bad) bq.err = kErrNonFinite;
+        }
+        __syncthreads();
+    }
+    if (!batch && blockIdx.x == 0) {
         for (int e = tid; e < kSeg * kSym; e += 256) A.t8[e] = t8[e];
         for (int e = tid; e < kSeg * kCoarse; e += 256) {
             const float* p = t8 + (e >> 5) * kSym + (e & 31) * 8;
@@ -270,7 +299,7 @@ __global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* 
         lo = ell * N / nl;
         hi = (ell + 1) * N / nl;
     }
-    if (blockIdx.x == 0 && tid == 0) {
+    if (!batch && blockIdx.x == 0 && tid == 0) {
         QState* qs = A.qs;
         qs->root = s_root;
         qs->k64 = kq;
@@ -310,7 +339,7 @@ __global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* 
             acc += (dx * dx + dy * dy) + (dz * dz + dw * dw);
         }
         acc = wave_sum(acc);
-        if (lane == 0) atomicMin(&A.qs->bsf_key, pack_key(acc, row));
+        if (lane == 0) atomicMin(bsf, pack_key(acc, row));
     }
 }
 
@@ -325,7 +354,15 @@ int seed_grid(const QueryArgs& a)
 
 hipError_t launch_prepare_seed(const QueryArgs& a, const float* q, hipStream_t st)
 {
-    k_prepare_seed<<<seed_grid(a), 256, (size_t)a.n * sizeof(float), st>>>(a, q);
+    SeedBatch none{nullptr, nullptr, nullptr, 0};
+    k_prepare_seed<<<seed_grid(a), 256, (size_t)a.n * sizeof(float), st>>>(a, q, none);
+    return hipGetLastError();
+}
+
+hipError_t launch_prepare_seed_batch(const QueryArgs& a, const SeedBatch& b, int n_queries, hipStream_t st)
+{
+    dim3 grid((unsigned)seed_grid(a), (unsigned)n_queries);
+    k_prepare_seed<<<grid, 256, (size_t)a.n * sizeof(float), st>>>(a, nullptr, b);
     return hipGetLastError();
 }
 

@@ -1,0 +1,155 @@
+"""GPU parity of the batched pipeline (bfloat16 MFMA screen + float32 re-score + float64 resolve)
+against the oracle, and the screen's certified error bound."""
+import math
+
+import numpy as np
+import pytest
+
+import synth
+from oracle import nn_bruteforce
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _gamma(k, u):
+    return k * u / (1 - k * u)
+
+
+def _screen_margin(n, np_):
+    """The bound of the screen as documented: |d~^2 - d^2| <= c (qn + xn)."""
+    ub = 2.0 ** -8
+    c = (2 * ub + ub * ub) + 2 * _gamma(np_ + 16, 2.0 ** -23) * (1 + ub) ** 2 + 2 * _gamma(n, 2.0 ** -24) \
+        + 16 * 2.0 ** -24
+    return 1.05 * c + 32 * 2.0 ** -24
+
+
+@pytest.fixture(scope="module")
+def coll(oracle_native):
+    _need_gpu()
+    import paper_2009_00166_amd as paris
+    X = synth.random_walks(100_000, 256, seed=0)
+    Xd = torch.from_numpy(X).cuda()
+    index = paris.build(Xd)
+    index.attach_batch(max_batch=512)
+    return dict(X=X, Xd=Xd, index=index)
+
+
+def test_screen_dot_error_bound_1e7_pairs(coll):
+    """Certified bound of the bfloat16 screen on >= 10^7 (query, series) pairs, plus
+    adversarial pairs (identical, opposite and scaled rows)."""
+    X = coll["X"]
+    idx = coll["index"]
+    rng = np.random.default_rng(0)
+    Q, _, _ = synth.noisy_queries(X, 400, seed=5, sigma=(0.0, 1.0))
+    adv = np.stack([X[0], -X[1], X[2] * np.float32(3.0), X[3], np.zeros(256, np.float32) + np.float32(1e-3)])
+    Qa = np.ascontiguousarray(np.concatenate([Q, adv, rng.standard_normal((107, 256)).astype(np.float32)]))
+    dots = idx.screen_dots(torch.from_numpy(Qa).cuda()).cpu().numpy().astype(np.float64)
+    assert dots.shape == (512, 100_000)
+    Xf = X.astype(np.float64)
+    Qf = Qa.astype(np.float64)
+    exact = Qf @ Xf.T
+    absum = np.abs(Qf) @ np.abs(Xf).T
+    ub = 2.0 ** -8
+    bound = (2 * ub + ub * ub) * absum + _gamma(256 + 16, 2.0 ** -23) * (1 + ub) ** 2 * absum + 1e-30
+    err = np.abs(dots - exact)
+    assert np.all(err <= bound), float((err / np.maximum(bound, 1e-300)).max())
+    # the squared-distance margin used by the screen
+    qn = (Qf ** 2).sum(1)[:, None]
+    xn = (Xf ** 2).sum(1)[None, :]
+    d2 = qn + xn - 2 * exact
+    d2_screen = qn + xn - 2 * dots
+    c = _screen_margin(256, 256)
+    assert np.all(np.abs(d2_screen - d2) <= c * (qn + xn))
+    # the bound is not vacuous: bfloat16 errors are a visible fraction of it
+    assert np.max(err / np.maximum(bound, 1e-300)) > 0.01
+
+
+def test_batch_answers_match_oracle(coll, oracle_native):
+    X, idx = coll["X"], coll["index"]
+    Q1, _, _ = synth.noisy_queries(X, 400, seed=1, sigma=(0.01, 0.5))
+    Q2 = synth.fresh_walk_queries(112, 256, seed=2)
+    Q = np.ascontiguousarray(np.concatenate([Q1, Q2]))
+    ri, rd, _ = oracle_native.nn_many(Q, X, threads=16)
+    I, D, st = idx.query_batch(torch.from_numpy(Q).cuda(), with_stats=True)
+    torch.cuda.synchronize()
+    I = I.cpu().numpy()
+    D = D.cpu().numpy()
+    assert np.array_equal(I, ri)
+    ref = np.sqrt(rd)
+    assert np.all(np.abs(D - ref) <= 1e-5 * ref + 1e-12)
+    assert np.array_equal(D, ref)  # same float64 operation order, correctly rounded sqrt
+    assert st["lb_survivors"] >= Q.shape[0]
+
+
+def test_batch_chunks_and_partial_chunk(coll, oracle_native):
+    """1,100 queries with max_batch 512: two graph-launched chunks and a partial one."""
+    X, idx = coll["X"], coll["index"]
+    Q, _, _ = synth.noisy_queries(X, 1100, seed=3, sigma=(0.01, 0.5))
+    ri, rd, _ = oracle_native.nn_many(Q, X, threads=16)
+    I, D = idx.query_batch(torch.from_numpy(Q).cuda())
+    torch.cuda.synchronize()
+    assert np.array_equal(I.cpu().numpy(), ri)
+
+
+def test_batch_ties_fallback_nan_and_equal_count(oracle_native):
+    _need_gpu()
+    import paper_2009_00166_amd as paris
+    X = synth.random_walks(20_000, 256, seed=7)
+    for dst in (500, 900, 1200, 5000, 7000, 9000, 11000, 19999):
+        X[dst] = X[321]                       # nine identical rows: the band list overflows
+    X[77] = X[4500]
+    Xd = torch.from_numpy(X).cuda()
+    Q = np.stack([X[321], X[5000], X[4500], (X[321] + np.float32(1e-3)).astype(np.float32), X[10]]).astype(np.float32)
+    bad = X[11].copy()
+    bad[7] = np.nan
+    Qn = np.ascontiguousarray(np.concatenate([Q, bad[None, :], X[12:13]]))
+    for kw in ({}, {"leaf_mode": 1, "n_leaves": 64}):
+        idx = paris.build(Xd, **kw)
+        idx.attach_batch(max_batch=64)
+        I, D, st = idx.query_batch(torch.from_numpy(Qn).cuda(), with_stats=True)
+        torch.cuda.synchronize()
+        I = I.cpu().numpy()
+        D = D.cpu().numpy()
+        for m in range(5):
+            ri, _, rdist = nn_bruteforce(Q[m], X)
+            assert I[m] == ri and D[m] == rdist
+        assert I[0] == 321 and I[1] == 321 and I[2] == 77
+        assert I[5] == -1 and np.isnan(D[5]) and I[6] == 12
+        assert st["resolved"] >= 2            # the tied queries went to the per-query path
+        idx.close()
+
+
+@pytest.mark.parametrize("n", [64, 128])
+def test_batch_other_lengths(n, oracle_native):
+    _need_gpu()
+    import paper_2009_00166_amd as paris
+    X = synth.random_walks(30_000, n, seed=n)
+    Q, _, _ = synth.noisy_queries(X, 200, seed=4, sigma=(0.01, 0.5))
+    ri, rd, _ = oracle_native.nn_many(Q, X, threads=16)
+    idx = paris.build(torch.from_numpy(X).cuda())
+    idx.attach_batch(max_batch=256)
+    I, D = idx.query_batch(torch.from_numpy(Q).cuda())
+    torch.cuda.synchronize()
+    assert np.array_equal(I.cpu().numpy(), ri)
+    assert np.all(np.abs(D.cpu().numpy() - np.sqrt(rd)) <= 1e-5 * np.sqrt(rd) + 1e-12)
+    idx.close()
+
+
+def test_long_series_fall_back_to_per_query_path(oracle_native):
+    _need_gpu()
+    import paper_2009_00166_amd as paris
+    X = synth.random_walks(5000, 512, seed=9)
+    Q, _, _ = synth.noisy_queries(X, 20, seed=4, sigma=0.3)
+    ri, _, _ = oracle_native.nn_many(Q, X, threads=16)
+    idx = paris.build(torch.from_numpy(X).cuda())
+    idx.attach_batch(max_batch=32)
+    I, _ = idx.query_batch(torch.from_numpy(Q).cuda())
+    torch.cuda.synchronize()
+    assert np.array_equal(I.cpu().numpy(), ri)
+    idx.close()

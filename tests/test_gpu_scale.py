@@ -74,3 +74,18 @@ def test_sampled_exact_answers(full, oracle_native):
     I, D = index.query_batch(Qd)
     torch.cuda.synchronize()
     assert np.array_equal(I.cpu().numpy(), ri)
+
+
+def test_batched_pipeline_at_scale(full, oracle_native):
+    """The batched pipeline (bfloat16 MFMA screen) at 10M x 256, in the launch configuration the
+    benchmark times (chunks of 4096), on a sample of uneven-difficulty queries."""
+    X, index = full["X"], full["index"]
+    index.attach_batch(max_batch=4096)
+    Q, _, _ = synth.noisy_queries(X, 48, seed=2, sigma=(0.01, 0.5))
+    ri, rd, _ = oracle_native.nn_many(Q, X, threads=16)
+    I, D, st = index.query_batch(torch.from_numpy(Q).cuda(), with_stats=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(I.cpu().numpy(), ri)
+    ref = np.sqrt(rd)
+    assert np.all(np.abs(D.cpu().numpy() - ref) <= 1e-5 * ref)
+    print(f"[scale] batched: {st['lb_survivors']} screen survivors, {st['resolved']} fallbacks", flush=True)
