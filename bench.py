@@ -6,7 +6,8 @@ resolve, one query at a time with its result back on the host), over an index bu
 the timed region (the build time is reported beside). Inputs are resident in HBM before timing.
 
 Prints one JSON line. Options: --gpus N (only 1 is supported: this build measures one GPU),
---steps K, --warmup W, --queries Q, --series N, --length n, --no-cpu-baseline.
+--steps K, --warmup W, --queries Q, --series N, --length n, --no-cpu-baseline, --no-batched,
+--batch B, --batch-steps K (the batched section: batches of B queries through paris_query_batch).
 """
 from __future__ import annotations
 
@@ -57,7 +58,11 @@ def main() -> int:
     ap.add_argument("--cpu-queries", type=int, default=16)
     ap.add_argument("--cpu-threads", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true")
+    ap.add_argument("--batch", type=int, default=4096)
+    ap.add_argument("--batch-steps", type=int, default=3)
     args = ap.parse_args()
+    args._plain_qps = None
 
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the exact search is built and measured on a single "
@@ -119,6 +124,7 @@ def main() -> int:
     mean = lambda k: float(np.mean([s[k] for s in stats]))
 
     total_q = M * args.steps
+    args._plain_qps = total_q / elapsed
     lb_ms = phase_ms[1] / max(timed, 1)
     lb_bytes = SAX_BYTES_PER_SERIES * N
     achieved = lb_bytes / (lb_ms * 1e-3) / 1e9
@@ -155,12 +161,73 @@ def main() -> int:
                                                "resolved")},
         "answers_match_source_frac": float(np.mean(answers == src)),
     }
+    if not args.no_batched:
+        rec["batched"] = batched_section(index, X, args)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")
         rec["cpu_baseline"] = cpu_baseline(X, Q, answers, min(args.cpu_queries, M), args.cpu_threads)
     print(json.dumps(rec), flush=True)
     index.close()
     return 0
+
+
+def batched_section(index, X, args):
+    """Batches of 4096 queries with noise sigma ~ U[0.01, 0.5] through paris_query_batch
+    (per-query seeds, bfloat16 MFMA screen, float32 re-score, float64 resolve; one HIP graph
+    per batch) over the same 10M x 256 collection."""
+    import numpy as np
+    import torch
+
+    import synth
+    B = args.batch
+    N, n = X.shape
+    t0 = time.perf_counter()
+    ws_bytes = index.attach_batch(max_batch=B)
+    attach_s = time.perf_counter() - t0
+    Qb, src, _ = synth.noisy_queries(X, B, seed=1, sigma=(0.01, 0.5))
+    Qd = torch.from_numpy(Qb).cuda()
+    I = torch.empty(B, dtype=torch.int64, device="cuda")
+    D = torch.empty(B, dtype=torch.float64, device="cuda")
+    for _ in range(args.warmup):
+        index.query_batch(Qd, out=(I, D))
+    torch.cuda.synchronize()
+    log(f"batched warmup done (attach {attach_s * 1e3:.0f} ms)")
+    t1 = time.perf_counter()
+    for k in range(args.batch_steps):
+        index.query_batch(Qd, out=(I, D))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t1
+    log(f"batched timed {args.batch_steps} batches")
+    answers = I.cpu().numpy()
+    # one more batch, launched stage by stage with HIP events, for the per-stage times
+    index.set_timing(True)
+    _, _, st = index.query_batch(Qd, out=(I, D), with_stats=True)
+    ms, chunks = index.batch_timing()
+    index.set_timing(False)
+    stage = [m / max(chunks, 1) for m in ms]
+    np_ = (n + 31) // 32 * 32
+    flops = 2.0 * B * N * np_
+    achieved = flops / (stage[1] * 1e-3) / 1e12
+    qps = B * args.batch_steps / elapsed
+    return {
+        "metric": "exact 1-NN queries/s @10M x 256 fp32 (batched)",
+        "value": qps, "unit": "queries/s", "ms_per_batch": elapsed / args.batch_steps * 1e3,
+        "steps": args.batch_steps, "dtype": "bf16 screen, f32 re-score, f64 resolve",
+        "config": {"workload": f"batched exact 1-NN: {N} x {n} random walks, batches of {B} queries "
+                               "(dataset series + N(0, sigma) noise, sigma ~ U[0.01, 0.5]), per-query "
+                               "seeds, bfloat16 MFMA screen with certified margin, float32 re-score, "
+                               "float64 resolve, one HIP graph per batch",
+                   "batch": B, "n_series": N, "length": n},
+        "vs_plain": qps / args._plain_qps if args._plain_qps else None,
+        "roofline": {"bound": "mfma", "kernel": "k_screen", "achieved": achieved, "peak": 2500.0,
+                     "unit": "TFLOP/s", "frac": achieved / 2500.0, "traffic": None,
+                     "flops_per_launch": flops, "avg_launch_ms": stage[1]},
+        "stages_ms_per_batch": dict(zip(["seeds", "screen", "rescore", "resolve"], stage)),
+        "screen_survivors_per_query": st["lb_survivors"] / B,
+        "fallback_queries": st["resolved"],
+        "workspace_bytes": ws_bytes,
+        "answers_match_source_frac": float(np.mean(answers == src)),
+    }
 
 
 if __name__ == "__main__":

@@ -215,6 +215,14 @@ paris_status paris_lb_scan(paris_index *idx, const float *query_dev, float thres
 paris_status paris_set_timing(paris_index *idx, int32_t enable);
 paris_status paris_get_timing(const paris_index *idx, double *ms_out3, int64_t *n_queries);
 
+/*
+ * With timing on, paris_query_batch launches its pipeline directly (not through the captured
+ * graph) with HIP events between the stages; ms_out4 receives the summed milliseconds of
+ * [0] reset + seeds + screen thresholds, [1] bfloat16 MFMA screen, [2] float32 re-score,
+ * [3] float64 resolve, and n_chunks the number of timed chunks.
+ */
+paris_status paris_get_batch_timing(const paris_index *idx, double *ms_out4, int64_t *n_chunks);
+
 /* Release the handle (the borrowed buffers are not touched). NULL is accepted. */
 paris_status paris_free(paris_index *idx);
 

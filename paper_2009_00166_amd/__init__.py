@@ -213,6 +213,13 @@ class Index:
         check(load_library().paris_get_timing(self._h, ms, ctypes.byref(n)), "paris_get_timing")
         return list(ms), int(n.value)
 
+    def batch_timing(self):
+        """(summed ms per batch stage [seeds, screen, rescore, resolve], timed chunks)."""
+        ms = (ctypes.c_double * 4)()
+        n = ctypes.c_int64(0)
+        check(load_library().paris_get_batch_timing(self._h, ms, ctypes.byref(n)), "paris_get_batch_timing")
+        return list(ms), int(n.value)
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             load_library().paris_free(self._h)

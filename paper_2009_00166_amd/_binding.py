@@ -64,6 +64,7 @@ SIGNATURES = [
     ("paris_screen_dots", ctypes.c_int, [_P, _P, _I32, _P, _P]),
     ("paris_set_timing", ctypes.c_int, [_P, _I32]),
     ("paris_get_timing", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
+    ("paris_get_batch_timing", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     ("paris_free", ctypes.c_int, [_P]),
     ("paris_status_string", ctypes.c_char_p, [ctypes.c_int]),
 ]

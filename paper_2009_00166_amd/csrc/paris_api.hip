@@ -92,16 +92,17 @@ Margins margins_for_length(int n)
 }
 
 // Relative margin c of the bfloat16 screen, |d~^2 - d^2| <= c (qn + xn): bfloat16 rounding of
-// both operands (2 u_b + u_b^2, u_b = 2^-8), the MFMA's float32 accumulation over np + 16 terms
-// (unit roundoff taken as 2^-23 so truncating accumulation is covered), the float32 norms
-// (gamma_n), and the float32 evaluation of the folded test; inflated by 5%.
+// both operands (2 u_b + u_b^2, u_b = 2^-8), the float32 norms (gamma_n), and the MFMA's float32
+// accumulation of the np products plus the two folded threshold terms, whose magnitudes are
+// below 2 (qn + xn) (unit roundoff taken as 2^-23 so truncating accumulation is covered:
+// 2 gamma (1/2 (1 + u_b)^2 + 2) <= 6 gamma); inflated by 5%.
 float screen_margin(int n, int np)
 {
     const double ub = std::ldexp(1.0, -8);
     const double u23 = std::ldexp(1.0, -23);
     const double u24 = std::ldexp(1.0, -24);
     auto gam = [](int k, double u) { return k * u / (1.0 - k * u); };
-    const double c = (2.0 * ub + ub * ub) + 2.0 * gam(np + 16, u23) * (1.0 + ub) * (1.0 + ub) +
+    const double c = (2.0 * ub + ub * ub) + 6.0 * gam(np + 48, u23) * (1.0 + ub) * (1.0 + ub) +
                      2.0 * gam(n, u24) + 16.0 * u24;
     return (float)(1.05 * c + 32.0 * u24);
 }
@@ -141,7 +142,7 @@ struct paris_index {
     int np;
     bool screen_ok;
     struct {
-        size_t hdr, xb, xn, qin, qb, bq, cand, oidx, odist, fb, total;
+        size_t hdr, xb, xn, qin, qb, bq, cand, cand_d2, oidx, odist, fb, total;
         uint32_t cand_cap;
     } bp;
     ScreenShape screen;
@@ -152,6 +153,9 @@ struct paris_index {
     BatchHdr* host_hdr;   // pinned read-back of the batch header
     uint32_t* host_fb;    // pinned read-back of the fallback list
     long long batch_candidates;
+    hipEvent_t bev[5];    // batch stage events (timing on): seeds | screen | re-score | resolve
+    double batch_ms[4];
+    long long timed_chunks;
 };
 
 namespace {
@@ -310,6 +314,7 @@ void make_batch_plan(paris_index* h, int max_batch)
     const size_t cap = M * 4096 < (size_t)0xFFFFFFF0u ? M * 4096 : (size_t)0xFFFFFFF0u;
     h->bp.cand_cap = (uint32_t)cap;
     h->bp.cand = take(cap * 8);
+    h->bp.cand_d2 = take(cap * 4);
     h->bp.oidx = take(M * 8);
     h->bp.odist = take(M * 8);
     h->bp.fb = take(M * 4);
@@ -350,6 +355,7 @@ RescoreArgs rescore_args(paris_index* h, int m)
     r.M = m;
     r.bq = bqs(h);
     r.cand = reinterpret_cast<const uint2*>(h->bws + h->bp.cand);
+    r.cand_d2 = reinterpret_cast<float*>(h->bws + h->bp.cand_d2);
     r.cand_cap = h->bp.cand_cap;
     r.hdr = bhdr(h);
     r.prune_rel = h->mg.prune_rel;
@@ -360,7 +366,7 @@ RescoreArgs rescore_args(paris_index* h, int m)
 
 // The batch pipeline on queries already copied to the internal query buffer: reset, seeds,
 // screen thresholds, the MFMA screen, float32 re-score, float64 resolve.
-paris_status launch_batch_pipeline(paris_index* h, int m, hipStream_t st)
+paris_status launch_batch_pipeline(paris_index* h, int m, hipStream_t st, bool timed = false)
 {
     const QueryArgs a = args_for(h);
     SeedBatch sb;
@@ -368,14 +374,19 @@ paris_status launch_batch_pipeline(paris_index* h, int m, hipStream_t st)
     sb.bq = bqs(h);
     sb.qb = reinterpret_cast<uint16_t*>(h->bws + h->bp.qb);
     sb.np = h->np;
+    if (timed) HIP_TRY(hipEventRecord(h->bev[0], st));
     HIP_TRY(launch_batch_init(bqs(h), m, bhdr(h), st));
     HIP_TRY(launch_prepare_seed_batch(a, sb, m, st));
     HIP_TRY(launch_batch_thresholds(bqs(h), m, h->c_screen, h->seed_rel, st));
+    if (timed) HIP_TRY(hipEventRecord(h->bev[1], st));
     HIP_TRY(launch_screen(screen_args(h, m, nullptr), h->np, h->screen, st));
+    if (timed) HIP_TRY(hipEventRecord(h->bev[2], st));
     const RescoreArgs r = rescore_args(h, m);
     HIP_TRY(launch_rescore(r, st));
+    if (timed) HIP_TRY(hipEventRecord(h->bev[3], st));
     HIP_TRY(launch_batch_resolve(r, reinterpret_cast<long long*>(h->bws + h->bp.oidx),
                                  reinterpret_cast<double*>(h->bws + h->bp.odist), st));
+    if (timed) HIP_TRY(hipEventRecord(h->bev[4], st));
     return PARIS_OK;
 }
 
@@ -404,16 +415,25 @@ paris_status run_batch_chunk(paris_index* h, const float* queries, long long q0,
 {
     const size_t qbytes = (size_t)m * h->n * 4;
     HIP_TRY(hipMemcpyAsync(h->bws + h->bp.qin, queries + q0 * h->n, qbytes, hipMemcpyDeviceToDevice, st));
-    if (m == h->max_batch && h->graph_exec) {
+    const bool timed = h->timing && h->bev[0];
+    if (m == h->max_batch && h->graph_exec && !timed) {
         HIP_TRY(hipGraphLaunch(h->graph_exec, st));
     } else {
-        paris_status s = launch_batch_pipeline(h, m, st);
+        paris_status s = launch_batch_pipeline(h, m, st, timed);
         if (s != PARIS_OK) return s;
     }
     HIP_TRY(hipMemcpyAsync(out_idx + q0, h->bws + h->bp.oidx, (size_t)m * 8, hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipMemcpyAsync(out_dist + q0, h->bws + h->bp.odist, (size_t)m * 8, hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipMemcpyAsync(h->host_hdr, bhdr(h), sizeof(BatchHdr), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
+    if (timed) {
+        for (int k = 0; k < 4; ++k) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, h->bev[k], h->bev[k + 1]));
+            h->batch_ms[k] += ms;
+        }
+        h->timed_chunks += 1;
+    }
     const BatchHdr hd = *h->host_hdr;
     *cands += hd.n_cand;
     if (hd.n_fallback) {
@@ -430,19 +450,22 @@ paris_status run_batch_chunk(paris_index* h, const float* queries, long long q0,
     return PARIS_OK;
 }
 
-// Screen autotuner: the query-tile height (32 or 64 rows) with every threshold at +inf (no
-// candidate), timed over full-size batches; the median of three runs decides.
+// Screen autotuner: query-tile height (32 or 64 rows) x series per wave (32, two waves per SIMD;
+// or 64, one wave per SIMD), every threshold at +inf (no candidate), timed over full-size
+// batches; the median of three runs decides. PARIS_SCREEN_SHAPE="qt,subs" overrides.
 paris_status tune_screen(paris_index* h, hipStream_t st)
 {
-    const char* env = std::getenv("PARIS_SCREEN_QT");
+    const char* env = std::getenv("PARIS_SCREEN_SHAPE");
     int cus = 256, dev = 0;
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         cus = 256;
-    h->screen.grid = cus;
-    if (env && (std::atoi(env) == 32 || std::atoi(env) == 64)) {
-        h->screen.qt = std::atoi(env);
-        return PARIS_OK;
+    if (env) {
+        int qt = 0, subs = 0;
+        if (std::sscanf(env, "%d,%d", &qt, &subs) == 2 && (qt == 32 || qt == 64) && (subs == 2 || subs == 4)) {
+            h->screen = ScreenShape{qt, cus * (subs == 2 ? 2 : 1), subs};
+            return PARIS_OK;
+        }
     }
     const int m = h->max_batch;
     HIP_TRY(hipMemsetAsync(h->bws + h->bp.qb, 0, (size_t)m * h->np * 2, st));
@@ -450,9 +473,9 @@ paris_status tune_screen(paris_index* h, hipStream_t st)
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     float best = 1e30f;
-    int pick = 64;
-    for (int qt : {32, 64}) {
-        ScreenShape sh{qt, cus};
+    ScreenShape pick{64, cus, 4};
+    const ScreenShape cands[] = {{32, cus * 2, 2}, {64, cus * 2, 2}, {32, cus, 4}, {64, cus, 4}};
+    for (const ScreenShape& sh : cands) {
         float t[3];
         for (int r = 0; r < 4; ++r) {
             HIP_TRY(launch_batch_init(bqs(h), m, bhdr(h), st));  // thresholds +inf
@@ -466,11 +489,11 @@ paris_status tune_screen(paris_index* h, hipStream_t st)
         }
         const float lo = std::fmin(t[0], std::fmin(t[1], t[2])), hi = std::fmax(t[0], std::fmax(t[1], t[2]));
         const float med = t[0] + t[1] + t[2] - lo - hi;
-        if (med < best) { best = med; pick = qt; }
+        if (med < best) { best = med; pick = sh; }
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
-    h->screen.qt = pick;
+    h->screen = pick;
     return PARIS_OK;
 }
 
@@ -638,7 +661,7 @@ paris_status paris_build(const float* series_dev, int64_t n_series, int32_t leng
     h->np = (length + 31) / 32 * 32;
     h->screen_ok = false;
     std::memset(&h->bp, 0, sizeof(h->bp));
-    h->screen = ScreenShape{64, 0};
+    h->screen = ScreenShape{64, 0, 4};
     h->c_screen = screen_margin(length, h->np);
     // the seed series' exact squared distance is at most d32 (1 + g) / (1 - g) < d32 (1 + 3 g)
     h->seed_rel = 3.0 * gamma_k(length + 2) + std::ldexp(1.0, -30);
@@ -647,6 +670,9 @@ paris_status paris_build(const float* series_dev, int64_t n_series, int32_t leng
     h->host_hdr = nullptr;
     h->host_fb = nullptr;
     h->batch_candidates = 0;
+    for (int k = 0; k < 5; ++k) h->bev[k] = nullptr;
+    for (int k = 0; k < 4; ++k) h->batch_ms[k] = 0.0;
+    h->timed_chunks = 0;
     if (hipHostMalloc(reinterpret_cast<void**>(&h->host_qs), sizeof(QState), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&h->host_res), sizeof(QResult), hipHostMallocMapped) != hipSuccess ||
         hipHostGetDevicePointer(reinterpret_cast<void**>(&h->host_res_dev), h->host_res, 0) != hipSuccess) {
@@ -841,10 +867,22 @@ paris_status paris_set_timing(paris_index* h, int32_t enable)
     if (!handle_ok(h)) return PARIS_ESTATE;
     if (enable && !h->ev[0]) {
         for (int k = 0; k < 4; ++k) HIP_TRY(hipEventCreate(&h->ev[k]));
+        for (int k = 0; k < 5; ++k) HIP_TRY(hipEventCreate(&h->bev[k]));
     }
     h->timing = enable != 0;
     for (int k = 0; k < 3; ++k) h->phase_ms[k] = 0.0;
     h->timed_queries = 0;
+    for (int k = 0; k < 4; ++k) h->batch_ms[k] = 0.0;
+    h->timed_chunks = 0;
+    return PARIS_OK;
+}
+
+paris_status paris_get_batch_timing(const paris_index* h, double* ms_out4, int64_t* n_chunks)
+{
+    if (!handle_ok(h)) return PARIS_ESTATE;
+    if (!ms_out4 || !n_chunks) return PARIS_EINVAL;
+    for (int k = 0; k < 4; ++k) ms_out4[k] = h->batch_ms[k];
+    *n_chunks = h->timed_chunks;
     return PARIS_OK;
 }
 
@@ -870,6 +908,8 @@ paris_status paris_free(paris_index* h)
     if (h->host_res) (void)hipHostFree(h->host_res);
     for (int k = 0; k < 4; ++k)
         if (h->ev[k]) (void)hipEventDestroy(h->ev[k]);
+    for (int k = 0; k < 5; ++k)
+        if (h->bev[k]) (void)hipEventDestroy(h->bev[k]);
     delete h;
     return PARIS_OK;
 }

@@ -12,7 +12,10 @@
 // seed's distance, rounded up). The nearest neighbour and every series tied with it always pass.
 // The test is folded into per-row and per-column constants: keep iff
 //     dot >= a_q + b_x,  a_q = ((1 - c) qn - U_q) / 2,  b_x = (1 - c) xn / 2
-// (both rounded down, c inflated for the float32 evaluation of the test itself).
+// (both rounded down, c inflated for the evaluation of the test itself). The constants enter
+// the contraction itself through one extra k-step: the query row carries RU(-a_q) and 1, the
+// series row 1 and RU(-b_x) (bfloat16 rounded toward +inf, so the sum never decreases), hence
+// every accumulator ends as dot - a_q - b_x (or more) and a series survives iff it is >= 0.
 #include "paris_internal.h"
 
 namespace paris {
@@ -26,11 +29,42 @@ __device__ __forceinline__ uint16_t to_bf16(float f)
     return (uint16_t)((b + 0x7FFFu + ((b >> 16) & 1u)) >> 16);
 }
 
+// bfloat16 of a finite float32, rounded toward +inf
+__device__ __forceinline__ uint16_t to_bf16_up(float f)
+{
+    const uint32_t b = __float_as_uint(f);
+    uint32_t h = b >> 16;
+    if ((b & 0xFFFFu) != 0u && !(b >> 31)) h += 1u;  // positive with dropped bits: away from 0
+    return (uint16_t)h;                               // negative: truncation is toward +inf
+}
+
 __device__ __forceinline__ float key_dist_b(unsigned long long k) { return __uint_as_float((uint32_t)(k >> 32)); }
 
 __device__ __forceinline__ unsigned long long pack_key_b(float d2, uint32_t idx)
 {
     return ((unsigned long long)__float_as_uint(d2) << 32) | idx;
+}
+
+constexpr float kNoPass = -1.0e30f;  // bias of absent rows / columns: never >= 0
+constexpr int kCandStage = 512;      // screen candidates staged per block in LDS
+
+// bfloat16 of a finite float32, rounded toward -inf
+__device__ __forceinline__ uint16_t to_bf16_down(float f)
+{
+    const uint32_t b = __float_as_uint(f);
+    uint32_t h = b >> 16;
+    if ((b & 0xFFFFu) != 0u && (b >> 31)) h += 1u;  // negative with dropped bits: away from 0
+    return (uint16_t)h;
+}
+
+// A bias t as two bfloat16 terms hi + lo >= t: hi = t rounded down (t - hi is then exact in
+// float32 and non-negative), lo = that remainder rounded up. Packed as [hi, lo].
+__device__ __forceinline__ uint2 bias_pair(float t)
+{
+    const uint16_t hi = to_bf16_down(t);
+    const float rem = t - __uint_as_float((uint32_t)hi << 16);
+    const uint16_t lo = to_bf16_up(rem);
+    return make_uint2((uint32_t)hi | ((uint32_t)lo << 16), 0u);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -101,35 +135,62 @@ __global__ void k_batch_thresholds(BQuery* __restrict__ bq, int M, float c_scree
 
 // ------------------------------------------------------------------------------------------
 // The screen. Persistent blocks of 4 waves take series tiles of 256 (64 per wave) from an
-// atomic work counter. A wave keeps its 64 series' bfloat16 fragments (np/32 k-steps) in
-// registers for the whole item and streams every query tile (QT queries, double-buffered in
-// LDS, rows padded by 16 bytes so the 16 rows read by a quarter-wave hit distinct banks)
-// through v_mfma_f32_16x16x32_bf16: per k-step QT/16 x 4 MFMAs. Operand layout (16x16x32):
-// lane l holds row/column (l % 16) and the 8 k-elements 8 (l / 16) .. +7 of the k-step, for
-// both A (queries) and B (series); the accumulator of lane l holds rows 4 (l / 16) + r,
-// r = 0..3, of column l % 16. Survivors are rare: a lane ORs its pass tests and only a wave
-// with a pass takes the append path.
+// atomic work counter. A wave keeps its 64 series' bfloat16 fragments (np/32 k-steps plus the
+// bias step) in registers for the whole item and streams every query tile (QT queries,
+// double-buffered in LDS, rows padded by 16 bytes so the 16 rows read by a quarter-wave hit
+// distinct banks) through v_mfma_f32_16x16x32_bf16: per k-step QT/16 x 4 MFMAs, with the next
+// k-step's query operands read from LDS before the current MFMAs issue. Operand layout
+// (16x16x32): lane l holds row/column (l % 16) and the 8 k-elements 8 (l / 16) .. +7 of the
+// k-step, for both A (queries) and B (series); the accumulator of lane l holds rows
+// 4 (l / 16) + r, r = 0..3, of column l % 16. A wave takes the append path only when the
+// maximum over its accumulators is >= 0 (rare).
 // ------------------------------------------------------------------------------------------
-template <int KS, int QT>
-__global__ __launch_bounds__(256, 1) void k_screen(ScreenArgs S)
+template <int KS, int QT, int SUBS>
+__global__ __launch_bounds__(256, SUBS == 2 ? 2 : 1) void k_screen(ScreenArgs S)
 {
+    constexpr int XW = 16 * SUBS;       // series per wave (kept in registers)
+    constexpr int XB = 4 * XW;          // series per work item (block)
     constexpr int NP = KS * 32;
-    constexpr int RS = NP + 8;          // LDS row stride (bfloat16 elements)
+    constexpr int KT = KS + 1;          // k-steps including the bias step
+    constexpr int RS = KT * 32 + 8;     // LDS row stride (bfloat16 elements)
     constexpr int QS = QT / 16;         // query subtiles per tile
-    constexpr int V8 = NP / 8;          // 16-byte vectors per row
+    constexpr int V8 = NP / 8;          // 16-byte vectors per data row
     constexpr int STAGE = (QT * V8 + 255) / 256;
     __shared__ __attribute__((aligned(16))) uint16_t qtile[2][QT * RS];
-    __shared__ __attribute__((aligned(16))) float qa[2][QT];
     __shared__ long long s_item;
-
+    // candidates are staged per block (LDS atomics) and flushed with one global atomic
+    __shared__ uint2 cbuf[kCandStage];
+    __shared__ uint32_t ccount, cbase;
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    if (tid == 0) ccount = 0;
+    auto flush_cands = [&]() {
+        const uint32_t cnt = min(ccount, (uint32_t)kCandStage);
+        if (tid == 0) cbase = atomicAdd(&S.hdr->n_cand, cnt);
+        __syncthreads();
+        for (uint32_t k = tid; k < cnt; k += 256) {
+            const uint32_t pos = cbase + k;
+            if (pos < S.cand_cap) S.cand[pos] = cbuf[k];
+        }
+        __syncthreads();
+        if (tid == 0) ccount = 0;
+        __syncthreads();
+    };
+
     const int col = l & 15, kg = l >> 4;
     const int M = S.M;
     const long long N = S.N;
     const int n_qt = (M + QT - 1) / QT;
-    const long long n_items = (N + 255) / 256;
+    const long long n_items = (N + XB - 1) / XB;
+    const bool dump = S.dump != nullptr;
 
-    auto stage_load = [&](int t, uint4* pre, float& pa) {
+    // bias block of every row: chunk 0 = [hi(-a_q), lo(-a_q), 1, 1, 0 ...] is rewritten with
+    // each tile, chunks 1..3 stay zero
+    for (int e = tid; e < 2 * QT * 4; e += 256) {
+        const int buf = e / (QT * 4), rem = e - buf * QT * 4, row = rem >> 2, ch = rem & 3;
+        *reinterpret_cast<uint4*>(&qtile[buf][row * RS + NP + ch * 8]) = make_uint4(0, 0, 0, 0);
+    }
+
+    auto stage_load = [&](int t, uint4* pre, uint2& bias) {
 #pragma unroll
         for (int s = 0; s < STAGE; ++s) {
             const int e = tid + s * 256;
@@ -141,10 +202,13 @@ __global__ __launch_bounds__(256, 1) void k_screen(ScreenArgs S)
         }
         if (tid < QT) {
             const int q = t * QT + tid;
-            pa = q < M ? S.bq[q].a : __builtin_inff();
+            const float a = (q < M && !dump) ? S.bq[q].a : (dump ? 0.f : __builtin_inff());
+            const float t1 = a < __builtin_inff() ? -a : kNoPass;
+            bias = bias_pair(t1);  // [hi(-a_q), lo(-a_q), 1.0, 1.0]
+            bias.y = 0x3F803F80u;
         }
     };
-    auto stage_store = [&](int buf, const uint4* pre, float pa) {
+    auto stage_store = [&](int buf, const uint4* pre, uint2 bias) {
 #pragma unroll
         for (int s = 0; s < STAGE; ++s) {
             const int e = tid + s * 256;
@@ -153,7 +217,7 @@ __global__ __launch_bounds__(256, 1) void k_screen(ScreenArgs S)
                 *reinterpret_cast<uint4*>(&qtile[buf][row * RS + v * 8]) = pre[s];
             }
         }
-        if (tid < QT) qa[buf][tid] = pa;
+        if (tid < QT) *reinterpret_cast<uint2*>(&qtile[buf][tid * RS + NP]) = bias;
     };
 
     for (;;) {
@@ -162,12 +226,11 @@ __global__ __launch_bounds__(256, 1) void k_screen(ScreenArgs S)
         __syncthreads();
         const long long item = s_item;
         if (item >= n_items) break;  // uniform: every wave reaches this exit
-        const long long xb0 = item * 256 + w * 64;
+        const long long xb0 = item * XB + w * XW;
 
-        bf16x8 bfr[4][KS];
-        float bx[4];
+        bf16x8 bfr[SUBS][KT];
 #pragma unroll
-        for (int sub = 0; sub < 4; ++sub) {
+        for (int sub = 0; sub < SUBS; ++sub) {
             const long long x = xb0 + sub * 16 + col;
             const bool ok = x < N;
 #pragma unroll
@@ -175,122 +238,147 @@ __global__ __launch_bounds__(256, 1) void k_screen(ScreenArgs S)
                 if (ok) bfr[sub][ks] = *reinterpret_cast<const bf16x8*>(S.Xb + x * NP + ks * 32 + kg * 8);
                 else bfr[sub][ks] = bf16x8{};
             }
-            bx[sub] = ok ? __double2float_rd((1.0 - (double)S.c_screen) * (double)S.xn[x] * 0.5)
-                         : __builtin_inff();
+            // bias step: lanes of k-group 0 carry [1, RU(-b_x), 0 ...]
+            float t2 = kNoPass;
+            if (ok) t2 = dump ? 0.f : -__double2float_rd((1.0 - (double)S.c_screen) * (double)S.xn[x] * 0.5);
+            uint4 bb = make_uint4(0, 0, 0, 0);
+            if (kg == 0) {
+                bb.x = 0x3F803F80u;   // [1.0, 1.0, hi(-b_x), lo(-b_x)]
+                const uint2 hl = bias_pair(t2);
+                bb.y = hl.x;
+            }
+            bfr[sub][KS] = __builtin_bit_cast(bf16x8, bb);
         }
 
         {
             uint4 pre[STAGE];
-            float pa = 0.f;
-            stage_load(0, pre, pa);
-            stage_store(0, pre, pa);
+            uint2 bias = make_uint2(0u, 0u);
+            stage_load(0, pre, bias);
+            stage_store(0, pre, bias);
         }
         __syncthreads();
 
         for (int t = 0; t < n_qt; ++t) {
             const int buf = t & 1;
             uint4 pre[STAGE];
-            float pa = 0.f;
+            uint2 bias = make_uint2(0u, 0u);
             const bool more = t + 1 < n_qt;
-            if (more) stage_load(t + 1, pre, pa);  // in flight during the MFMAs
+            if (more) stage_load(t + 1, pre, bias);  // in flight during the MFMAs
 
-            f32x4 acc[QS][4];
+            f32x4 acc[QS][SUBS];
 #pragma unroll
             for (int qs = 0; qs < QS; ++qs)
 #pragma unroll
-                for (int sub = 0; sub < 4; ++sub) acc[qs][sub] = f32x4{0.f, 0.f, 0.f, 0.f};
-            const uint16_t* tb = qtile[buf];
+                for (int sub = 0; sub < SUBS; ++sub) acc[qs][sub] = f32x4{0.f, 0.f, 0.f, 0.f};
+            const uint16_t* tb = qtile[buf] + col * RS + kg * 8;
+            bf16x8 a[QS], an[QS];
 #pragma unroll
-            for (int ks = 0; ks < KS; ++ks) {
-                bf16x8 a[QS];
+            for (int qs = 0; qs < QS; ++qs) a[qs] = *reinterpret_cast<const bf16x8*>(tb + qs * 16 * RS);
+#pragma unroll
+            for (int ks = 0; ks < KT; ++ks) {
+                if (ks + 1 < KT) {
+#pragma unroll
+                    for (int qs = 0; qs < QS; ++qs)
+                        an[qs] = *reinterpret_cast<const bf16x8*>(tb + qs * 16 * RS + (ks + 1) * 32);
+                }
 #pragma unroll
                 for (int qs = 0; qs < QS; ++qs)
-                    a[qs] = *reinterpret_cast<const bf16x8*>(tb + (qs * 16 + col) * RS + ks * 32 + kg * 8);
 #pragma unroll
-                for (int qs = 0; qs < QS; ++qs)
-#pragma unroll
-                    for (int sub = 0; sub < 4; ++sub)
+                    for (int sub = 0; sub < SUBS; ++sub)
                         acc[qs][sub] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[qs], bfr[sub][ks], acc[qs][sub],
                                                                                0, 0, 0);
+                if (ks + 1 < KT) {
+#pragma unroll
+                    for (int qs = 0; qs < QS; ++qs) a[qs] = an[qs];
+                }
             }
 
-            bool hit = false;
-#pragma unroll
-            for (int qs = 0; qs < QS; ++qs) {
-                const f32x4 av = *reinterpret_cast<const f32x4*>(&qa[buf][qs * 16 + kg * 4]);
-#pragma unroll
-                for (int sub = 0; sub < 4; ++sub)
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) hit |= (acc[qs][sub][r] - bx[sub]) >= av[r];
-            }
-            if (S.dump) {
+            if (dump) {
 #pragma unroll
                 for (int qs = 0; qs < QS; ++qs)
 #pragma unroll
-                    for (int sub = 0; sub < 4; ++sub)
+                    for (int sub = 0; sub < SUBS; ++sub)
 #pragma unroll
                         for (int r = 0; r < 4; ++r) {
                             const int q = t * QT + qs * 16 + kg * 4 + r;
                             const long long x = xb0 + sub * 16 + col;
                             if (q < M && x < N) S.dump[(long long)q * N + x] = acc[qs][sub][r];
                         }
-            }
-            if (__ballot(hit)) {
-                if (hit) {
+            } else {
+                float m = kNoPass;
 #pragma unroll
-                    for (int qs = 0; qs < QS; ++qs) {
-                        const f32x4 av = *reinterpret_cast<const f32x4*>(&qa[buf][qs * 16 + kg * 4]);
+                for (int qs = 0; qs < QS; ++qs)
 #pragma unroll
-                        for (int sub = 0; sub < 4; ++sub)
+                    for (int sub = 0; sub < SUBS; ++sub)
+                        m = fmaxf(m, fmaxf(fmaxf(acc[qs][sub][0], acc[qs][sub][1]),
+                                           fmaxf(acc[qs][sub][2], acc[qs][sub][3])));
+                const bool hit = m >= 0.f;
+                if (__ballot(hit) && hit) {
+#pragma unroll
+                    for (int qs = 0; qs < QS; ++qs)
+#pragma unroll
+                        for (int sub = 0; sub < SUBS; ++sub)
 #pragma unroll
                             for (int r = 0; r < 4; ++r) {
-                                if ((acc[qs][sub][r] - bx[sub]) >= av[r]) {
+                                if (acc[qs][sub][r] >= 0.f) {
                                     const int q = t * QT + qs * 16 + kg * 4 + r;
                                     const long long x = xb0 + sub * 16 + col;
                                     if (q < M && x < N) {
-                                        const uint32_t pos = atomicAdd(&S.hdr->n_cand, 1u);
-                                        if (pos < S.cand_cap) S.cand[pos] = make_uint2((uint32_t)q, (uint32_t)x);
+                                        const uint32_t p = atomicAdd(&ccount, 1u);
+                                        if (p < (uint32_t)kCandStage) {
+                                            cbuf[p] = make_uint2((uint32_t)q, (uint32_t)x);
+                                        } else {  // more than the stage holds in one tile
+                                            const uint32_t pos = atomicAdd(&S.hdr->n_cand, 1u);
+                                            if (pos < S.cand_cap) S.cand[pos] = make_uint2((uint32_t)q, (uint32_t)x);
+                                        }
                                     }
                                 }
                             }
-                    }
                 }
             }
-            if (more) stage_store(buf ^ 1, pre, pa);
+            if (more) stage_store(buf ^ 1, pre, bias);
             __syncthreads();
+            if (ccount >= (uint32_t)(kCandStage / 2)) flush_cands();  // uniform: read after the barrier
         }
     }
+    __syncthreads();
+    if (ccount) flush_cands();
 }
 
-template <int KS, int QT>
-static hipError_t launch_screen_t(const ScreenArgs& s, int grid, hipStream_t st)
+template <int KS>
+static hipError_t launch_screen_ks(const ScreenArgs& s, ScreenShape shape, hipStream_t st)
 {
-    k_screen<KS, QT><<<grid, 256, 0, st>>>(s);
+    const int grid = shape.grid > 0 ? shape.grid : 256;
+    if (shape.subs == 2) {
+        if (shape.qt == 64) k_screen<KS, 64, 2><<<grid, 256, 0, st>>>(s);
+        else k_screen<KS, 32, 2><<<grid, 256, 0, st>>>(s);
+    } else {
+        if (shape.qt == 64) k_screen<KS, 64, 4><<<grid, 256, 0, st>>>(s);
+        else k_screen<KS, 32, 4><<<grid, 256, 0, st>>>(s);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_screen(const ScreenArgs& s, int np, ScreenShape shape, hipStream_t st)
 {
-    const int ks = np / 32;
-    const int grid = shape.grid > 0 ? shape.grid : 512;
-    const bool q64 = shape.qt == 64;
-    switch (ks) {
-    case 1: return q64 ? launch_screen_t<1, 64>(s, grid, st) : launch_screen_t<1, 32>(s, grid, st);
-    case 2: return q64 ? launch_screen_t<2, 64>(s, grid, st) : launch_screen_t<2, 32>(s, grid, st);
-    case 3: return q64 ? launch_screen_t<3, 64>(s, grid, st) : launch_screen_t<3, 32>(s, grid, st);
-    case 4: return q64 ? launch_screen_t<4, 64>(s, grid, st) : launch_screen_t<4, 32>(s, grid, st);
-    case 5: return q64 ? launch_screen_t<5, 64>(s, grid, st) : launch_screen_t<5, 32>(s, grid, st);
-    case 6: return q64 ? launch_screen_t<6, 64>(s, grid, st) : launch_screen_t<6, 32>(s, grid, st);
-    case 7: return q64 ? launch_screen_t<7, 64>(s, grid, st) : launch_screen_t<7, 32>(s, grid, st);
-    case 8: return q64 ? launch_screen_t<8, 64>(s, grid, st) : launch_screen_t<8, 32>(s, grid, st);
+    switch (np / 32) {
+    case 1: return launch_screen_ks<1>(s, shape, st);
+    case 2: return launch_screen_ks<2>(s, shape, st);
+    case 3: return launch_screen_ks<3>(s, shape, st);
+    case 4: return launch_screen_ks<4>(s, shape, st);
+    case 5: return launch_screen_ks<5>(s, shape, st);
+    case 6: return launch_screen_ks<6>(s, shape, st);
+    case 7: return launch_screen_ks<7>(s, shape, st);
+    case 8: return launch_screen_ks<8>(s, shape, st);
     default: return hipErrorInvalidValue;
     }
 }
 
 // ------------------------------------------------------------------------------------------
 // Re-score: float32 squared distance of every screen candidate (16 lanes per candidate, 64
-// points per step, early abandoning against the query's best-so-far), atomicMin into the
-// query's key, and the resolve band list.
+// points per step, early abandoning against the query's best-so-far), stored per candidate
+// and folded into the query's key with atomicMin. Then the band pass selects, against the
+// final best of each query, the candidates within the resolve band.
 // ------------------------------------------------------------------------------------------
 __device__ __forceinline__ float group16_sum_b(float v)
 {
@@ -314,7 +402,7 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs R)
         unsigned long long key = 0;
         if (l == 0) key = __hip_atomic_load(&b.bsf_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         key = __shfl(key, lane & ~15);
-        float thr = __double2float_ru((double)key_dist_b(key) * (1.0 + R.prune_rel) + 1e-25);
+        const float thr = __double2float_ru((double)key_dist_b(key) * (1.0 + R.prune_rel) + 1e-25);
         const float4* r4 = reinterpret_cast<const float4*>(R.X + (long long)e.y * n);
         const float4* q4 = reinterpret_cast<const float4*>(R.Q + (long long)e.x * n);
         float acc = 0.f;
@@ -330,13 +418,23 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs R)
             acc += group16_sum_b(part);
             if (acc > thr) { ab = true; break; }
         }
-        if (ab || l != 0) continue;
-        const unsigned long long mine = pack_key_b(acc, e.y);
-        const unsigned long long old = atomicMin(&b.bsf_key, mine);
-        const unsigned long long now = mine < old ? mine : old;
-        if ((double)acc <= (double)key_dist_b(now) * (1.0 + R.band_rel) + 1e-25) {
+        if (l != 0) continue;
+        R.cand_d2[c] = ab ? __builtin_inff() : acc;
+        if (!ab) atomicMin(&b.bsf_key, pack_key_b(acc, e.y));
+    }
+}
+
+__global__ __launch_bounds__(256) void k_band(RescoreArgs R)
+{
+    const uint32_t count = min(R.hdr->n_cand, R.cand_cap);
+    for (uint32_t c = blockIdx.x * 256u + threadIdx.x; c < count; c += gridDim.x * 256u) {
+        const float d = R.cand_d2[c];
+        if (!(d < __builtin_inff())) continue;
+        const uint2 e = R.cand[c];
+        BQuery& b = R.bq[e.x];
+        if ((double)d <= (double)key_dist_b(b.bsf_key) * (1.0 + R.band_rel) + 1e-25) {
             const uint32_t pos = atomicAdd(&b.n_band, 1u);
-            if (pos < kBandCap) b.band[pos] = make_uint2(e.y, __float_as_uint(acc));
+            if (pos < kBandCap) b.band[pos] = make_uint2(e.y, __float_as_uint(d));
         }
     }
 }
@@ -344,55 +442,54 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs R)
 hipError_t launch_rescore(const RescoreArgs& r, hipStream_t st)
 {
     k_rescore<<<512, 256, 0, st>>>(r);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    k_band<<<256, 256, 0, st>>>(r);
     return hipGetLastError();
 }
 
 // ------------------------------------------------------------------------------------------
-// Resolve: one wave per query. Every band entry within band_rel of the final float32 best is
-// re-scored in float64 with the fixed operation order (terms in parallel, one lane adds them in
-// ascending j); the smallest (squared distance, index) is written out. A query whose band list
-// overflowed is handed back to the host (fallback list) and answered by the per-query path.
+// Resolve: one wave per query (lane 0 works). Every band entry within band_rel of the final
+// float32 best is re-scored in float64 with the fixed operation order (ascending j:
+// d = q_j - x_j; t = d * d; acc = acc + t); the smallest (squared distance, index) is written
+// out. A query whose band list overflowed (exact ties beyond its capacity) or whose candidate
+// list overflowed is handed back to the host (fallback list) and answered by the per-query path.
 // ------------------------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void k_batch_resolve(RescoreArgs R, long long* __restrict__ out_idx,
                                                        double* __restrict__ out_dist)
 {
     const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
     const int q = blockIdx.x * 4 + w;
-    if (q >= R.M) return;  // wave-uniform
+    if (q >= R.M || lane != 0) return;
     BQuery& b = R.bq[q];
     const int n = R.n;
     if (b.err) {
-        if (lane == 0) { out_idx[q] = -1; out_dist[q] = __builtin_nan(""); }
-        return;
-    }
-    if (b.n_band > (uint32_t)kBandCap || R.hdr->n_cand > R.cand_cap) {
-        if (lane == 0) {
-            out_idx[q] = -2;
-            const uint32_t p = atomicAdd(&R.hdr->n_fallback, 1u);
-            R.fallback[p] = (uint32_t)q;
-        }
+        out_idx[q] = -1;
+        out_dist[q] = __builtin_nan("");
         return;
     }
     const unsigned long long key = b.bsf_key;
     const double band = (double)key_dist_b(key) * (1.0 + R.band_rel) + 1e-25;
     double bd = __builtin_inf();
     long long bi = -1;
-    const float* qv = R.Q + (long long)q * n;
-    if (lane != 0) return;
-    for (uint32_t e = 0; e < b.n_band; ++e) {
-        const uint2 v = b.band[e];
-        if ((double)__uint_as_float(v.y) > band) continue;
-        const float* x = R.X + (long long)v.x * n;
-        double acc = 0.0;
+    const bool overflow = b.n_band > (uint32_t)kBandCap || R.hdr->n_cand > R.cand_cap;
+    if (!overflow) {
+        const float* qv = R.Q + (long long)q * n;
+        for (uint32_t e = 0; e < b.n_band; ++e) {
+            const uint2 v = b.band[e];
+            if ((double)__uint_as_float(v.y) > band) continue;
+            const float* x = R.X + (long long)v.x * n;
+            double acc = 0.0;
 #pragma unroll 8
-        for (int j = 0; j < n; ++j) {
-            const double d = (double)qv[j] - (double)x[j];
-            const double t = d * d;
-            acc = acc + t;
+            for (int j = 0; j < n; ++j) {
+                const double d = (double)qv[j] - (double)x[j];
+                const double t = d * d;
+                acc = acc + t;
+            }
+            if (acc < bd || (acc == bd && (long long)v.x < bi)) { bd = acc; bi = v.x; }
         }
-        if (acc < bd || (acc == bd && (long long)v.x < bi)) { bd = acc; bi = v.x; }
     }
-    if (bi < 0) {  // no completed candidate (cannot happen with a seed): per-query path
+    if (bi < 0) {  // overflow, or no completed candidate (cannot happen with a seed)
         out_idx[q] = -2;
         const uint32_t p = atomicAdd(&R.hdr->n_fallback, 1u);
         R.fallback[p] = (uint32_t)q;

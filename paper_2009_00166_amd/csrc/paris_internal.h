@@ -145,6 +145,7 @@ struct RescoreArgs {
     int n, M;
     BQuery* bq;
     const uint2* cand;
+    float* cand_d2;        // float32 squared distance of each candidate (+inf: abandoned)
     uint32_t cand_cap;
     BatchHdr* hdr;
     double prune_rel, band_rel;
@@ -154,6 +155,7 @@ struct RescoreArgs {
 struct ScreenShape {
     int qt;     // queries per LDS tile: 32 or 64
     int grid;   // persistent blocks
+    int subs;   // 16-series subtiles per wave held in registers: 2 (two waves per SIMD) or 4
 };
 
 hipError_t launch_to_bf16(const float* X, long long N, int n, int np, uint16_t* Xb, float* xn, hipStream_t st);

@@ -24,7 +24,7 @@ def _gamma(k, u):
 def _screen_margin(n, np_):
     """The bound of the screen as documented: |d~^2 - d^2| <= c (qn + xn)."""
     ub = 2.0 ** -8
-    c = (2 * ub + ub * ub) + 2 * _gamma(np_ + 16, 2.0 ** -23) * (1 + ub) ** 2 + 2 * _gamma(n, 2.0 ** -24) \
+    c = (2 * ub + ub * ub) + 6 * _gamma(np_ + 48, 2.0 ** -23) * (1 + ub) ** 2 + 2 * _gamma(n, 2.0 ** -24) \
         + 16 * 2.0 ** -24
     return 1.05 * c + 32 * 2.0 ** -24
 
