@@ -5,7 +5,8 @@ tests, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of ``bench.py`` 
 It shares no code, headers, tables or constant generators with the GPU library: its Gaussian
 breakpoints come from its own high-precision computation (``breakpoints.py``), its arithmetic
 from ``reference.py`` (numpy, float64) and ``paris_oracle.c`` (plain C, float64, built with
-``-ffp-contract=off``).
+``-ffp-contract=off``); the learned seed's network (forward, back-propagation, Adam, top
+leaves, labels) from ``mlp.py`` (numpy, float64).
 
 Parity pins: every function here is checked by ``tests/test_oracle_*.py`` against values that
 do not come from the oracle itself (closed forms, the paper's printed word example, library

@@ -93,3 +93,35 @@ def test_strict_tie_rule_is_caught(monkeypatch):
     monkeypatch.setattr(T_search, "nn_bruteforce", last_index_nn)
     _fails(T_search.test_twin_ties_and_degenerate)
     monkeypatch.setattr(T_search, "nn_bruteforce", real_nn)
+
+
+# ---- learned-seed oracle: back-propagation slips must fail the finite-difference pins ----------
+import oracle.mlp as MLP  # noqa: E402
+import tests.test_oracle_mlp as T_mlp  # noqa: E402
+
+
+def _patched_grad(monkeypatch, edit):
+    real = MLP.loss_and_grad
+
+    def wrong(theta, P, y, n_out, rounding=True):
+        L, g = real(theta, P, y, n_out, rounding)
+        parts = MLP.unpack(g.copy(), n_out)
+        edit(parts)
+        return L, MLP.pack(parts, n_out)
+
+    monkeypatch.setattr(MLP, "loss_and_grad", wrong)
+
+
+def test_mlp_transposed_hidden_gradient_is_caught(monkeypatch):
+    _patched_grad(monkeypatch, lambda p: p.__setitem__("W2", p["W2"].T.copy()))
+    _fails(T_mlp.test_gradient_matches_finite_differences)
+
+
+def test_mlp_dropped_bias_gradient_is_caught(monkeypatch):
+    _patched_grad(monkeypatch, lambda p: p.__setitem__("b1", np.zeros_like(p["b1"])))
+    _fails(T_mlp.test_gradient_matches_finite_differences)
+
+
+def test_mlp_output_gradient_sign_is_caught(monkeypatch):
+    _patched_grad(monkeypatch, lambda p: p.__setitem__("W3", -p["W3"]))
+    _fails(T_mlp.test_gradient_matches_finite_differences)
