@@ -163,7 +163,8 @@ paris_status paris_query_batch(paris_index *idx, const float *queries_dev, int64
  * Batched pipeline resources (the batched pattern of the paper's worker pools: many queries,
  * one launch). paris_batch_workspace_size gives the bytes for chunks of up to max_batch queries
  * (1 .. 65536): a bfloat16 copy of the collection [N][roundup(length, 32)], its norms, the
- * query buffers, per-query states and a candidate list of 4096 * max_batch entries.
+ * query buffers, per-query states, a candidate list of min(4096 * max_batch, 2^32 - 16) entries
+ * (12 bytes each: query, series, float32 re-scored distance) and per-query learned-seed leaves.
  * paris_batch_attach borrows that device memory (256-byte aligned) for the life of the handle
  * (or until the next attach), converts the collection, times the screen's tile shapes and
  * captures the pipeline into a HIP graph. Synchronous on hip_stream.
@@ -225,6 +226,105 @@ paris_status paris_get_batch_timing(const paris_index *idx, double *ms_out4, int
 
 /* Release the handle (the borrowed buffers are not touched). NULL is accepted. */
 paris_status paris_free(paris_index *idx);
+
+/*
+ * ---- Learned best-so-far seed ------------------------------------------------------------
+ * The approximate search that opens exact search (Section 3.3) visits the one leaf selected by
+ * the query's own iSAX word. With a seed network attached to an EQUAL_COUNT index, it instead
+ * visits the 8 leaves with the highest scores of a 16 -> 256 -> 256 -> n_leaves perceptron on
+ * the query's PAA (ReLU hidden layers; ties by lowest leaf id), refining in every run of 512
+ * sorted positions of those leaves the member with the smallest lower bound. The seed stays a
+ * true distance, so answers are unchanged; only the pruning power of the first best-so-far
+ * changes. The network is not part of the paper: it is trained with the calls below on
+ * (query features, leaf of the query's exact nearest neighbour) pairs from the exact search.
+ *
+ * Parameters: one float32 vector of paris_mlp_param_count() values, packed as
+ *   W1 [256][16], b1 [256], W2 [256][256], b2 [256], W3 [n_leaves][256], b3 [n_leaves]
+ * (row-major, rows indexed by output unit; 1,122,816 values at 4096 leaves).
+ * Arithmetic: products take bfloat16 operands (weights rounded to nearest even from the
+ * float32 master copy, hidden activations and back-propagated gradients likewise; the
+ * 16 features stay float32) with float32 accumulation; biases are float32. Loss: mean softmax
+ * cross-entropy. Optimiser: Adam (Kingma and Ba 2015, Algorithm 1) on the master copy.
+ * A network handle holds its own device memory (parameters, Adam moments, and activations for
+ * max_rows rows). One call at a time per network and per index using it.
+ */
+typedef struct paris_mlp paris_mlp;  /* opaque, library-owned host handle */
+
+typedef struct paris_adam {
+    float lr;      /* step size, > 0                    */
+    float beta1;   /* first-moment decay, in [0, 1)     */
+    float beta2;   /* second-moment decay, in [0, 1)    */
+    float eps;     /* denominator offset, > 0           */
+} paris_adam;
+
+/* count (host out): parameters of a network scoring n_leaves leaves (multiple of 64,
+   64 .. 65536). */
+paris_status paris_mlp_param_count(int32_t n_leaves, int64_t *count);
+
+/* Create a network with all-zero parameters. max_rows (multiple of 64, 64 .. 65536) bounds
+   the rows of one training step; inference on more rows runs in pieces of max_rows.
+   Synchronous. Release with paris_mlp_free. */
+paris_status paris_mlp_create(int32_t n_leaves, int32_t max_rows, paris_mlp **out);
+
+/* Copy parameters in (params_dev float32 [count], device) and reset Adam's moments and step
+   count; or copy them out. Asynchronous on hip_stream. */
+paris_status paris_mlp_set_params(paris_mlp *net, const float *params_dev, void *hip_stream);
+paris_status paris_mlp_get_params(const paris_mlp *net, float *params_dev, void *hip_stream);
+
+/* Features of queries [n_queries][length] (device, float32; length a multiple of 16, <= 2048):
+   features_dev float32 [n_queries][16] receives each query's PAA (Section 2.2), summed in
+   float64 in ascending position and divided by length / 16, then rounded to float32.
+   Asynchronous. */
+paris_status paris_query_features(const float *queries_dev, int64_t n_queries, int32_t length,
+                                  float *features_dev, void *hip_stream);
+
+/* logits_dev float32 [rows][n_leaves] (device out) of features_dev float32 [rows][16].
+   Asynchronous. */
+paris_status paris_mlp_forward(paris_mlp *net, const float *features_dev, int64_t rows,
+                               float *logits_dev, void *hip_stream);
+
+/* leaves_dev int32 [rows][8] (device out): the 8 best-scoring leaves of every row, best first,
+   equal logits by lowest leaf id. Asynchronous. */
+paris_status paris_mlp_top_leaves(paris_mlp *net, const float *features_dev, int64_t rows,
+                                  int32_t *leaves_dev, void *hip_stream);
+
+/* Gradient of the mean loss over rows (1 .. max_rows) examples, packed like the parameters,
+   into grad_dev float32 [count] (device out); loss_dev (device out, may be NULL) receives the
+   mean loss. Example r is features_dev[s] with label labels_dev[s] (leaf id, int32), where
+   s = rows_sel_dev[r] if rows_sel_dev (device int32 [rows]) is not NULL, else s = r.
+   Asynchronous. */
+paris_status paris_mlp_grad(paris_mlp *net, const float *features_dev, const int32_t *labels_dev,
+                            const int32_t *rows_sel_dev, int64_t rows, float *grad_dev,
+                            float *loss_dev, void *hip_stream);
+
+/* One training step: the gradient as in paris_mlp_grad, then one Adam update of the master
+   parameters and their bfloat16 copy. Asynchronous. */
+paris_status paris_mlp_train_step(paris_mlp *net, const float *features_dev, const int32_t *labels_dev,
+                                  const int32_t *rows_sel_dev, int64_t rows, const paris_adam *opt,
+                                  float *loss_dev, void *hip_stream);
+
+/* One Adam update of the master parameters (and their bfloat16 copy) with a caller-supplied
+   gradient grad_dev float32 [count] (device), packed like the parameters: e.g. a gradient
+   summed over several devices' paris_mlp_grad results. Asynchronous. */
+paris_status paris_mlp_apply(paris_mlp *net, const float *grad_dev, const paris_adam *opt, void *hip_stream);
+
+/* Release a network; indexes using it go back to the plain seed. NULL is accepted. */
+paris_status paris_mlp_free(paris_mlp *net);
+
+/* Training labels: leaves_dev int32 [count] (device out) receives the EQUAL_COUNT leaf holding
+   each series index of series_dev int64 [count] (device; -1 for an index outside the
+   collection): the leaf whose slice [floor(l N / n_leaves), floor((l+1) N / n_leaves)) of the
+   order sorted by (leaf key, index) contains the series. PARIS_EINVAL on a ROOT16 index.
+   Asynchronous. */
+paris_status paris_leaf_of(const paris_index *idx, const int64_t *series_dev, int64_t count,
+                           int32_t *leaves_dev, void *hip_stream);
+
+/* Attach (enabled = 1) or detach (enabled = 0, or net = NULL) the learned seed for both
+   paris_query_exact and paris_query_batch. The index must be EQUAL_COUNT with n_leaves equal
+   to the network's, on the same device (else PARIS_EINVAL). The network is borrowed: it must
+   outlive its use. With a batch workspace attached, the pipeline graph is captured again
+   (synchronous). */
+paris_status paris_set_seed_model(paris_index *idx, paris_mlp *net, int32_t enabled);
 
 /* Static English text for a status code. */
 const char *paris_status_string(paris_status s);

@@ -220,6 +220,22 @@ class Index:
         check(load_library().paris_get_batch_timing(self._h, ms, ctypes.byref(n)), "paris_get_batch_timing")
         return list(ms), int(n.value)
 
+    # -- learned seed ------------------------------------------------------------------------
+    def leaf_of(self, series_idx, stream=None):
+        """int32 [k] equal-count leaf of every series index (int64 device tensor)."""
+        torch = _torch()
+        ip = _dev_ptr(series_idx, torch.int64, 1, "series indices")
+        out = torch.empty(series_idx.shape[0], dtype=torch.int32, device=series_idx.device)
+        check(load_library().paris_leaf_of(self._h, ip, int(series_idx.shape[0]),
+                                           ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)), "paris_leaf_of")
+        return out
+
+    def set_seed_model(self, model, enabled: bool = True) -> None:
+        """Use (or stop using) a trained SeedModel for the approximate-search seed."""
+        check(load_library().paris_set_seed_model(self._h, model._h if model is not None else None,
+                                                  1 if enabled else 0), "paris_set_seed_model")
+        self._seed_model = model if enabled else None   # keep the network alive while in use
+
     def close(self):
         if getattr(self, "_h", None) is not None and self._h.value:
             load_library().paris_free(self._h)
@@ -230,6 +246,11 @@ class Index:
             self.close()
         except Exception:
             pass
+
+
+from .learned import SeedModel, init_params, query_features, train_seed_model  # noqa: E402,F401
+
+__all__ += ["SeedModel", "init_params", "query_features", "train_seed_model"]
 
 
 def build(series, cfg: ParisConfig | None = None, stream=None, **cfg_kw) -> Index:

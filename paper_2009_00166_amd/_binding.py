@@ -45,6 +45,11 @@ class ParisQueryInfo(ctypes.Structure):
                 ("win_lo", ctypes.c_int64), ("win_hi", ctypes.c_int64)]
 
 
+class ParisAdam(ctypes.Structure):
+    _fields_ = [("lr", ctypes.c_float), ("beta1", ctypes.c_float), ("beta2", ctypes.c_float),
+                ("eps", ctypes.c_float)]
+
+
 # (name, restype, argtypes) for every entry point declared in include/paris.h
 _P, _I64, _I32, _F32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_float
 SIGNATURES = [
@@ -66,6 +71,19 @@ SIGNATURES = [
     ("paris_get_timing", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     ("paris_get_batch_timing", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     ("paris_free", ctypes.c_int, [_P]),
+    ("paris_mlp_param_count", ctypes.c_int, [_I32, ctypes.POINTER(ctypes.c_int64)]),
+    ("paris_mlp_create", ctypes.c_int, [_I32, _I32, ctypes.POINTER(_P)]),
+    ("paris_mlp_set_params", ctypes.c_int, [_P, _P, _P]),
+    ("paris_mlp_get_params", ctypes.c_int, [_P, _P, _P]),
+    ("paris_query_features", ctypes.c_int, [_P, _I64, _I32, _P, _P]),
+    ("paris_mlp_forward", ctypes.c_int, [_P, _P, _I64, _P, _P]),
+    ("paris_mlp_top_leaves", ctypes.c_int, [_P, _P, _I64, _P, _P]),
+    ("paris_mlp_grad", ctypes.c_int, [_P, _P, _P, _P, _I64, _P, _P, _P]),
+    ("paris_mlp_train_step", ctypes.c_int, [_P, _P, _P, _P, _I64, ctypes.POINTER(ParisAdam), _P, _P]),
+    ("paris_mlp_apply", ctypes.c_int, [_P, _P, ctypes.POINTER(ParisAdam), _P]),
+    ("paris_mlp_free", ctypes.c_int, [_P]),
+    ("paris_leaf_of", ctypes.c_int, [_P, _P, _I64, _P, _P]),
+    ("paris_set_seed_model", ctypes.c_int, [_P, _P, _I32]),
     ("paris_status_string", ctypes.c_char_p, [ctypes.c_int]),
 ]
 

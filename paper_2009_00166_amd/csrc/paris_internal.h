@@ -93,6 +93,8 @@ struct QueryArgs {
     Margins mg;
     QResult* host_res;  // pinned host memory mapped for the device (may be null): the result is
                         // also stored there, so the host needs no copy after synchronising
+    const int32_t* leaves;  // learned seed, per-query path: [kTopLeaves] leaf ids (or null)
+    int learned_cpl;        // > 0: learned seed over kTopLeaves leaves of up to this many chunks
 };
 
 // ---- batched path ----
@@ -116,6 +118,7 @@ struct SeedBatch {
     BQuery* bq;           // [M]
     uint16_t* qb;         // [M][np] bfloat16 copies, zero padded
     int np;               // n rounded up to a multiple of 32
+    const int32_t* leaves;  // learned seed: [M][kTopLeaves] leaf ids (used when learned_cpl > 0)
 };
 
 struct BatchHdr {
@@ -165,6 +168,83 @@ hipError_t launch_screen(const ScreenArgs& s, int np, ScreenShape shape, hipStre
 hipError_t launch_rescore(const RescoreArgs& r, hipStream_t st);
 hipError_t launch_batch_resolve(const RescoreArgs& r, long long* out_idx, double* out_dist, hipStream_t st);
 
+// ---- learned seed ----
+constexpr int kMlpIn = 16;          // PAA features
+constexpr int kMlpHid = 256;        // hidden width
+constexpr int kTopLeaves = 8;       // leaves visited by the learned seed
+constexpr int kMaxLeaves = 65536;   // largest leaf count the network can score
+
+// Offsets (in elements) of the packed parameter vector [W1 (256x16), b1, W2 (256x256), b2,
+// W3 (n_out x 256), b3], rows indexed by output unit.
+struct MlpOffsets {
+    long long w1, b1, w2, b2, w3, b3, total;
+};
+
+inline MlpOffsets mlp_offsets(int n_out)
+{
+    MlpOffsets o;
+    o.w1 = 0;
+    o.b1 = o.w1 + (long long)kMlpHid * kMlpIn;
+    o.w2 = o.b1 + kMlpHid;
+    o.b2 = o.w2 + (long long)kMlpHid * kMlpHid;
+    o.w3 = o.b2 + kMlpHid;
+    o.b3 = o.w3 + (long long)n_out * kMlpHid;
+    o.total = o.b3 + n_out;
+    return o;
+}
+
+struct MlpNet {
+    const float* master;    // float32 parameters (biases are read from here)
+    const uint16_t* wb;     // bfloat16 mirror of the same vector (weights are read from here)
+    int n_out;
+    MlpOffsets off;
+};
+
+struct MlpQueryScratch {
+    float* z;               // [n_out] logits of the current query
+    uint32_t* counter;      // blocks finished (re-armed by the last block)
+    int32_t* leaves;        // [kTopLeaves] result
+};
+
+enum GemmEpilogue { kEpiBiasReluBf16 = 0, kEpiBiasF32 = 1, kEpiMask = 2, kEpiF32 = 3 };
+
+struct GemmArgs {
+    const uint16_t* A;
+    long long lda;
+    const uint16_t* B;
+    long long ldb;
+    int M, N, K;
+    const float* bias;      // kEpiBiasReluBf16, kEpiBiasF32: [N]
+    const uint16_t* mask;   // kEpiMask: bfloat16 activation [M][ldm]; zero entries zero the output
+    long long ldm;
+    float* Cf;              // float32 output (kEpiBiasF32, kEpiMask, kEpiF32)
+    uint16_t* Cb;           // bfloat16 output (kEpiBiasReluBf16, kEpiMask)
+    long long ldc;
+};
+
+struct AdamArgs {
+    float lr, beta1, beta2, eps;
+    float bc1, bc2;         // 1 - beta1^t, 1 - beta2^t
+};
+
+hipError_t launch_paa_features(const float* Q, long long M, long long Mpad, int n, float* P, hipStream_t st);
+hipError_t launch_l1_fwd(const MlpNet& net, const float* P, const int32_t* sel, int rows_real, int rows_pad,
+                         uint16_t* H1, hipStream_t st);
+hipError_t launch_l1_bwd(const float* G1, const float* P, const int32_t* sel, int rows_real, float* dW1,
+                         hipStream_t st);
+hipError_t launch_gemm(const GemmArgs& g, int ta, int tb, int epi, hipStream_t st);
+hipError_t launch_softmax_ce(const float* Z, int n_out, const int32_t* y, const int32_t* sel, int rows_real,
+                             int rows_pad, float* G, uint16_t* Gb, float* loss_row, hipStream_t st);
+hipError_t launch_colsum(const float* G, int rows, int cols, float* out, hipStream_t st);
+hipError_t launch_mean_loss(const float* loss_row, int rows, float* out, hipStream_t st);
+hipError_t launch_adam(float* p, const float* g, float* m, float* v, uint16_t* wb, long long count,
+                       const AdamArgs& a, hipStream_t st);
+hipError_t launch_mirror(const float* p, uint16_t* wb, long long count, hipStream_t st);
+hipError_t launch_topk(const float* Z, int rows, int n_out, int k, int32_t* out, hipStream_t st);
+hipError_t launch_mlp_query(const MlpNet& net, const float* q, int n, const MlpQueryScratch& s, hipStream_t st);
+hipError_t launch_leaf_of(const uint8_t* sax, const unsigned long long* keys, const uint32_t* perm, long long N,
+                          int n_leaves, const long long* idx, long long count, int32_t* out, hipStream_t st);
+
 // Launch shape of the lower-bound scan (chosen by the autotuner on first use).
 struct ScanShape {
     int threads;   // 256 or 512
@@ -173,6 +253,7 @@ struct ScanShape {
 };
 
 hipError_t launch_reset(const QueryArgs& a, hipStream_t st);
+hipError_t launch_touch(const void* p, size_t bytes, uint32_t* sink, hipStream_t st);
 // query summaries, tables, window, and the lower-bound-guided approximate-search seed
 hipError_t launch_prepare_seed(const QueryArgs& a, const float* q, hipStream_t st);
 hipError_t launch_prepare_seed_batch(const QueryArgs& a, const SeedBatch& b, int n_queries, hipStream_t st);

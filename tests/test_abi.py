@@ -106,3 +106,30 @@ def test_status_strings():
     for s in range(-6, 1):
         assert lib.paris_status_string(s)
     assert lib.paris_status_string(-99) == b"unknown status"
+
+
+def test_seed_network_argument_errors_before_any_launch():
+    lib = paris.load_library()
+    cnt = ctypes.c_int64(0)
+    assert lib.paris_mlp_param_count(4096, ctypes.byref(cnt)) == B.PARIS_OK and cnt.value == 1_122_816
+    for bad in (0, 8, 100, 65600):
+        assert lib.paris_mlp_param_count(bad, ctypes.byref(cnt)) == B.PARIS_EINVAL
+    h = ctypes.c_void_p()
+    for nl, rows in ((100, 64), (4096, 100), (4096, 0), (0, 64)):
+        assert lib.paris_mlp_create(nl, rows, ctypes.byref(h)) == B.PARIS_EINVAL
+    assert lib.paris_mlp_create(4096, 64, None) == B.PARIS_EINVAL
+    null = ctypes.c_void_p()
+    opt = B.ParisAdam(1e-3, 0.9, 0.999, 1e-8)
+    assert lib.paris_mlp_set_params(null, null, null) == B.PARIS_ESTATE
+    assert lib.paris_mlp_forward(null, null, 1, null, null) == B.PARIS_ESTATE
+    assert lib.paris_mlp_top_leaves(null, null, 1, null, null) == B.PARIS_ESTATE
+    assert lib.paris_mlp_grad(null, null, null, null, 1, null, null, null) == B.PARIS_ESTATE
+    assert lib.paris_mlp_train_step(null, null, null, null, 1, ctypes.byref(opt), null, null) == B.PARIS_ESTATE
+    assert lib.paris_mlp_apply(null, null, ctypes.byref(opt), null) == B.PARIS_ESTATE
+    assert lib.paris_mlp_free(null) == B.PARIS_OK
+    assert lib.paris_leaf_of(null, null, 1, null, null) == B.PARIS_ESTATE
+    assert lib.paris_set_seed_model(null, null, 0) == B.PARIS_ESTATE
+    assert lib.paris_query_features(null, 1, 256, null, null) == B.PARIS_EINVAL
+    fake = ctypes.c_void_p(16)
+    for n in (0, 8, 250, 4096):
+        assert lib.paris_query_features(fake, 1, n, fake, null) == B.PARIS_EINVAL
