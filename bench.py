@@ -8,7 +8,9 @@ the timed region (the build time is reported beside). Inputs are resident in HBM
 Prints one JSON line. Options: --gpus N (only 1 is supported: this build measures one GPU),
 --steps K, --warmup W, --queries Q, --series N, --length n, --no-cpu-baseline, --no-batched,
 --batch B, --batch-steps K (the batched section: batches of B queries through paris_query_batch),
---cold-queries C (the lower-bound scan timed with caches flushed before each of C queries).
+--cold-queries C (the lower-bound scan timed with caches flushed before each of C queries),
+--no-learned, --train-queries T, --epochs E, --eval-queries V (the learned-seed section: a seed
+network trained on T exact labels, evaluated on V hard queries and in the batched pipeline).
 """
 from __future__ import annotations
 
@@ -63,6 +65,10 @@ def main() -> int:
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--batch-steps", type=int, default=3)
     ap.add_argument("--cold-queries", type=int, default=200)
+    ap.add_argument("--no-learned", action="store_true")
+    ap.add_argument("--train-queries", type=int, default=200_000)
+    ap.add_argument("--epochs", type=int, default=20)
+    ap.add_argument("--eval-queries", type=int, default=1000)
     args = ap.parse_args()
     args._plain_qps = None
 
@@ -168,6 +174,8 @@ def main() -> int:
     }
     if not args.no_batched:
         rec["batched"] = batched_section(index, X, args)
+    if not args.no_learned:
+        rec["learned"] = learned_section(Xd, X, args)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")
         rec["cpu_baseline"] = cpu_baseline(X, Q, answers, min(args.cpu_queries, M), args.cpu_threads)
@@ -259,6 +267,101 @@ def batched_section(index, X, args):
         "fallback_queries": st["resolved"],
         "workspace_bytes": ws_bytes,
         "answers_match_source_frac": float(np.mean(answers == src)),
+    }
+
+
+def learned_section(Xd, X, args):
+    """The learned best-so-far seed on the same collection: an index with 4096 equal-count leaves,
+    a 16-256-256-4096 network trained on exact (query, nearest-neighbour leaf) pairs from the
+    training stream (noise sigma ~ U[0.05, 0.5]), then hard queries (sigma 0.5) through the
+    per-query path with the plain one-leaf seed and with the learned 8-leaf seed, and one batch
+    of the batched workload through the pipeline with the learned seed."""
+    import numpy as np
+    import torch
+
+    import paper_2009_00166_amd as paris
+    import synth
+    N, n = X.shape
+    n_leaves = 4096
+    idx = paris.build(Xd, leaf_mode=1, n_leaves=n_leaves)
+    idx.attach_batch(max_batch=args.batch)
+    Qt, _, _ = synth.training_queries(X, args.train_queries, seed=0)
+    Qtd = torch.from_numpy(Qt).cuda()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    F, y, _ = paris.learned.exact_labels(idx, Qtd)
+    torch.cuda.synchronize()
+    label_s = time.perf_counter() - t0
+    log(f"labelled {args.train_queries} training queries in {label_s:.1f}s")
+    net = paris.SeedModel(n_leaves, max_rows=1024, params=paris.init_params(n_leaves, seed=0))
+    t1 = time.perf_counter()
+    hist = paris.train_seed_model(net, F, y, epochs=args.epochs, batch=1024, lr=2e-3, seed=0)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t1
+    steps = args.epochs * ((args.train_queries + 1023) // 1024)
+    log(f"trained {args.epochs} epochs ({steps} steps) in {train_s:.1f}s, loss {hist[0]:.3f} -> {hist[-1]:.3f}")
+    del Qtd, F, y
+
+    Qe, _, _ = synth.noisy_queries(X, args.eval_queries, seed=2, sigma=0.5)
+    Qed = torch.from_numpy(Qe).cuda()
+    rows = [Qed[m] for m in range(Qe.shape[0])]
+
+    def per_query(enabled):
+        idx.set_seed_model(net, enabled)
+        for m in range(min(50, len(rows))):
+            idx.query(rows[m])
+        torch.cuda.synchronize()
+        ta = time.perf_counter()
+        ans = [idx.query(r)[0] for r in rows]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - ta
+        st = [idx.query(r, with_stats=True)[2] for r in rows[:300]]
+        nn = np.array([idx.query(r)[1] for r in rows[:300]])
+        seed = np.array([x["seed_dist"] for x in st])
+        return ans, {"queries_per_s": len(rows) / dt,
+                     "mean_lb_survivors": float(np.mean([x["lb_survivors"] for x in st])),
+                     "mean_refined": float(np.mean([x["refined"] for x in st])),
+                     "mean_seed_over_nn_distance": float(np.mean(seed / np.maximum(nn, 1e-30)))}
+
+    a0, plain = per_query(False)
+    a1, learned = per_query(True)
+    log(f"hard queries: plain {plain['queries_per_s']:.0f} q/s, learned {learned['queries_per_s']:.0f} q/s")
+
+    B = args.batch
+    Qb, _, _ = synth.noisy_queries(X, B, seed=1, sigma=(0.01, 0.5))
+    Qbd = torch.from_numpy(Qb).cuda()
+    I = torch.empty(B, dtype=torch.int64, device="cuda")
+    D = torch.empty(B, dtype=torch.float64, device="cuda")
+    res = {}
+    for enabled in (False, True):
+        idx.set_seed_model(net, enabled)
+        idx.query_batch(Qbd, out=(I, D))
+        torch.cuda.synchronize()
+        tb = time.perf_counter()
+        for _ in range(args.batch_steps):
+            idx.query_batch(Qbd, out=(I, D))
+        torch.cuda.synchronize()
+        el = time.perf_counter() - tb
+        _, _, st = idx.query_batch(Qbd, out=(I, D), with_stats=True)
+        res[enabled] = {"queries_per_s": B * args.batch_steps / el, "ms_per_batch": el / args.batch_steps * 1e3,
+                        "screen_survivors_per_query": st["lb_survivors"] / B, "fallback_queries": st["resolved"],
+                        "answers": I.cpu().numpy()}
+    same_batch = bool(np.array_equal(res[False].pop("answers"), res[True].pop("answers")))
+    idx.set_seed_model(None, False)
+    net.close()
+    idx.close()
+    return {
+        "workload": f"{N} x {n} random walks, {n_leaves} equal-count leaves; network 16-256-256-{n_leaves} "
+                    f"(bfloat16 MFMA, float32 accumulate) trained {args.epochs} epochs on {args.train_queries} "
+                    "exact labels (sigma ~ U[0.05, 0.5]); evaluation: hard queries (sigma 0.5) one at a time, "
+                    f"and batches of {B} (sigma ~ U[0.01, 0.5])",
+        "label_s": label_s, "train_s": train_s, "train_steps": steps, "loss_first_epoch": hist[0],
+        "loss_last_epoch": hist[-1],
+        "hard_queries": {"count": len(rows), "plain_seed": plain, "learned_seed": learned,
+                         "answers_identical": bool(np.array_equal(np.array(a0), np.array(a1)))},
+        "batched": {"plain_seed": res[False], "learned_seed": res[True], "answers_identical": same_batch,
+                    "learned_vs_plain_per_query_path": (res[True]["queries_per_s"] / args._plain_qps
+                                                        if args._plain_qps else None)},
     }
 
 
