@@ -161,6 +161,8 @@ struct paris_index {
     QResult* host_res_dev;   // its device address
     Margins mg;
     ScanShape scan;
+    int refine_blocks;
+    int refine_lanes;
     bool timing;
     hipEvent_t ev[4];
     double phase_ms[3];
@@ -218,6 +220,8 @@ QueryArgs args_for(const paris_index* h)
     a.host_res = nullptr;
     a.leaves = nullptr;
     a.learned_cpl = 0;
+    a.refine_blocks = h->refine_blocks;
+    a.refine_lanes = h->refine_lanes;
     return a;
 }
 
@@ -835,6 +839,16 @@ paris_status paris_build(const float* series_dev, int64_t n_series, int32_t leng
     h->plan = plan;
     h->mg = margins_for_length(length);
     h->scan = ScanShape{512, 4, 4};
+    h->refine_blocks = kRefineBlocks;
+    if (const char* rb = std::getenv("PARIS_REFINE_BLOCKS")) {
+        const int v = std::atoi(rb);
+        if (v >= 16 && v <= 4096) h->refine_blocks = v;
+    }
+    h->refine_lanes = 8;
+    if (const char* rl = std::getenv("PARIS_REFINE_LANES")) {
+        const int v = std::atoi(rl);
+        if (v == 4 || v == 8 || v == 16) h->refine_lanes = v;
+    }
     h->timing = false;
     for (int k = 0; k < 4; ++k) h->ev[k] = nullptr;
     for (int k = 0; k < 3; ++k) h->phase_ms[k] = 0.0;

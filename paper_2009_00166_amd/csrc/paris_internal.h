@@ -14,7 +14,11 @@ constexpr int kCoarse = 32;        // 5-bit prefix alphabet of the coarse lower-
 constexpr int kMaxLength = 2048;   // longest series the summarise kernel stages in LDS
 constexpr int kSeedChunk = 512;    // sorted positions per seed block: its smallest bound is refined
 constexpr int kResolveList = 256;  // in-band candidates resolved block-cooperatively
-constexpr int kRefineBlocks = 128; // refine grid (16 lane groups of 16 lanes per block)
+constexpr int kRefineBlocks = 512; // default refine grid (16 lane groups of 16 lanes per block)
+constexpr int kRefineMinBlocks = 128;  // refine blocks taking part with few survivors
+constexpr int kRefinePerBlock = 512;   // survivors per taking-part refine block
+constexpr int kKeyEvery = 8;       // refine: rows between re-reads of the shared best-so-far
+constexpr int kRefineVec = 4;      // float4 per lane per refine chunk (a 1 KiB piece of a row per group)
 
 // Best-so-far key: float32 bits of the squared distance (non-negative, so the bit pattern
 // orders like the value) in the high word, series index in the low word. atomicMin on it keeps
@@ -95,6 +99,8 @@ struct QueryArgs {
                         // also stored there, so the host needs no copy after synchronising
     const int32_t* leaves;  // learned seed, per-query path: [kTopLeaves] leaf ids (or null)
     int learned_cpl;        // > 0: learned seed over kTopLeaves leaves of up to this many chunks
+    int refine_blocks;      // refine grid (0: kRefineBlocks)
+    int refine_lanes;       // lanes per refined row: 4, 8 (default) or 16
 };
 
 // ---- batched path ----

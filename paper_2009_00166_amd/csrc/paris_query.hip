@@ -662,16 +662,39 @@ __device__ void resolve_block(const QueryArgs& A, const float* __restrict__ q, l
     }
 }
 
+// all-reduce over groups of G lanes (butterfly: bit-identical result on all G lanes)
+template <int G>
+__device__ __forceinline__ float group_sum(float v)
+{
+#pragma unroll
+    for (int off = G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, G);
+    return v;
+}
+
+template <int G>
 __global__ __launch_bounds__(256) void k_refine_resolve(QueryArgs A, const float* __restrict__ q,
                                                         long long* out_idx, double* out_dist, long long qi)
 {
+    constexpr int F = 16 / G;            // float4 per lane per step of 64 points
+    constexpr int GPB = 256 / G;         // lane groups per block
     __shared__ bool s_last;
-    const int tid = threadIdx.x, l = tid & 15, lane = tid & 63;
+    __shared__ __attribute__((aligned(16))) float qs_l[kMaxLength];
+    const int tid = threadIdx.x, l = tid & (G - 1), lane = tid & 63, lead = lane & ~(G - 1);
     const uint32_t count = min(A.qs->n_surv, A.surv_cap);
-    const uint32_t grp = (blockIdx.x * 256u + tid) >> 4;
-    const uint32_t ngrp = gridDim.x * 16u;
+    // Blocks taking part: one per kRefinePerBlock survivors, at least kRefineMinBlocks, at most the
+    // grid. Every block derives the same number from the same count; the others leave at once
+    // (a large grid serves queries with many survivors, a small one keeps the few-survivor case
+    // free of the extra blocks' completion traffic).
+    uint32_t active = count / kRefinePerBlock;
+    active = active < (uint32_t)kRefineMinBlocks ? (uint32_t)kRefineMinBlocks : active;
+    active = active > gridDim.x ? gridDim.x : active;
+    if (blockIdx.x >= active) return;
+    const uint32_t grp = blockIdx.x * (uint32_t)GPB + (uint32_t)(tid / G);
+    const uint32_t ngrp = active * (uint32_t)GPB;
     const int nv = A.n >> 2;
-    const float4* q4 = reinterpret_cast<const float4*>(q);
+    for (int j = tid; j < A.n; j += 256) qs_l[j] = q[j];
+    __syncthreads();
+    const float4* q4 = reinterpret_cast<const float4*>(qs_l);
     uint32_t refined = 0, abandoned = 0;
     bool wrote = false;
     // More survivors than lane groups: every group first computes the distance of the survivor
@@ -684,8 +707,8 @@ __global__ __launch_bounds__(256) void k_refine_resolve(QueryArgs A, const float
             const uint32_t hrow = (uint32_t)(hk & 0xFFFFFFFFu);
             const float4* h4 = reinterpret_cast<const float4*>(A.X + (long long)hrow * A.n);
             float part = 0.f;
-            for (int v = l; v < nv; v += 16) part += sqdiff4(h4[v], q4[v]);
-            local_best = group16_sum(part);
+            for (int v = l; v < nv; v += G) part += sqdiff4(h4[v], q4[v]);
+            local_best = group_sum<G>(part);
             if (grp == 0 && l == 0) {
                 const unsigned long long mine = pack_key(local_best, hrow);
                 const unsigned long long old = atomicMin(&A.qs->bsf_key, mine);
@@ -699,31 +722,72 @@ __global__ __launch_bounds__(256) void k_refine_resolve(QueryArgs A, const float
             }
         }
     }
+    // A row is read in chunks of 4 steps of 64 points (1 KiB), every lane's share of a chunk
+    // (4 F float4) loaded at once and the next chunk's loads issued before the current one is
+    // summed; the partial sum is compared with the threshold after every step (early abandoning).
+    // The next survivor's entry is fetched one iteration ahead. A survivor is first tested
+    // against the group's last threshold (the best-so-far only decreases, so a stale threshold
+    // prunes less, never wrongly); the shared best-so-far is re-read with every kKeyEvery-th
+    // row's first chunk (one address read by every group: reading it per row makes a hot spot)
+    // and once per chunk of longer rows.
+    constexpr int CV = 4 * F;            // float4 per lane per chunk
+    unsigned long long key0 = 0;
+    if (l == 0) key0 = load_key(&A.qs->bsf_key);
+    key0 = __shfl(key0, lead);
+    float thr = prune_threshold(fminf(key_dist(key0), local_best), A.mg.prune_rel);
+    uint2 e_next = grp < count ? A.surv[grp] : make_uint2(0u, 0u);
     for (uint32_t c = grp; c < count; c += ngrp) {
-        const uint2 e = A.surv[c];
+        const uint2 e = e_next;
+        if (c + ngrp < count) e_next = A.surv[c + ngrp];
         const float lb = __uint_as_float(e.y);
-        unsigned long long key = 0;
-        if (l == 0) key = load_key(&A.qs->bsf_key);
-        key = __shfl(key, lane & ~15);
-        float thr = prune_threshold(fminf(key_dist(key), local_best), A.mg.prune_rel);
-        if (lb > thr) continue;  // re-check against the current best (uniform in the group)
-        ++refined;
+        if (lb > thr) continue;  // uniform in the group
         const float4* r4 = reinterpret_cast<const float4*>(A.X + (long long)e.x * A.n);
-        float4 a = make_float4(0.f, 0.f, 0.f, 0.f), b = a;
-        if (l < nv) { a = r4[l]; b = q4[l]; }
+        const bool fresh = (refined % kKeyEvery) == 0;
+        unsigned long long key = 0;
+        if (fresh && l == 0) key = load_key(&A.qs->bsf_key);
+        float4 xa[CV];
+#pragma unroll
+        for (int k = 0; k < CV; ++k) {
+            const int v = (k / F) * 16 + (k % F) * G + l;
+            xa[k] = v < nv ? r4[v] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+        if (fresh) {
+            key = __shfl(key, lead);
+            thr = prune_threshold(fminf(key_dist(key), local_best), A.mg.prune_rel);
+            if (lb > thr) continue;  // re-check against the current best
+        }
+        ++refined;
         float acc = 0.f;
         bool ab = false;
-        for (int v0 = 0; v0 < nv; v0 += 16) {
-            const int vn = v0 + 16 + l;
-            float4 an = make_float4(0.f, 0.f, 0.f, 0.f), bn = an;
-            if (vn < nv) { an = r4[vn]; bn = q4[vn]; }   // next step in flight
-            const float part = (v0 + l < nv) ? sqdiff4(a, b) : 0.f;
-            acc += group16_sum(part);
-            if (acc > thr) { ab = true; break; }
-            a = an;
-            b = bn;
-            if (l == 0) key = load_key(&A.qs->bsf_key);
-            key = __shfl(key, lane & ~15);
+        for (int v0 = 0; v0 < nv; v0 += 64) {
+            const int v1 = v0 + 64;
+            const bool more = v1 < nv;
+            float4 xn[CV];
+            if (more) {
+                if (l == 0) key = load_key(&A.qs->bsf_key);
+#pragma unroll
+                for (int k = 0; k < CV; ++k) {
+                    const int v = v1 + (k / F) * 16 + (k % F) * G + l;
+                    xn[k] = v < nv ? r4[v] : make_float4(0.f, 0.f, 0.f, 0.f);
+                }
+            }
+#pragma unroll
+            for (int st = 0; st < 4; ++st) {
+                if (v0 + st * 16 < nv) {
+                    float part = 0.f;
+#pragma unroll
+                    for (int f = 0; f < F; ++f) {
+                        const int v = v0 + st * 16 + f * G + l;
+                        part += v < nv ? sqdiff4(xa[st * F + f], q4[v]) : 0.f;
+                    }
+                    acc += group_sum<G>(part);
+                    if (acc > thr) { ab = true; break; }
+                }
+            }
+            if (ab || !more) break;
+#pragma unroll
+            for (int k = 0; k < CV; ++k) xa[k] = xn[k];
+            key = __shfl(key, lead);
             thr = prune_threshold(fminf(key_dist(key), local_best), A.mg.prune_rel);
         }
         if (ab) { ++abandoned; continue; }
@@ -757,7 +821,7 @@ __global__ __launch_bounds__(256) void k_refine_resolve(QueryArgs A, const float
     if (wrote) s_wrote = 1;
     __syncthreads();
     if (s_wrote) __threadfence();
-    if (tid == 0) s_last = atomicAdd(&A.qs->blocks_done, 1u) == gridDim.x - 1;
+    if (tid == 0) s_last = atomicAdd(&A.qs->blocks_done, 1u) == active - 1;
     __syncthreads();
     if (!s_last) return;
     __threadfence();
@@ -767,7 +831,13 @@ __global__ __launch_bounds__(256) void k_refine_resolve(QueryArgs A, const float
 hipError_t launch_refine_resolve(const QueryArgs& a, const float* q, long long* out_idx, double* out_dist,
                                  long long qi, hipStream_t st)
 {
-    k_refine_resolve<<<kRefineBlocks, 256, 0, st>>>(a, q, out_idx, out_dist, qi);
+    const int grid = a.refine_blocks > 0 ? a.refine_blocks : kRefineBlocks;
+    if (a.refine_lanes == 4)
+        k_refine_resolve<4><<<grid, 256, 0, st>>>(a, q, out_idx, out_dist, qi);
+    else if (a.refine_lanes == 16)
+        k_refine_resolve<16><<<grid, 256, 0, st>>>(a, q, out_idx, out_dist, qi);
+    else
+        k_refine_resolve<8><<<grid, 256, 0, st>>>(a, q, out_idx, out_dist, qi);
     return hipGetLastError();
 }
 
