@@ -140,9 +140,7 @@ struct paris_mlp {
     float* G1;         // [max_rows][256]
     uint16_t* G1b;
     float* loss_row;   // [max_rows]
-    float* zq;         // [n_out] per-query logits
-    uint32_t* counter; // per-query kernel's finished-block counter
-    int32_t* leaves_q; // [kTopLeaves] per-query result
+    unsigned long long* partq;  // [n_out / 256 + 1][8] per-query block keys
     long long step;    // Adam steps taken
 };
 
@@ -218,7 +216,8 @@ QueryArgs args_for(const paris_index* h)
     a.done_cap = (uint32_t)h->N;
     a.mg = h->mg;
     a.host_res = nullptr;
-    a.leaves = nullptr;
+    a.leaf_keys = nullptr;
+    a.leaf_key_count = 0;
     a.learned_cpl = 0;
     a.refine_blocks = h->refine_blocks;
     a.refine_lanes = h->refine_lanes;
@@ -267,9 +266,10 @@ paris_status run_query(paris_index* h, const float* q, hipStream_t st, long long
     if (timed) HIP_TRY(hipEventRecord(h->ev[0], st));
     if (h->learned) {
         const paris_mlp* m = h->model;
-        MlpQueryScratch sc{m->zq, m->counter, m->leaves_q};
+        MlpQueryScratch sc{m->partq};
         HIP_TRY(launch_mlp_query(net_of(m), q, h->n, sc, st));
-        a.leaves = m->leaves_q;
+        a.leaf_keys = m->partq;
+        a.leaf_key_count = (m->n_out + 255) / 256 * kTopLeaves;
         a.learned_cpl = learned_chunks(h);
     }
     HIP_TRY(launch_prepare_seed(a, q, st));
@@ -1147,7 +1147,7 @@ paris_status paris_mlp_create(int32_t n_leaves, int32_t max_rows, paris_mlp** ou
                  o_v = take(np * 4), o_P = take(R * kMlpIn * 4), o_H1 = take(R * H * 2), o_H2 = take(R * H * 2),
                  o_Z = take(R * no * 4), o_G3 = take(R * no * 4), o_G3b = take(R * no * 2), o_G2 = take(R * H * 4),
                  o_G2b = take(R * H * 2), o_G1 = take(R * H * 4), o_G1b = take(R * H * 2), o_lr = take(R * 4),
-                 o_zq = take(no * 4), o_cnt = take(4), o_lq = take(kTopLeaves * 4);
+                 o_zq = take((no / 256 + 1) * kTopLeaves * 8);
     if (hipMalloc(reinterpret_cast<void**>(&m->mem), off) != hipSuccess) {
         delete m;
         return PARIS_ENOMEM;
@@ -1169,10 +1169,8 @@ paris_status paris_mlp_create(int32_t n_leaves, int32_t max_rows, paris_mlp** ou
     m->G1 = reinterpret_cast<float*>(b + o_G1);
     m->G1b = reinterpret_cast<uint16_t*>(b + o_G1b);
     m->loss_row = reinterpret_cast<float*>(b + o_lr);
-    m->zq = reinterpret_cast<float*>(b + o_zq);
-    m->counter = reinterpret_cast<uint32_t*>(b + o_cnt);
-    m->leaves_q = reinterpret_cast<int32_t*>(b + o_lq);
-    // all-zero parameters, moments and counter until the caller sets parameters
+    m->partq = reinterpret_cast<unsigned long long*>(b + o_zq);
+    // all-zero parameters and moments until the caller sets parameters
     if (hipMemset(m->mem, 0, off) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
         (void)hipFree(m->mem);
         delete m;

@@ -97,7 +97,8 @@ struct QueryArgs {
     Margins mg;
     QResult* host_res;  // pinned host memory mapped for the device (may be null): the result is
                         // also stored there, so the host needs no copy after synchronising
-    const int32_t* leaves;  // learned seed, per-query path: [kTopLeaves] leaf ids (or null)
+    const unsigned long long* leaf_keys;  // learned seed, per-query path: best (logit, leaf) keys
+    int leaf_key_count;                   // of the network's blocks, merged by the seed kernel
     int learned_cpl;        // > 0: learned seed over kTopLeaves leaves of up to this many chunks
     int refine_blocks;      // refine grid (0: kRefineBlocks)
     int refine_lanes;       // lanes per refined row: 4, 8 (default) or 16
@@ -207,10 +208,18 @@ struct MlpNet {
 };
 
 struct MlpQueryScratch {
-    float* z;               // [n_out] logits of the current query
-    uint32_t* counter;      // blocks finished (re-armed by the last block)
-    int32_t* leaves;        // [kTopLeaves] result
+    unsigned long long* part;  // [blocks][kTopLeaves] every block's best (logit, leaf) keys
 };
+
+// (logit, leaf) order key of the top-leaf selections: float bits mapped to an unsigned order
+// (NaN lowest), leaf id complemented so that among equal logits the lower id has the larger key.
+__device__ __forceinline__ unsigned long long top_key(float v, uint32_t c)
+{
+    uint32_t u = __float_as_uint(v);
+    u = (u >> 31) ? ~u : (u | 0x80000000u);
+    if (v != v) u = 0u;
+    return ((unsigned long long)u << 32) | (uint32_t)(~c);
+}
 
 enum GemmEpilogue { kEpiBiasReluBf16 = 0, kEpiBiasF32 = 1, kEpiMask = 2, kEpiF32 = 3 };
 

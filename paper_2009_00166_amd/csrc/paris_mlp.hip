@@ -272,16 +272,6 @@ __global__ __launch_bounds__(256) void k_mirror(const float* __restrict__ p, uin
 }
 
 // ---- top leaves: the k largest logits of a row, equal logits by lowest leaf id --------------
-// Order key: float bits mapped to an unsigned order (NaN lowest), leaf id complemented so that
-// the larger key is the lower id; taken entries get key 0, below every untaken entry.
-__device__ __forceinline__ unsigned long long top_key(float v, uint32_t c)
-{
-    uint32_t u = __float_as_uint(v);
-    u = (u >> 31) ? ~u : (u | 0x80000000u);
-    if (v != v) u = 0u;
-    return ((unsigned long long)u << 32) | (uint32_t)(~c);
-}
-
 __device__ void block_top(const float* __restrict__ z, int n_out, int k, int32_t* __restrict__ out)
 {
     __shared__ uint32_t taken[kMaxLeaves / 32];
@@ -320,40 +310,87 @@ __global__ __launch_bounds__(256) void k_topk(const float* __restrict__ Z, int n
 }
 
 // ---- one query (per-query search path): PAA, the three layers and the top leaves ------------
-// Every block recomputes the two hidden layers (65k multiply-adds) and scores 256 leaves; the
-// last block to finish selects the top leaves and re-arms the counter for the next query.
-// Hidden layers: 16 lanes per unit, each lane 16 consecutive inputs (one 32-byte read of the
-// unit's weight row), reduced over the 16 lanes.
-__device__ __forceinline__ float sum16(float v)
+// Every block (1024 threads) recomputes the two hidden layers (65k multiply-adds) and scores 256
+// leaves, then stores its 8 best (logit, leaf) keys; the seed kernel that runs next merges the
+// blocks' keys (after the kernel boundary, so no fence or completion counter is needed here).
+// All weight reads are issued at the start, before the query is summarised, so their latency
+// overlaps the first layer: a wave owns 16 rows of a layer, a row (256 bfloat16) is read by 32
+// lanes with 16 bytes each, and a lane's 8 partial dot products are combined by a butterfly
+// that halves the set at each step (a reduce-scatter over the half-wave).
+__device__ __forceinline__ float dot8_bf(const uint4 w, const float* hv)
 {
-    for (int off = 8; off > 0; off >>= 1) v += __shfl_xor(v, off);
-    return v;
-}
-
-__device__ __forceinline__ float dot16_bf(const uint16_t* __restrict__ wrow, const float* __restrict__ h)
-{
-    const uint4 a = *reinterpret_cast<const uint4*>(wrow);
-    const uint4 b = *reinterpret_cast<const uint4*>(wrow + 8);
-    const uint32_t u[8] = {a.x, a.y, a.z, a.w, b.x, b.y, b.z, b.w};
+    const uint32_t u[4] = {w.x, w.y, w.z, w.w};
     float acc = 0.f;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
-        acc = acc + h[2 * e] * __uint_as_float(u[e] << 16);
-        acc = acc + h[2 * e + 1] * __uint_as_float(u[e] & 0xFFFF0000u);
+    for (int e = 0; e < 4; ++e) {
+        acc = acc + hv[2 * e] * __uint_as_float(u[e] << 16);
+        acc = acc + hv[2 * e + 1] * __uint_as_float(u[e] & 0xFFFF0000u);
     }
     return acc;
 }
 
-__global__ __launch_bounds__(256) void k_mlp_query(MlpNet net, const float* __restrict__ q, int n,
-                                                   MlpQueryScratch s)
+// sum over the 32 lanes of a half-wave of 8 partials per lane; lane l returns the sum of
+// partial index (l % 32) / 4 (the 4 lanes of a quad return the same sum)
+__device__ __forceinline__ float reduce_scatter8(float (&part)[8], int lane)
+{
+#pragma unroll
+    for (int off = 16, cnt = 4; off >= 4; off >>= 1, cnt >>= 1) {
+        const bool upper = (lane & off) != 0;
+#pragma unroll
+        for (int i = 0; i < cnt; ++i) {
+            const float send = upper ? part[i] : part[i + cnt];
+            const float keep = upper ? part[i + cnt] : part[i];
+            part[i] = keep + __shfl_xor(send, off);
+        }
+    }
+    float v = part[0];
+    v += __shfl_xor(v, 2);
+    v += __shfl_xor(v, 1);
+    return v;
+}
+
+__global__ __launch_bounds__(1024) void k_mlp_query(MlpNet net, const float* __restrict__ q, int n,
+                                                    MlpQueryScratch s)
 {
     __shared__ float qv[kMaxLength];
     __shared__ float f[kMlpIn];
     __shared__ float h1[kMlpHid];
     __shared__ float h2[kMlpHid];
-    __shared__ uint32_t s_last;
-    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
-    for (int j = tid; j < n; j += 256) qv[j] = q[j];
+    __shared__ unsigned long long bk[256];
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63, half = lane >> 5, kk = (lane & 31) * 8;
+    // the query, then every weight this thread needs (issued together)
+    float qr[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int j = tid + i * 1024;
+        qr[i] = j < n ? q[j] : 0.f;
+    }
+    const int hu = tid & 255;   // layer-1 unit of this thread (threads >= 256 repeat a row, unused)
+    const uint4 w1a = *reinterpret_cast<const uint4*>(net.wb + net.off.w1 + (long long)hu * kMlpIn);
+    const uint4 w1b = *reinterpret_cast<const uint4*>(net.wb + net.off.w1 + (long long)hu * kMlpIn + 8);
+    uint4 w2v[8], w3v[8];
+#pragma unroll
+    for (int p = 0; p < 8; ++p)
+        w2v[p] = *reinterpret_cast<const uint4*>(net.wb + net.off.w2 + (long long)(16 * w + 2 * p + half) * kMlpHid + kk);
+    const long long u0 = (long long)blockIdx.x * 256 + 16 * w;
+#pragma unroll
+    for (int p = 0; p < 8; ++p) {
+        long long u = u0 + 2 * p + half;
+        u = u < net.n_out ? u : net.n_out - 1;   // rows past the last leaf: read a valid row, unused
+        w3v[p] = *reinterpret_cast<const uint4*>(net.wb + net.off.w3 + u * kMlpHid + kk);
+    }
+    // biases too: every read of this kernel is in flight before the first wait
+    const int pr = (lane & 31) >> 2;          // this lane's row pair after the reduce-scatter
+    const int row = 16 * w + 2 * pr + half;   // its row of the layer (block-local for layer 3)
+    const long long u3 = u0 + 2 * pr + half;
+    const float bias1 = net.master[net.off.b1 + hu];
+    const float bias2 = net.master[net.off.b2 + row];
+    const float bias3 = net.master[net.off.b3 + (u3 < net.n_out ? u3 : net.n_out - 1)];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) {
+        const int j = tid + i * 1024;
+        if (j < n) qv[j] = qr[i];
+    }
     __syncthreads();
     if (tid < kMlpIn) {
         const int L = n >> 4;
@@ -362,39 +399,48 @@ __global__ __launch_bounds__(256) void k_mlp_query(MlpNet net, const float* __re
         f[tid] = (float)(acc / (double)L);
     }
     __syncthreads();
-    {
-        const uint16_t* wr = net.wb + net.off.w1 + (long long)tid * kMlpIn;
+    if (tid < kMlpHid) {
+        const uint32_t u[8] = {w1a.x, w1a.y, w1a.z, w1a.w, w1b.x, w1b.y, w1b.z, w1b.w};
         float acc = 0.f;
-        for (int i = 0; i < kMlpIn; ++i) acc = acc + f[i] * bf2f(wr[i]);
-        acc = acc + net.master[net.off.b1 + tid];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            acc = acc + f[2 * e] * __uint_as_float(u[e] << 16);
+            acc = acc + f[2 * e + 1] * __uint_as_float(u[e] & 0xFFFF0000u);
+        }
+        acc = acc + bias1;
         h1[tid] = bf2f(rne16(fmaxf(acc, 0.f)));
     }
     __syncthreads();
-    const int grp = l >> 4, gl = l & 15;   // 4 units per wave at a time, 16 lanes each
-    for (int u0 = w * 4; u0 < kMlpHid; u0 += 16) {
-        const int u = u0 + grp;
-        float acc = dot16_bf(net.wb + net.off.w2 + (long long)u * kMlpHid + gl * 16, h1 + gl * 16);
-        acc = sum16(acc);
-        if (gl == 0) h2[u] = bf2f(rne16(fmaxf(acc + net.master[net.off.b2 + u], 0.f)));
+    {
+        float hv[8], part[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) hv[e] = h1[kk + e];
+#pragma unroll
+        for (int p = 0; p < 8; ++p) part[p] = dot8_bf(w2v[p], hv);
+        const float acc = reduce_scatter8(part, lane);
+        if ((lane & 3) == 0) h2[row] = bf2f(rne16(fmaxf(acc + bias2, 0.f)));
     }
     __syncthreads();
-    const int c0 = blockIdx.x * 256;
-    for (int u0 = c0 + w * 4; u0 < c0 + 256 && u0 < net.n_out; u0 += 16) {
-        const int u = u0 + grp;
-        float acc = 0.f;
-        if (u < net.n_out) acc = dot16_bf(net.wb + net.off.w3 + (long long)u * kMlpHid + gl * 16, h2 + gl * 16);
-        acc = sum16(acc);
-        if (gl == 0 && u < net.n_out) s.z[u] = acc + net.master[net.off.b3 + u];
+    {
+        float hv[8], part[8];
+#pragma unroll
+        for (int e = 0; e < 8; ++e) hv[e] = h2[kk + e];
+#pragma unroll
+        for (int p = 0; p < 8; ++p) part[p] = dot8_bf(w3v[p], hv);
+        const float acc = reduce_scatter8(part, lane);
+        if ((lane & 3) == 0) bk[row] = u3 < net.n_out ? top_key(acc + bias3, (uint32_t)u3) : 0ull;
     }
-    // last block: every block's logits are visible after its fence and the counter increment
-    __threadfence();
     __syncthreads();
-    if (tid == 0) s_last = (atomicAdd(s.counter, 1u) == gridDim.x - 1) ? 1u : 0u;
-    __syncthreads();
-    if (!s_last) return;
-    __threadfence();
-    block_top(s.z, net.n_out, kTopLeaves, s.leaves);
-    if (tid == 0) *s.counter = 0u;
+    // the block's 8 largest keys, by rank (valid keys are distinct; absent leaves have key 0 and
+    // are never among the 8, as every block holds at least 64 leaves)
+    if (tid < 256) {
+        const unsigned long long key = bk[tid];
+        if (key != 0ull) {
+            int r = 0;
+            for (int i = 0; i < 256; ++i) r += bk[i] > key ? 1 : 0;
+            if (r < kTopLeaves) s.part[blockIdx.x * kTopLeaves + r] = key;
+        }
+    }
 }
 
 // ---- labels: the equal-count leaf of a series ---------------------------------------------
@@ -505,7 +551,7 @@ hipError_t launch_topk(const float* Z, int rows, int n_out, int k, int32_t* out,
 
 hipError_t launch_mlp_query(const MlpNet& net, const float* q, int n, const MlpQueryScratch& s, hipStream_t st)
 {
-    k_mlp_query<<<(net.n_out + 255) / 256, 256, 0, st>>>(net, q, n, s);
+    k_mlp_query<<<(net.n_out + 255) / 256, 1024, 0, st>>>(net, q, n, s);
     return hipGetLastError();
 }
 

@@ -162,6 +162,8 @@ __global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* 
     __shared__ double red_lb[256];
     __shared__ int red_r[256];
     __shared__ unsigned long long red_key[4];
+    __shared__ int32_t s_leaves[kTopLeaves];
+    __shared__ unsigned long long s_keys[(kMaxLeaves / 256) * kTopLeaves];
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int n = A.n, L = n >> 4;
@@ -243,8 +245,25 @@ __global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* 
     const bool learned = A.learned_cpl > 0;
     long long chunk0 = (long long)blockIdx.x * kSeedChunk;
     if (learned) {
-        // learned seed: block (slot, chunk) scans chunk `chunk` of the slot-th best-scoring leaf
-        const int32_t* lv = batch ? B.leaves + (long long)blockIdx.y * kTopLeaves : A.leaves;
+        // learned seed: block (slot, chunk) scans chunk `chunk` of the slot-th best-scoring leaf.
+        // Per-query path: the 8 best of the network blocks' (logit, leaf) keys, merged here.
+        const int32_t* lv;
+        if (batch) {
+            lv = B.leaves + (long long)blockIdx.y * kTopLeaves;
+        } else {
+            // (keys are distinct: a key's place is the number of larger keys)
+            const int nk = A.leaf_key_count;
+            for (int c = tid; c < nk; c += 256) s_keys[c] = A.leaf_keys[c];
+            __syncthreads();
+            for (int c = tid; c < nk; c += 256) {
+                const unsigned long long k3 = s_keys[c];
+                int r = 0;
+                for (int i = 0; i < nk; ++i) r += s_keys[i] > k3 ? 1 : 0;
+                if (r < kTopLeaves) s_leaves[r] = (int32_t)(~(uint32_t)(k3 & 0xFFFFFFFFu));
+            }
+            __syncthreads();
+            lv = s_leaves;
+        }
         const int slot = (int)blockIdx.x / A.learned_cpl;
         const long long N = A.N, nl = A.n_leaves;
         long long ell = lv[slot];
