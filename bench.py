@@ -32,6 +32,40 @@ def log(msg: str) -> None:
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_10Mx256.md")
+KERNEL_SOURCES = {"k_lbscan": "paris_query.hip", "k_screen": "paris_batch.hip"}
+
+
+def source_digest(kernel: str) -> str:
+    """Digest of the source file that holds a kernel, comments and whitespace removed: the
+    measured HBM traffic of a kernel is reported only while this digest is unchanged."""
+    import hashlib
+    import re
+    path = os.path.join(ROOT, "paper_2009_00166_amd", "csrc", KERNEL_SOURCES[kernel])
+    txt = open(path).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    txt = re.sub(r"//[^\n]*", "", txt)
+    txt = re.sub(r"\s+", " ", txt).strip()
+    return hashlib.sha256(txt.encode()).hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE summary, or
+    None when it is absent or the kernel's source has changed since it was taken."""
+    try:
+        lines = open(TRAFFIC_FILE).read().splitlines()
+    except OSError:
+        return None
+    vals = {}
+    for ln in lines:
+        if ln.startswith(f"{kernel}.") and "=" in ln:
+            k, v = ln.split("=", 1)
+            vals[k.strip()[len(kernel) + 1:]] = v.strip()
+    if vals.get("source_digest") != source_digest(kernel) or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
 def cpu_baseline(X, Q, gpu_idx, n_queries: int, threads: int):
     """The C oracle (brute force, float64) on a bounded sample of the same workload."""
     import numpy as np
@@ -159,7 +193,7 @@ def main() -> int:
                    "seed_cap": 16384},
         "roofline": {"bound": "hbm", "kernel": "k_lbscan", "achieved": achieved,
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
-                     "traffic": None,
+                     "traffic": measured_traffic("k_lbscan"),
                      "bytes_per_launch": lb_bytes, "avg_launch_ms": lb_ms,
                      "note": "16 B of iSAX word per series per launch; the 160 MB array fits the "
                              "256 MB Infinity Cache, so back-to-back scans can exceed HBM rate"},
@@ -260,7 +294,7 @@ def batched_section(index, X, args):
                    "batch": B, "n_series": N, "length": n},
         "vs_plain": qps / args._plain_qps if args._plain_qps else None,
         "roofline": {"bound": "mfma", "kernel": "k_screen", "achieved": achieved, "peak": 2500.0,
-                     "unit": "TFLOP/s", "frac": achieved / 2500.0, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / 2500.0, "traffic": measured_traffic("k_screen"),
                      "flops_per_launch": flops, "avg_launch_ms": stage[1]},
         "stages_ms_per_batch": dict(zip(["seeds", "screen", "rescore", "resolve"], stage)),
         "screen_survivors_per_query": st["lb_survivors"] / B,

@@ -13,9 +13,11 @@
 // The test is folded into per-row and per-column constants: keep iff
 //     dot >= a_q + b_x,  a_q = ((1 - c) qn - U_q) / 2,  b_x = (1 - c) xn / 2
 // (both rounded down, c inflated for the evaluation of the test itself). The constants enter
-// the contraction itself through one extra k-step: the query row carries RU(-a_q) and 1, the
-// series row 1 and RU(-b_x) (bfloat16 rounded toward +inf, so the sum never decreases), hence
-// every accumulator ends as dot - a_q - b_x (or more) and a series survives iff it is >= 0.
+// the contraction itself through one extra k-step: the query row carries [hi, lo, 1, 1] and the
+// series row [1, 1, hi', lo'], where hi + lo >= -a_q and hi' + lo' >= -b_x are pairs of
+// bfloat16 values (hi rounded down, the exact float32 remainder rounded up: bias_pair), so
+// every accumulator ends as dot - a_q - b_x or more, within about 2^-16 relative of it, and a
+// series survives iff its accumulator is >= 0.
 #include "paris_internal.h"
 
 namespace paris {
