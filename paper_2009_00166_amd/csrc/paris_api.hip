@@ -640,9 +640,9 @@ paris_status run_batch_chunk(paris_index* h, const float* queries, long long q0,
     return PARIS_OK;
 }
 
-// Screen autotuner: query-tile height (32 or 64 rows) x series per wave (32, two waves per SIMD;
-// or 64, one wave per SIMD), every threshold at +inf (no candidate), timed over full-size
-// batches; the median of three runs decides. PARIS_SCREEN_SHAPE="qt,subs" overrides.
+// Screen autotuner: MFMA form (16x16x32 or 32x32x16) x query-tile height (32 or 64 rows) x
+// series per wave, every threshold at +inf (no candidate), timed over full-size batches; the
+// median of three runs decides. PARIS_SCREEN_SHAPE="qt,subs[,mfma]" overrides.
 paris_status tune_screen(paris_index* h, hipStream_t st)
 {
     const char* env = std::getenv("PARIS_SCREEN_SHAPE");
@@ -651,9 +651,14 @@ paris_status tune_screen(paris_index* h, hipStream_t st)
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         cus = 256;
     if (env) {
-        int qt = 0, subs = 0;
-        if (std::sscanf(env, "%d,%d", &qt, &subs) == 2 && (qt == 32 || qt == 64) && (subs == 2 || subs == 4)) {
-            h->screen = ScreenShape{qt, cus * (subs == 2 ? 2 : 1), subs};
+        int qt = 0, subs = 0, mf = 16;
+        const int got = std::sscanf(env, "%d,%d,%d", &qt, &subs, &mf);
+        if (got >= 2 && mf == 16 && (qt == 32 || qt == 64) && (subs == 2 || subs == 4)) {
+            h->screen = ScreenShape{qt, cus * (subs == 2 ? 2 : 1), subs, 16};
+            return PARIS_OK;
+        }
+        if (got == 3 && mf == 32 && ((qt == 32 && (subs == 1 || subs == 2)) || (qt == 64 && subs == 1))) {
+            h->screen = ScreenShape{qt, cus * 2, subs, 32};
             return PARIS_OK;
         }
     }
@@ -663,8 +668,9 @@ paris_status tune_screen(paris_index* h, hipStream_t st)
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     float best = 1e30f;
-    ScreenShape pick{64, cus, 4};
-    const ScreenShape cands[] = {{32, cus * 2, 2}, {64, cus * 2, 2}, {32, cus, 4}, {64, cus, 4}};
+    ScreenShape pick{64, cus, 4, 16};
+    const ScreenShape cands[] = {{32, cus * 2, 2, 16}, {64, cus * 2, 2, 16}, {32, cus, 4, 16}, {64, cus, 4, 16},
+                                 {32, cus * 2, 2, 32}, {64, cus * 2, 1, 32}, {32, cus * 2, 1, 32}};
     for (const ScreenShape& sh : cands) {
         float t[3];
         for (int r = 0; r < 4; ++r) {
@@ -862,7 +868,7 @@ paris_status paris_build(const float* series_dev, int64_t n_series, int32_t leng
     h->np = (length + 31) / 32 * 32;
     h->screen_ok = false;
     std::memset(&h->bp, 0, sizeof(h->bp));
-    h->screen = ScreenShape{64, 0, 4};
+    h->screen = ScreenShape{64, 0, 4, 16};
     h->c_screen = screen_margin(length, h->np);
     // the seed series' exact squared distance is at most d32 (1 + g) / (1 - g) < d32 (1 + 3 g)
     h->seed_rel = 3.0 * gamma_k(length + 2) + std::ldexp(1.0, -30);

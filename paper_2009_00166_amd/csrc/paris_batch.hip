@@ -24,6 +24,7 @@ namespace paris {
 
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 __device__ __forceinline__ uint16_t to_bf16(float f)
 {
@@ -347,6 +348,226 @@ __global__ __launch_bounds__(256, SUBS == 2 ? 2 : 1) void k_screen(ScreenArgs S)
     if (ccount) flush_cands();
 }
 
+// The same screen on v_mfma_f32_32x32x16_bf16: a 32 x 32 output tile per instruction doubles
+// the work per operand byte, so a query fragment read from LDS feeds twice the arithmetic of
+// the 16 x 16 form. A wave holds S subtiles of 32 series (k-steps of 16, plus the bias step) in
+// registers; query tiles of QT rows stream through LDS. Operand layout (32x32x16): lane l holds
+// row/column (l % 32) and the 8 k-elements 8 (l / 32) .. +7 of the k-step for both A (queries)
+// and B (series); accumulator element i of lane l is row 8 (i / 4) + 4 (l / 32) + i % 4, column
+// l % 32. Bias step: query rows carry [hi(-a_q), lo(-a_q), 1, 1] and series rows
+// [1, 1, hi(-b_x), lo(-b_x)] in k-elements 0..3, zeros elsewhere.
+template <int KS16, int QT, int S>
+__global__ __launch_bounds__(256, 2) void k_screen32(ScreenArgs Sa)
+{
+    constexpr int XW = 32 * S;          // series per wave (kept in registers)
+    constexpr int XB = 4 * XW;          // series per work item (block)
+    constexpr int NP = KS16 * 16;
+    constexpr int KT = KS16 + 1;        // k-steps including the bias step
+    constexpr int RS = KT * 16 + 8;     // LDS row stride (bfloat16): an odd multiple of 16 bytes
+    constexpr int QS = QT / 32;         // query subtiles per tile
+    constexpr int V8 = NP / 8;          // 16-byte vectors per data row
+    constexpr int STAGE = (QT * V8 + 255) / 256;
+    __shared__ __attribute__((aligned(16))) uint16_t qtile[2][QT * RS];
+    __shared__ long long s_item;
+    __shared__ uint2 cbuf[kCandStage];
+    __shared__ uint32_t ccount, cbase;
+    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    if (tid == 0) ccount = 0;
+    auto flush_cands = [&]() {
+        const uint32_t cnt = min(ccount, (uint32_t)kCandStage);
+        if (tid == 0) cbase = atomicAdd(&Sa.hdr->n_cand, cnt);
+        __syncthreads();
+        for (uint32_t k = tid; k < cnt; k += 256) {
+            const uint32_t pos = cbase + k;
+            if (pos < Sa.cand_cap) Sa.cand[pos] = cbuf[k];
+        }
+        __syncthreads();
+        if (tid == 0) ccount = 0;
+        __syncthreads();
+    };
+
+    const int col = l & 31, kh = l >> 5;
+    const int M = Sa.M;
+    const long long N = Sa.N;
+    const int n_qt = (M + QT - 1) / QT;
+    const long long n_items = (N + XB - 1) / XB;
+    const bool dump = Sa.dump != nullptr;
+
+    // bias block of every row (16 bfloat16 after the data): [hi, lo, 1, 1, 0 ...], the first
+    // 4 rewritten with each tile, the rest stays zero
+    for (int e = tid; e < 2 * QT * 2; e += 256) {
+        const int buf = e / (QT * 2), rem = e - buf * QT * 2, row = rem >> 1, ch = rem & 1;
+        *reinterpret_cast<uint4*>(&qtile[buf][row * RS + NP + ch * 8]) = make_uint4(0, 0, 0, 0);
+    }
+
+    auto stage_load = [&](int t, uint4* pre, uint2& bias) {
+#pragma unroll
+        for (int s = 0; s < STAGE; ++s) {
+            const int e = tid + s * 256;
+            const int row = e / V8, v = e - row * V8;
+            const int q = t * QT + row;
+            pre[s] = (e < QT * V8 && q < M)
+                         ? *reinterpret_cast<const uint4*>(Sa.Qb + (long long)q * NP + v * 8)
+                         : make_uint4(0, 0, 0, 0);
+        }
+        if (tid < QT) {
+            const int q = t * QT + tid;
+            const float a = (q < M && !dump) ? Sa.bq[q].a : (dump ? 0.f : __builtin_inff());
+            const float t1 = a < __builtin_inff() ? -a : kNoPass;
+            bias = bias_pair(t1);  // [hi(-a_q), lo(-a_q), 1.0, 1.0]
+            bias.y = 0x3F803F80u;
+        }
+    };
+    auto stage_store = [&](int buf, const uint4* pre, uint2 bias) {
+#pragma unroll
+        for (int s = 0; s < STAGE; ++s) {
+            const int e = tid + s * 256;
+            if (e < QT * V8) {
+                const int row = e / V8, v = e - row * V8;
+                *reinterpret_cast<uint4*>(&qtile[buf][row * RS + v * 8]) = pre[s];
+            }
+        }
+        if (tid < QT) *reinterpret_cast<uint2*>(&qtile[buf][tid * RS + NP]) = bias;
+    };
+
+    for (;;) {
+        __syncthreads();
+        if (tid == 0) s_item = (long long)atomicAdd(&Sa.hdr->next_item, 1u);
+        __syncthreads();
+        const long long item = s_item;
+        if (item >= n_items) break;  // uniform: every wave reaches this exit
+        const long long xb0 = item * XB + w * XW;
+
+        bf16x8 bfr[S][KT];
+#pragma unroll
+        for (int sub = 0; sub < S; ++sub) {
+            const long long x = xb0 + sub * 32 + col;
+            const bool ok = x < N;
+#pragma unroll
+            for (int ks = 0; ks < KS16; ++ks) {
+                if (ok) bfr[sub][ks] = *reinterpret_cast<const bf16x8*>(Sa.Xb + x * NP + ks * 16 + kh * 8);
+                else bfr[sub][ks] = bf16x8{};
+            }
+            float t2 = kNoPass;
+            if (ok) t2 = dump ? 0.f : -__double2float_rd((1.0 - (double)Sa.c_screen) * (double)Sa.xn[x] * 0.5);
+            uint4 bb = make_uint4(0, 0, 0, 0);
+            if (kh == 0) {
+                bb.x = 0x3F803F80u;   // [1.0, 1.0, hi(-b_x), lo(-b_x)]
+                bb.y = bias_pair(t2).x;
+            }
+            bfr[sub][KS16] = __builtin_bit_cast(bf16x8, bb);
+        }
+
+        {
+            uint4 pre[STAGE];
+            uint2 bias = make_uint2(0u, 0u);
+            stage_load(0, pre, bias);
+            stage_store(0, pre, bias);
+        }
+        __syncthreads();
+
+        for (int t = 0; t < n_qt; ++t) {
+            const int buf = t & 1;
+            uint4 pre[STAGE];
+            uint2 bias = make_uint2(0u, 0u);
+            const bool more = t + 1 < n_qt;
+            if (more) stage_load(t + 1, pre, bias);  // in flight during the MFMAs
+
+            f32x16 acc[QS][S];
+#pragma unroll
+            for (int qs = 0; qs < QS; ++qs)
+#pragma unroll
+                for (int sub = 0; sub < S; ++sub)
+#pragma unroll
+                    for (int i = 0; i < 16; ++i) acc[qs][sub][i] = 0.f;
+            const uint16_t* tb = qtile[buf] + col * RS + kh * 8;
+            bf16x8 a[QS], an[QS];
+#pragma unroll
+            for (int qs = 0; qs < QS; ++qs) a[qs] = *reinterpret_cast<const bf16x8*>(tb + qs * 32 * RS);
+#pragma unroll
+            for (int ks = 0; ks < KT; ++ks) {
+                if (ks + 1 < KT) {
+#pragma unroll
+                    for (int qs = 0; qs < QS; ++qs)
+                        an[qs] = *reinterpret_cast<const bf16x8*>(tb + qs * 32 * RS + (ks + 1) * 16);
+                }
+#pragma unroll
+                for (int qs = 0; qs < QS; ++qs)
+#pragma unroll
+                    for (int sub = 0; sub < S; ++sub)
+                        acc[qs][sub] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[qs], bfr[sub][ks], acc[qs][sub],
+                                                                               0, 0, 0);
+                if (ks + 1 < KT) {
+#pragma unroll
+                    for (int qs = 0; qs < QS; ++qs) a[qs] = an[qs];
+                }
+            }
+
+            if (dump) {
+#pragma unroll
+                for (int qs = 0; qs < QS; ++qs)
+#pragma unroll
+                    for (int sub = 0; sub < S; ++sub)
+#pragma unroll
+                        for (int i = 0; i < 16; ++i) {
+                            const int q = t * QT + qs * 32 + 8 * (i >> 2) + 4 * kh + (i & 3);
+                            const long long x = xb0 + sub * 32 + col;
+                            if (q < M && x < N) Sa.dump[(long long)q * N + x] = acc[qs][sub][i];
+                        }
+            } else {
+                float m = kNoPass;
+#pragma unroll
+                for (int qs = 0; qs < QS; ++qs)
+#pragma unroll
+                    for (int sub = 0; sub < S; ++sub)
+#pragma unroll
+                        for (int i = 0; i < 16; ++i) m = fmaxf(m, acc[qs][sub][i]);
+                const bool hit = m >= 0.f;
+                if (__ballot(hit) && hit) {
+#pragma unroll
+                    for (int qs = 0; qs < QS; ++qs)
+#pragma unroll
+                        for (int sub = 0; sub < S; ++sub)
+#pragma unroll
+                            for (int i = 0; i < 16; ++i) {
+                                if (acc[qs][sub][i] >= 0.f) {
+                                    const int q = t * QT + qs * 32 + 8 * (i >> 2) + 4 * kh + (i & 3);
+                                    const long long x = xb0 + sub * 32 + col;
+                                    if (q < M && x < N) {
+                                        const uint32_t p = atomicAdd(&ccount, 1u);
+                                        if (p < (uint32_t)kCandStage) {
+                                            cbuf[p] = make_uint2((uint32_t)q, (uint32_t)x);
+                                        } else {  // more than the stage holds in one tile
+                                            const uint32_t pos = atomicAdd(&Sa.hdr->n_cand, 1u);
+                                            if (pos < Sa.cand_cap) Sa.cand[pos] = make_uint2((uint32_t)q, (uint32_t)x);
+                                        }
+                                    }
+                                }
+                            }
+                }
+            }
+            if (more) stage_store(buf ^ 1, pre, bias);
+            __syncthreads();
+            if (ccount >= (uint32_t)(kCandStage / 2)) flush_cands();  // uniform: read after the barrier
+        }
+    }
+    __syncthreads();
+    if (ccount) flush_cands();
+}
+
+template <int KS16>
+static hipError_t launch_screen32_ks(const ScreenArgs& s, ScreenShape shape, hipStream_t st)
+{
+    const int grid = shape.grid > 0 ? shape.grid : 512;
+    if (shape.subs == 1) {
+        if (shape.qt == 64) k_screen32<KS16, 64, 1><<<grid, 256, 0, st>>>(s);
+        else k_screen32<KS16, 32, 1><<<grid, 256, 0, st>>>(s);
+    } else {
+        k_screen32<KS16, 32, 2><<<grid, 256, 0, st>>>(s);
+    }
+    return hipGetLastError();
+}
+
 template <int KS>
 static hipError_t launch_screen_ks(const ScreenArgs& s, ScreenShape shape, hipStream_t st)
 {
@@ -363,6 +584,19 @@ static hipError_t launch_screen_ks(const ScreenArgs& s, ScreenShape shape, hipSt
 
 hipError_t launch_screen(const ScreenArgs& s, int np, ScreenShape shape, hipStream_t st)
 {
+    if (shape.mfma == 32) {
+        switch (np / 32) {
+        case 1: return launch_screen32_ks<2>(s, shape, st);
+        case 2: return launch_screen32_ks<4>(s, shape, st);
+        case 3: return launch_screen32_ks<6>(s, shape, st);
+        case 4: return launch_screen32_ks<8>(s, shape, st);
+        case 5: return launch_screen32_ks<10>(s, shape, st);
+        case 6: return launch_screen32_ks<12>(s, shape, st);
+        case 7: return launch_screen32_ks<14>(s, shape, st);
+        case 8: return launch_screen32_ks<16>(s, shape, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
     switch (np / 32) {
     case 1: return launch_screen_ks<1>(s, shape, st);
     case 2: return launch_screen_ks<2>(s, shape, st);

@@ -165,7 +165,8 @@ struct RescoreArgs {
 struct ScreenShape {
     int qt;     // queries per LDS tile: 32 or 64
     int grid;   // persistent blocks
-    int subs;   // 16-series subtiles per wave held in registers: 2 (two waves per SIMD) or 4
+    int subs;   // series subtiles per wave held in registers (16 wide: 2 or 4; 32 wide: 1 or 2)
+    int mfma;   // 16: v_mfma_f32_16x16x32_bf16; 32: v_mfma_f32_32x32x16_bf16
 };
 
 hipError_t launch_to_bf16(const float* X, long long N, int n, int np, uint16_t* Xb, float* xn, hipStream_t st);
