@@ -208,13 +208,16 @@ paris_status paris_lb_scan(paris_index *idx, const float *query_dev, float thres
 
 /*
  * Per-phase device timing of paris_query_exact, with HIP events recorded on the call's stream
- * around its three kernels: [0] query summaries + approximate-search seed, [1] lower-bound
- * scan, [2] refinement + float64 resolve. paris_lb_scan adds its scan time to [1].
- * paris_set_timing(idx, 1) enables it and zeroes the totals; paris_get_timing returns the
- * summed milliseconds (ms_out3[3]) and the number of timed calls.
+ * around its kernels: [0] query summaries + approximate-search seed (+ the seed network),
+ * [1] lower-bound scan, [2] refinement + float64 resolve. paris_lb_scan adds its scan time to
+ * [1]. paris_set_timing(idx, 1) times all three phases, paris_set_timing(idx, 2) only the scan
+ * (two events per query), 0 turns timing off; each call zeroes the totals. Events are read back
+ * one query late (two event sets alternate), so timing adds no synchronisation to a query.
+ * paris_get_timing waits for the outstanding events and returns the summed milliseconds
+ * (ms_out3[3]) and the number of timed calls.
  */
 paris_status paris_set_timing(paris_index *idx, int32_t enable);
-paris_status paris_get_timing(const paris_index *idx, double *ms_out3, int64_t *n_queries);
+paris_status paris_get_timing(paris_index *idx, double *ms_out3, int64_t *n_queries);
 
 /*
  * With timing on, paris_query_batch launches its pipeline directly (not through the captured

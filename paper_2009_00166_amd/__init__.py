@@ -77,23 +77,32 @@ class Index:
         check(lib.paris_build(p, n_series, length, ctypes.byref(self.cfg),
                               ctypes.c_void_p(self.workspace.data_ptr()), nbytes, _stream_ptr(stream),
                               ctypes.byref(self._h)), "paris_build")
+        # reused by every query() call (the per-query path is latency-bound)
+        self._torch = torch
+        self._query_fn = lib.paris_query_exact
+        self._idx = ctypes.c_int64(-1)
+        self._dist = ctypes.c_double(0.0)
+        self._idx_ref = ctypes.pointer(self._idx)
+        self._dist_ref = ctypes.pointer(self._dist)
 
     # -- queries --------------------------------------------------------------------------
     def query(self, q, stream=None, with_stats: bool = False):
         """Exact 1-NN of one query (float32 [length] on the device): (index, distance[, stats])."""
-        torch = _torch()
-        qp = _dev_ptr(q, torch.float32, 1, "query")
+        torch = self._torch
+        if not (isinstance(q, torch.Tensor) and q.is_cuda and q.dtype == torch.float32 and q.dim() == 1
+                and q.is_contiguous()):
+            _dev_ptr(q, torch.float32, 1, "query")   # raises with the reason
         if q.shape[0] != self.length:
             raise ValueError("query length differs from the collection's")
-        idx = ctypes.c_int64(-1)
-        dist = ctypes.c_double(0.0)
-        st = ParisStats()
-        check(load_library().paris_query_exact(self._h, qp, ctypes.byref(idx), ctypes.byref(dist),
-                                               ctypes.byref(st) if with_stats else None,
-                                               _stream_ptr(stream)), "paris_query_exact")
+        st = ParisStats() if with_stats else None
+        s = stream if stream is not None else torch.cuda.current_stream()
+        rc = self._query_fn(self._h, q.data_ptr(), self._idx_ref, self._dist_ref,
+                            ctypes.byref(st) if with_stats else None, s.cuda_stream)
+        if rc != PARIS_OK:
+            check(rc, "paris_query_exact")
         if with_stats:
-            return int(idx.value), float(dist.value), st.as_dict()
-        return int(idx.value), float(dist.value)
+            return int(self._idx.value), float(self._dist.value), st.as_dict()
+        return int(self._idx.value), float(self._dist.value)
 
     def query_batch(self, Q, stream=None, with_stats: bool = False, out=None):
         """Exact 1-NN of every row of Q (float32 [M, length] on the device).
@@ -202,9 +211,11 @@ class Index:
                                                _stream_ptr(stream)), "paris_screen_dots")
         return out
 
-    def set_timing(self, enable: bool = True) -> None:
-        """Enable per-phase HIP-event timing of query() (and zero the totals)."""
-        check(load_library().paris_set_timing(self._h, 1 if enable else 0), "paris_set_timing")
+    def set_timing(self, enable: bool = True, scan_only: bool = False) -> None:
+        """Enable HIP-event timing of query() (all three phases, or the scan only) and zero
+        the totals."""
+        check(load_library().paris_set_timing(self._h, (2 if scan_only else 1) if enable else 0),
+              "paris_set_timing")
 
     def timing(self):
         """(summed ms per phase [prepare+seed, lbscan, refine+resolve], timed calls)."""

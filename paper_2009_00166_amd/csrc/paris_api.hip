@@ -8,6 +8,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <atomic>
 #include <mutex>
 #include <new>
 #include <unordered_set>
@@ -162,7 +163,10 @@ struct paris_index {
     int refine_blocks;
     int refine_lanes;
     bool timing;
-    hipEvent_t ev[4];
+    int timing_mode;        // paris_set_timing: 1 all three phases, 2 the scan only
+    hipEvent_t ev[2][4];    // two event sets, used alternately: a set is read back one query later
+    bool ev_pending[2];
+    int ev_set;
     double phase_ms[3];
     long long timed_queries;
     // batched path (paris_batch_attach)
@@ -258,12 +262,55 @@ bool handle_ok(const paris_index* h)
         if ((expr) != hipSuccess) return PARIS_EHIP;   \
     } while (0)
 
+// Add the durations recorded in event set `set` to the totals (waits for its last event, which
+// the queries issued since have normally long passed).
+paris_status collect_timing(paris_index* h, int set)
+{
+    hipEvent_t* ev = h->ev[set];
+    if (h->timing_mode == 1) {
+        HIP_TRY(hipEventSynchronize(ev[3]));
+        for (int k = 0; k < 3; ++k) {
+            float ms = 0.f;
+            HIP_TRY(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+            h->phase_ms[k] += ms;
+        }
+    } else {
+        HIP_TRY(hipEventSynchronize(ev[2]));
+        float ms = 0.f;
+        HIP_TRY(hipEventElapsedTime(&ms, ev[1], ev[2]));
+        h->phase_ms[1] += ms;
+    }
+    h->ev_pending[set] = false;
+    h->timed_queries += 1;
+    return PARIS_OK;
+}
+
+paris_status collect_pending(paris_index* h)
+{
+    for (int set = 0; set < 2; ++set)
+        if (h->ev_pending[set]) {
+            paris_status s = collect_timing(h, set);
+            if (s != PARIS_OK) return s;
+        }
+    return PARIS_OK;
+}
+
 paris_status run_query(paris_index* h, const float* q, hipStream_t st, long long* out_idx,
                        double* out_dist, long long qi, bool timed, QResult* host_res = nullptr)
 {
     QueryArgs a = args_for(h);
     a.host_res = host_res;
-    if (timed) HIP_TRY(hipEventRecord(h->ev[0], st));
+    int set = 0;
+    const bool all = h->timing_mode == 1;
+    if (timed) {
+        set = h->ev_set;
+        if (h->ev_pending[set]) {
+            paris_status cs = collect_timing(h, set);
+            if (cs != PARIS_OK) return cs;
+        }
+    }
+    hipEvent_t* ev = h->ev[set];
+    if (timed && all) HIP_TRY(hipEventRecord(ev[0], st));
     if (h->learned) {
         const paris_mlp* m = h->model;
         MlpQueryScratch sc{m->partq};
@@ -273,23 +320,15 @@ paris_status run_query(paris_index* h, const float* q, hipStream_t st, long long
         a.learned_cpl = learned_chunks(h);
     }
     HIP_TRY(launch_prepare_seed(a, q, st));
-    if (timed) HIP_TRY(hipEventRecord(h->ev[1], st));
+    if (timed) HIP_TRY(hipEventRecord(ev[1], st));
     HIP_TRY(launch_lbscan(a, -1.f, h->scan, st));
-    if (timed) HIP_TRY(hipEventRecord(h->ev[2], st));
+    if (timed) HIP_TRY(hipEventRecord(ev[2], st));
     HIP_TRY(launch_refine_resolve(a, q, out_idx, out_dist, qi, st));
-    if (timed) HIP_TRY(hipEventRecord(h->ev[3], st));
-    return PARIS_OK;
-}
-
-// after the stream has been synchronised: add the three phase durations to the totals
-paris_status collect_timing(paris_index* h)
-{
-    for (int k = 0; k < 3; ++k) {
-        float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, h->ev[k], h->ev[k + 1]));
-        h->phase_ms[k] += ms;
+    if (timed && all) HIP_TRY(hipEventRecord(ev[3], st));
+    if (timed) {
+        h->ev_pending[set] = true;
+        h->ev_set = set ^ 1;
     }
-    h->timed_queries += 1;
     return PARIS_OK;
 }
 
@@ -856,7 +895,12 @@ paris_status paris_build(const float* series_dev, int64_t n_series, int32_t leng
         if (v == 4 || v == 8 || v == 16) h->refine_lanes = v;
     }
     h->timing = false;
-    for (int k = 0; k < 4; ++k) h->ev[k] = nullptr;
+    h->timing_mode = 0;
+    for (int set = 0; set < 2; ++set) {
+        for (int k = 0; k < 4; ++k) h->ev[set][k] = nullptr;
+        h->ev_pending[set] = false;
+    }
+    h->ev_set = 0;
     for (int k = 0; k < 3; ++k) h->phase_ms[k] = 0.0;
     h->timed_queries = 0;
     h->host_qs = nullptr;
@@ -934,14 +978,23 @@ paris_status paris_query_exact(paris_index* h, const float* query_dev, int64_t* 
     if (!query_dev || !nn_index || !nn_dist || reinterpret_cast<uintptr_t>(query_dev) % 16 != 0)
         return PARIS_EINVAL;
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
-    h->host_res->idx = -2;  // overwritten by the resolve
+    volatile long long* flag = &h->host_res->idx;
+    *flag = -2;  // overwritten by the resolve, last of the result's fields
     paris_status s = run_query(h, query_dev, st, nullptr, nullptr, 0, h->timing, h->host_res_dev);
     if (s != PARIS_OK) return s;
-    HIP_TRY(hipStreamSynchronize(st));
-    if (h->timing) {
-        s = collect_timing(h);
-        if (s != PARIS_OK) return s;
+    // The result lands in mapped host memory: wait for it there (a stream synchronisation costs
+    // a few microseconds more). Every 1024 polls the stream is asked whether it failed or
+    // drained without producing the result.
+    for (unsigned it = 1;; ++it) {
+        if (*flag != -2) break;
+        if ((it & 1023u) == 0u) {
+            const hipError_t e = hipStreamQuery(st);
+            if (e == hipSuccess) break;          // drained: the flag is read once more below
+            if (e != hipErrorNotReady) return PARIS_EHIP;
+        }
+        __builtin_ia32_pause();
     }
+    std::atomic_thread_fence(std::memory_order_acquire);
     const QResult r = *h->host_res;
     if (r.idx == -2) return PARIS_EHIP;
     if (r.err & kErrNonFinite) return PARIS_EINVAL;
@@ -1042,10 +1095,14 @@ paris_status paris_lb_scan(paris_index* h, const float* query_dev, float thresho
         return PARIS_EINVAL;
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     QueryArgs a = args_for(h);
+    if (h->timing) {
+        paris_status ps = collect_pending(h);
+        if (ps != PARIS_OK) return ps;
+    }
     HIP_TRY(launch_prepare_seed(a, query_dev, st));
-    if (h->timing) HIP_TRY(hipEventRecord(h->ev[1], st));
+    if (h->timing) HIP_TRY(hipEventRecord(h->ev[0][1], st));
     HIP_TRY(launch_lbscan(a, threshold_sq, h->scan, st));
-    if (h->timing) HIP_TRY(hipEventRecord(h->ev[2], st));
+    if (h->timing) HIP_TRY(hipEventRecord(h->ev[0][2], st));
     HIP_TRY(hipMemcpyAsync(h->host_qs, a.qs, sizeof(QState), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     const QState& q = *h->host_qs;
@@ -1053,7 +1110,7 @@ paris_status paris_lb_scan(paris_index* h, const float* query_dev, float thresho
     const uint32_t qerr = q.err;
     if (h->timing) {  // the scan alone is added to phase [1]
         float ms = 0.f;
-        HIP_TRY(hipEventElapsedTime(&ms, h->ev[1], h->ev[2]));
+        HIP_TRY(hipEventElapsedTime(&ms, h->ev[0][1], h->ev[0][2]));
         h->phase_ms[1] += ms;
         h->timed_queries += 1;
     }
@@ -1074,11 +1131,16 @@ paris_status paris_lb_scan(paris_index* h, const float* query_dev, float thresho
 paris_status paris_set_timing(paris_index* h, int32_t enable)
 {
     if (!handle_ok(h)) return PARIS_ESTATE;
-    if (enable && !h->ev[0]) {
-        for (int k = 0; k < 4; ++k) HIP_TRY(hipEventCreate(&h->ev[k]));
+    if (enable < 0 || enable > 2) return PARIS_EINVAL;
+    if (enable && !h->ev[0][0]) {
+        for (int set = 0; set < 2; ++set)
+            for (int k = 0; k < 4; ++k) HIP_TRY(hipEventCreate(&h->ev[set][k]));
         for (int k = 0; k < 5; ++k) HIP_TRY(hipEventCreate(&h->bev[k]));
     }
     h->timing = enable != 0;
+    h->timing_mode = enable;
+    h->ev_pending[0] = h->ev_pending[1] = false;
+    h->ev_set = 0;
     for (int k = 0; k < 3; ++k) h->phase_ms[k] = 0.0;
     h->timed_queries = 0;
     for (int k = 0; k < 4; ++k) h->batch_ms[k] = 0.0;
@@ -1095,10 +1157,14 @@ paris_status paris_get_batch_timing(const paris_index* h, double* ms_out4, int64
     return PARIS_OK;
 }
 
-paris_status paris_get_timing(const paris_index* h, double* ms_out3, int64_t* n_queries)
+paris_status paris_get_timing(paris_index* h, double* ms_out3, int64_t* n_queries)
 {
     if (!handle_ok(h)) return PARIS_ESTATE;
     if (!ms_out3 || !n_queries) return PARIS_EINVAL;
+    if (h->timing) {
+        paris_status s = collect_pending(h);
+        if (s != PARIS_OK) return s;
+    }
     for (int k = 0; k < 3; ++k) ms_out3[k] = h->phase_ms[k];
     *n_queries = h->timed_queries;
     return PARIS_OK;
@@ -1115,8 +1181,9 @@ paris_status paris_free(paris_index* h)
     release_batch(h);
     if (h->host_qs) (void)hipHostFree(h->host_qs);
     if (h->host_res) (void)hipHostFree(h->host_res);
-    for (int k = 0; k < 4; ++k)
-        if (h->ev[k]) (void)hipEventDestroy(h->ev[k]);
+    for (int set = 0; set < 2; ++set)
+        for (int k = 0; k < 4; ++k)
+            if (h->ev[set][k]) (void)hipEventDestroy(h->ev[set][k]);
     for (int k = 0; k < 5; ++k)
         if (h->bev[k]) (void)hipEventDestroy(h->bev[k]);
     delete h;

@@ -672,7 +672,15 @@ __device__ void resolve_block(const QueryArgs& A, const float* __restrict__ q, l
         r.n_bsf_upd = qs->n_bsf_upd;
         r.n_resolved = nres;
         r.err = err;
-        if (A.host_res) *A.host_res = r;
+        if (A.host_res) {
+            // the host polls idx (set to -2 before the launch): every other field first, then a
+            // system-scope fence, then idx
+            QResult hr = r;
+            hr.idx = -2;
+            *A.host_res = hr;
+            __threadfence_system();
+            *reinterpret_cast<volatile long long*>(&A.host_res->idx) = r.idx;
+        }
         if (out_idx) {
             out_idx[qi] = r.idx;
             out_dist[qi] = found ? sqrt(rd[0]) : __builtin_nan("");
