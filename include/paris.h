@@ -160,6 +160,20 @@ paris_status paris_query_batch(paris_index *idx, const float *queries_dev, int64
                                void *hip_stream);
 
 /*
+ * Several collections in one call (batches mixing collections of different lengths): for every
+ * c < n_idx, the n_queries[c] queries at queries_dev[c] (float32 [n_queries[c]][length of
+ * idx[c]], device, 16-byte aligned) are answered against idx[c] as by paris_query_batch, into
+ * nn_index_dev[c] / nn_dist_dev[c] (device, [n_queries[c]]). idx, queries_dev, n_queries,
+ * nn_index_dev and nn_dist_dev are host arrays of n_idx entries; the handles must be distinct.
+ * Each collection uses its own attached batch workspace, screen shape (tuned per length) and
+ * captured graph. stats (host, may be NULL) sums the counters over all collections. Errors as
+ * for paris_query_batch; arguments of every collection are checked before any launch.
+ */
+paris_status paris_query_batch_multi(paris_index *const *idx, int32_t n_idx, const float *const *queries_dev,
+                                     const int64_t *n_queries, int64_t *const *nn_index_dev,
+                                     double *const *nn_dist_dev, paris_stats *stats, void *hip_stream);
+
+/*
  * Batched pipeline resources (the batched pattern of the paper's worker pools: many queries,
  * one launch). paris_batch_workspace_size gives the bytes for chunks of up to max_batch queries
  * (1 .. 65536): a bfloat16 copy of the collection [N][roundup(length, 32)], its norms, the

@@ -259,6 +259,33 @@ class Index:
             pass
 
 
+def query_batch_multi(indexes, queries, stream=None, with_stats: bool = False):
+    """Exact 1-NN of the rows of queries[c] (float32 [M_c, n_c] on the device) against
+    indexes[c], for every collection c, in one call: [(I_c, D_c)] (and the summed stats)."""
+    torch = _torch()
+    k = len(indexes)
+    if k != len(queries) or k == 0:
+        raise ValueError("one query tensor per index")
+    outs = []
+    qp, nq, ip, dp = (ctypes.c_void_p * k)(), (ctypes.c_int64 * k)(), (ctypes.c_void_p * k)(), (ctypes.c_void_p * k)()
+    hs = (ctypes.c_void_p * k)()
+    for c, (ix, Q) in enumerate(zip(indexes, queries)):
+        if Q.dim() != 2 or Q.shape[1] != ix.length:
+            raise ValueError("query length differs from the collection's")
+        _dev_ptr(Q, torch.float32, 2, "queries")
+        I = torch.empty(Q.shape[0], dtype=torch.int64, device=Q.device)
+        D = torch.empty(Q.shape[0], dtype=torch.float64, device=Q.device)
+        outs.append((I, D))
+        hs[c], qp[c], nq[c] = ix._h.value, Q.data_ptr(), int(Q.shape[0])
+        ip[c], dp[c] = I.data_ptr(), D.data_ptr()
+    st = ParisStats()
+    check(load_library().paris_query_batch_multi(hs, k, qp, nq, ip, dp, ctypes.byref(st) if with_stats else None,
+                                                 _stream_ptr(stream)), "paris_query_batch_multi")
+    return (outs, st.as_dict()) if with_stats else outs
+
+
+__all__ += ["query_batch_multi"]
+
 from .learned import SeedModel, init_params, query_features, train_seed_model  # noqa: E402,F401
 
 __all__ += ["SeedModel", "init_params", "query_features", "train_seed_model"]

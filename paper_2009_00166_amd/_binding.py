@@ -62,6 +62,7 @@ SIGNATURES = [
     ("paris_query_exact", ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_int64),
                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ParisStats), _P]),
     ("paris_query_batch", ctypes.c_int, [_P, _P, _I64, _P, _P, ctypes.POINTER(ParisStats), _P]),
+    ("paris_query_batch_multi", ctypes.c_int, [_P, _I32, _P, _P, _P, _P, ctypes.POINTER(ParisStats), _P]),
     ("paris_query_info_get", ctypes.c_int, [_P, _P, ctypes.POINTER(ParisQueryInfo), _P, _P, _P]),
     ("paris_lb_scan", ctypes.c_int, [_P, _P, _F32, _P, _P, _I64, ctypes.POINTER(ctypes.c_int64), _P]),
     ("paris_batch_workspace_size", ctypes.c_int, [_P, _I32, ctypes.POINTER(ctypes.c_size_t)]),

@@ -173,7 +173,8 @@ struct paris_index {
     uint8_t* bws;
     size_t bws_bytes;
     int max_batch;
-    int np;
+    int np;     // screened dimensions rounded up to 32
+    int proj;   // segment length of the screen's projection (1: n <= 256, the series itself)
     bool screen_ok;
     struct {
         size_t hdr, xb, xn, qin, qb, bq, cand, cand_d2, oidx, odist, fb, leaves, total;
@@ -594,6 +595,7 @@ paris_status launch_batch_pipeline(paris_index* h, int m, hipStream_t st, bool t
     sb.bq = bqs(h);
     sb.qb = reinterpret_cast<uint16_t*>(h->bws + h->bp.qb);
     sb.np = h->np;
+    sb.P = h->proj;
     sb.leaves = nullptr;
     if (timed) HIP_TRY(hipEventRecord(h->bev[0], st));
     HIP_TRY(launch_batch_init(bqs(h), m, bhdr(h), st));
@@ -606,7 +608,7 @@ paris_status launch_batch_pipeline(paris_index* h, int m, hipStream_t st, bool t
         al.learned_cpl = learned_chunks(h);
     }
     HIP_TRY(launch_prepare_seed_batch(al, sb, m, st));
-    HIP_TRY(launch_batch_thresholds(bqs(h), m, h->c_screen, h->seed_rel, st));
+    HIP_TRY(launch_batch_thresholds(bqs(h), m, h->c_screen, h->seed_rel, h->proj, st));
     if (timed) HIP_TRY(hipEventRecord(h->bev[1], st));
     HIP_TRY(launch_screen(screen_args(h, m, nullptr), h->np, h->screen, st));
     if (timed) HIP_TRY(hipEventRecord(h->bev[2], st));
@@ -746,6 +748,45 @@ void release_batch(paris_index* h)
     h->screen_ok = false;
 }
 
+// All queries of one collection: chunks of max_batch through the batched pipeline, or one by one
+// through the per-query path when no batch workspace is attached. Counters are added to *agg.
+paris_status batch_core(paris_index* h, const float* queries_dev, long long n_queries, int64_t* nn_index_dev,
+                        double* nn_dist_dev, bool want_stats, paris_stats* agg, hipStream_t st)
+{
+    if (batch_screen_usable(h)) {
+        long long cands = 0, fallbacks = 0;
+        for (long long q0 = 0; q0 < n_queries; q0 += h->max_batch) {
+            const int m = (int)((n_queries - q0) < h->max_batch ? (n_queries - q0) : h->max_batch);
+            paris_status s = run_batch_chunk(h, queries_dev, q0, m, reinterpret_cast<long long*>(nn_index_dev),
+                                             nn_dist_dev, st, &cands, &fallbacks);
+            if (s != PARIS_OK) return s;
+        }
+        h->batch_candidates += cands;
+        agg->lb_survivors += cands;
+        agg->refined += cands;
+        agg->resolved += fallbacks;
+        return PARIS_OK;
+    }
+    for (long long i = 0; i < n_queries; ++i) {
+        const float* q = queries_dev + i * (long long)h->n;
+        paris_status s = run_query(h, q, st, reinterpret_cast<long long*>(nn_index_dev), nn_dist_dev, i, false);
+        if (s != PARIS_OK) return s;
+        if (want_stats) {
+            HIP_TRY(hipMemcpyAsync(&h->host_qs->res, &reinterpret_cast<QState*>(h->ws + h->plan.qs)->res,
+                                   sizeof(QResult), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            paris_stats one;
+            fill_stats(h->host_qs->res, &one);
+            agg->lb_survivors += one.lb_survivors;
+            agg->refined += one.refined;
+            agg->abandoned += one.abandoned;
+            agg->bsf_updates += one.bsf_updates;
+            agg->resolved += one.resolved;
+        }
+    }
+    return PARIS_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -781,11 +822,12 @@ paris_status paris_batch_attach(paris_index* h, void* workspace_dev, size_t work
         release_batch(h);
         return PARIS_EHIP;
     }
-    // the screen keeps a query tile's k-steps in registers: lengths up to 256
+    // the screen keeps a query tile's k-steps in registers: up to 256 dimensions (longer series
+    // are screened on segment means, see batch_dims)
     h->screen_ok = h->np <= 256;
     if (!h->screen_ok) return PARIS_OK;  // batches then use the per-query path
     paris_status s = PARIS_OK;
-    if (launch_to_bf16(h->X, h->N, h->n, h->np, reinterpret_cast<uint16_t*>(h->bws + h->bp.xb),
+    if (launch_to_bf16(h->X, h->N, h->n, h->np, h->proj, reinterpret_cast<uint16_t*>(h->bws + h->bp.xb),
                        reinterpret_cast<float*>(h->bws + h->bp.xn), st) != hipSuccess)
         s = PARIS_EHIP;
     if (s == PARIS_OK) s = tune_screen(h, st);
@@ -811,6 +853,7 @@ paris_status paris_screen_dots(paris_index* h, const float* queries_dev, int32_t
     sb.bq = bqs(h);
     sb.qb = reinterpret_cast<uint16_t*>(h->bws + h->bp.qb);
     sb.np = h->np;
+    sb.P = h->proj;
     sb.leaves = nullptr;
     HIP_TRY(hipMemcpyAsync(h->bws + h->bp.qin, queries_dev, (size_t)m * h->n * 4, hipMemcpyDeviceToDevice, st));
     HIP_TRY(launch_batch_init(bqs(h), m, bhdr(h), st));
@@ -909,11 +952,13 @@ paris_status paris_build(const float* series_dev, int64_t n_series, int32_t leng
     h->bws = nullptr;
     h->bws_bytes = 0;
     h->max_batch = 0;
-    h->np = (length + 31) / 32 * 32;
+    h->proj = 1;
+    while (length / h->proj > 256 || length % h->proj != 0) ++h->proj;   // n / P <= 256 dimensions
+    h->np = (length / h->proj + 31) / 32 * 32;
     h->screen_ok = false;
     std::memset(&h->bp, 0, sizeof(h->bp));
     h->screen = ScreenShape{64, 0, 4, 16};
-    h->c_screen = screen_margin(length, h->np);
+    h->c_screen = screen_margin(length / h->proj, h->np);
     // the seed series' exact squared distance is at most d32 (1 + g) / (1 - g) < d32 (1 + 3 g)
     h->seed_rel = 3.0 * gamma_k(length + 2) + std::ldexp(1.0, -30);
     h->graph = nullptr;
@@ -1013,44 +1058,41 @@ paris_status paris_query_batch(paris_index* h, const float* queries_dev, int64_t
     if (!queries_dev || !nn_index_dev || !nn_dist_dev || n_queries < 0 ||
         reinterpret_cast<uintptr_t>(queries_dev) % 16 != 0)
         return PARIS_EINVAL;
+    paris_stats agg;
+    std::memset(&agg, 0, sizeof(agg));
+    paris_status s = batch_core(h, queries_dev, n_queries, nn_index_dev, nn_dist_dev, stats != nullptr, &agg,
+                                reinterpret_cast<hipStream_t>(hip_stream));
+    if (s != PARIS_OK) return s;
+    if (stats) {
+        agg.seed_index = -1;
+        agg.seed_dist = INFINITY;
+        *stats = agg;
+    }
+    return PARIS_OK;
+}
+
+paris_status paris_query_batch_multi(paris_index* const* idx, int32_t n_idx, const float* const* queries_dev,
+                                     const int64_t* n_queries, int64_t* const* nn_index_dev,
+                                     double* const* nn_dist_dev, paris_stats* stats, void* hip_stream)
+{
+    if (!idx || n_idx < 1 || !queries_dev || !n_queries || !nn_index_dev || !nn_dist_dev) return PARIS_EINVAL;
+    for (int32_t c = 0; c < n_idx; ++c) {
+        if (!handle_ok(idx[c])) return PARIS_ESTATE;
+        for (int32_t d = 0; d < c; ++d)
+            if (idx[d] == idx[c]) return PARIS_EINVAL;   // one in-flight call per handle
+        if (n_queries[c] < 0) return PARIS_EINVAL;
+        if (n_queries[c] > 0 && (!queries_dev[c] || !nn_index_dev[c] || !nn_dist_dev[c] ||
+                                 reinterpret_cast<uintptr_t>(queries_dev[c]) % 16 != 0))
+            return PARIS_EINVAL;
+    }
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     paris_stats agg;
     std::memset(&agg, 0, sizeof(agg));
-    if (batch_screen_usable(h)) {
-        long long cands = 0, fallbacks = 0;
-        for (long long q0 = 0; q0 < n_queries; q0 += h->max_batch) {
-            const int m = (int)((n_queries - q0) < h->max_batch ? (n_queries - q0) : h->max_batch);
-            paris_status s = run_batch_chunk(h, queries_dev, q0, m, reinterpret_cast<long long*>(nn_index_dev),
-                                             nn_dist_dev, st, &cands, &fallbacks);
-            if (s != PARIS_OK) return s;
-        }
-        h->batch_candidates += cands;
-        if (stats) {
-            agg.lb_survivors = cands;
-            agg.refined = cands;
-            agg.resolved = fallbacks;
-            agg.seed_index = -1;
-            agg.seed_dist = INFINITY;
-            *stats = agg;
-        }
-        return PARIS_OK;
-    }
-    for (long long i = 0; i < n_queries; ++i) {
-        const float* q = queries_dev + i * (long long)h->n;
-        paris_status s = run_query(h, q, st, reinterpret_cast<long long*>(nn_index_dev), nn_dist_dev, i, false);
+    for (int32_t c = 0; c < n_idx; ++c) {
+        if (n_queries[c] == 0) continue;
+        paris_status s = batch_core(idx[c], queries_dev[c], n_queries[c], nn_index_dev[c], nn_dist_dev[c],
+                                    stats != nullptr, &agg, st);
         if (s != PARIS_OK) return s;
-        if (stats) {
-            HIP_TRY(hipMemcpyAsync(&h->host_qs->res, &reinterpret_cast<QState*>(h->ws + h->plan.qs)->res,
-                                   sizeof(QResult), hipMemcpyDeviceToHost, st));
-            HIP_TRY(hipStreamSynchronize(st));
-            paris_stats one;
-            fill_stats(h->host_qs->res, &one);
-            agg.lb_survivors += one.lb_survivors;
-            agg.refined += one.refined;
-            agg.abandoned += one.abandoned;
-            agg.bsf_updates += one.bsf_updates;
-            agg.resolved += one.resolved;
-        }
     }
     if (stats) {
         agg.seed_index = -1;

@@ -73,18 +73,32 @@ __device__ __forceinline__ uint2 bias_pair(float t)
 // ------------------------------------------------------------------------------------------
 // Collection -> zero-padded bfloat16 rows [N][np] and float32 squared norms (one wave per row).
 // ------------------------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void k_to_bf16(const float* __restrict__ X, long long N, int n, int np,
+// Series longer than the screen's 256 dimensions are screened on their segment means over
+// segments of P points (P the smallest divisor of n with n / P <= 256): for the mean vectors p,
+// P ||p_q - p_x||^2 <= ||q - x||^2 (Cauchy-Schwarz on every segment), so the projected distance
+// is a lower bound and pruning on it stays exact; the threshold is divided by P instead of
+// scaling the vectors (k_batch_thresholds). P = 1 is the series itself.
+__device__ __forceinline__ float seg_mean(const float* __restrict__ x, int j, int P)
+{
+    if (P == 1) return x[j];
+    double acc = 0.0;
+    for (int i = 0; i < P; ++i) acc = acc + (double)x[j * P + i];
+    return (float)(acc / (double)P);
+}
+
+__global__ __launch_bounds__(256) void k_to_bf16(const float* __restrict__ X, long long N, int n, int np, int P,
                                                  uint16_t* __restrict__ Xb, float* __restrict__ xn)
 {
     const int lane = threadIdx.x & 63;
     const long long wave = ((long long)blockIdx.x * 256 + threadIdx.x) >> 6;
     const long long nw = (long long)gridDim.x * 4;
+    const int nd = n / P;
     for (long long i = wave; i < N; i += nw) {
         const float* row = X + i * n;
         uint16_t* out = Xb + i * np;
         float sq = 0.f;
         for (int j = lane; j < np; j += 64) {
-            const float v = j < n ? row[j] : 0.f;
+            const float v = j < nd ? seg_mean(row, j, P) : 0.f;
             out[j] = to_bf16(v);
             sq += v * v;
         }
@@ -93,11 +107,11 @@ __global__ __launch_bounds__(256) void k_to_bf16(const float* __restrict__ X, lo
     }
 }
 
-hipError_t launch_to_bf16(const float* X, long long N, int n, int np, uint16_t* Xb, float* xn, hipStream_t st)
+hipError_t launch_to_bf16(const float* X, long long N, int n, int np, int P, uint16_t* Xb, float* xn, hipStream_t st)
 {
     long long blocks = (N + 3) / 4;
     if (blocks > 65536) blocks = 65536;
-    k_to_bf16<<<(unsigned)blocks, 256, 0, st>>>(X, N, n, np, Xb, xn);
+    k_to_bf16<<<(unsigned)blocks, 256, 0, st>>>(X, N, n, np, P, Xb, xn);
     return hipGetLastError();
 }
 
@@ -124,14 +138,16 @@ __global__ void k_batch_init(BQuery* __restrict__ bq, int M, BatchHdr* __restric
     }
 }
 
-// Screen threshold constant of every query from its seed (U_q = seed distance rounded up).
-__global__ void k_batch_thresholds(BQuery* __restrict__ bq, int M, float c_screen, double seed_rel)
+// Screen threshold constant of every query from its seed (U_q = seed distance rounded up, in
+// units of the screened vectors: divided by the segment length P of a projected screen).
+__global__ void k_batch_thresholds(BQuery* __restrict__ bq, int M, float c_screen, double seed_rel, int P)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= M) return;
     BQuery& b = bq[q];
     if (b.err || b.bsf_key == kBsfInit) { b.a = __builtin_inff(); return; }  // nothing to screen
-    const double U = (double)key_dist_b(b.bsf_key) * (1.0 + seed_rel) + 1e-20;
+    double U = (double)key_dist_b(b.bsf_key) * (1.0 + seed_rel) + 1e-20;
+    if (P > 1) U = U / (double)P * (1.0 + 0x1p-50);
     const double a = ((1.0 - (double)c_screen) * (double)b.qn - U) * 0.5;
     b.a = __double2float_rd(a);
 }
@@ -747,9 +763,9 @@ hipError_t launch_batch_init(BQuery* bq, int M, BatchHdr* hdr, hipStream_t st)
     return hipGetLastError();
 }
 
-hipError_t launch_batch_thresholds(BQuery* bq, int M, float c_screen, double seed_rel, hipStream_t st)
+hipError_t launch_batch_thresholds(BQuery* bq, int M, float c_screen, double seed_rel, int P, hipStream_t st)
 {
-    k_batch_thresholds<<<(M + 255) / 256, 256, 0, st>>>(bq, M, c_screen, seed_rel);
+    k_batch_thresholds<<<(M + 255) / 256, 256, 0, st>>>(bq, M, c_screen, seed_rel, P);
     return hipGetLastError();
 }
 

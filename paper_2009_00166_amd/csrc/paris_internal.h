@@ -124,7 +124,8 @@ struct SeedBatch {
     const float* Q;       // [M][n] float32 queries
     BQuery* bq;           // [M]
     uint16_t* qb;         // [M][np] bfloat16 copies, zero padded
-    int np;               // n rounded up to a multiple of 32
+    int np;               // screened dimensions (n / P) rounded up to a multiple of 32
+    int P;                // segment length of the screen's projection (1: the series itself)
     const int32_t* leaves;  // learned seed: [M][kTopLeaves] leaf ids (used when learned_cpl > 0)
 };
 
@@ -169,9 +170,9 @@ struct ScreenShape {
     int mfma;   // 16: v_mfma_f32_16x16x32_bf16; 32: v_mfma_f32_32x32x16_bf16
 };
 
-hipError_t launch_to_bf16(const float* X, long long N, int n, int np, uint16_t* Xb, float* xn, hipStream_t st);
+hipError_t launch_to_bf16(const float* X, long long N, int n, int np, int P, uint16_t* Xb, float* xn, hipStream_t st);
 hipError_t launch_batch_init(BQuery* bq, int M, BatchHdr* hdr, hipStream_t st);
-hipError_t launch_batch_thresholds(BQuery* bq, int M, float c_screen, double seed_rel, hipStream_t st);
+hipError_t launch_batch_thresholds(BQuery* bq, int M, float c_screen, double seed_rel, int P, hipStream_t st);
 hipError_t launch_screen(const ScreenArgs& s, int np, ScreenShape shape, hipStream_t st);
 hipError_t launch_rescore(const RescoreArgs& r, hipStream_t st);
 hipError_t launch_batch_resolve(const RescoreArgs& r, long long* out_idx, double* out_dist, hipStream_t st);

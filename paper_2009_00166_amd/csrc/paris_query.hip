@@ -208,10 +208,21 @@ __global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* 
     __syncthreads();
     if (batch && blockIdx.x == 0) {
         // bfloat16 copy of the query (zero padded to np) and its float32 squared norm
+        // (segment means over B.P points when the screen works on a projection of the series)
         uint16_t* qb = B.qb + (long long)blockIdx.y * B.np;
+        const int nd = n / B.P;
         float sq = 0.f;
         for (int j = tid; j < B.np; j += 256) {
-            const float v = j < n ? qv[j] : 0.f;
+            float v = 0.f;
+            if (j < nd) {
+                if (B.P == 1) {
+                    v = qv[j];
+                } else {
+                    double acc = 0.0;
+                    for (int i = 0; i < B.P; ++i) acc = acc + (double)qv[j * B.P + i];
+                    v = (float)(acc / (double)B.P);
+                }
+            }
             qb[j] = bf16_rne(v);
             sq += v * v;
         }
@@ -387,7 +398,7 @@ int seed_grid(const QueryArgs& a)
 
 hipError_t launch_prepare_seed(const QueryArgs& a, const float* q, hipStream_t st)
 {
-    SeedBatch none{nullptr, nullptr, nullptr, 0, nullptr};
+    SeedBatch none{nullptr, nullptr, nullptr, 0, 1, nullptr};
     k_prepare_seed<<<seed_grid(a), 256, (size_t)a.n * sizeof(float), st>>>(a, q, none);
     return hipGetLastError();
 }

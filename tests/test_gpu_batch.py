@@ -141,15 +141,71 @@ def test_batch_other_lengths(n, oracle_native):
     idx.close()
 
 
-def test_long_series_fall_back_to_per_query_path(oracle_native):
+@pytest.mark.parametrize("n", [272, 512, 1024, 2048])
+def test_long_series_screened_on_segment_means(n, oracle_native):
+    """Series longer than 256 points are screened on segment means (a lower bound of the
+    distance); answers stay exact and the screen still prunes."""
     _need_gpu()
     import paper_2009_00166_amd as paris
-    X = synth.random_walks(5000, 512, seed=9)
-    Q, _, _ = synth.noisy_queries(X, 20, seed=4, sigma=0.3)
-    ri, _, _ = oracle_native.nn_many(Q, X, threads=16)
+    N = 6000 if n < 2048 else 3000
+    X = synth.random_walks(N, n, seed=9)
+    Q, _, _ = synth.noisy_queries(X, 40, seed=4, sigma=(0.05, 0.5))
+    ri, rd, _ = oracle_native.nn_many(Q, X, threads=16)
     idx = paris.build(torch.from_numpy(X).cuda())
     idx.attach_batch(max_batch=32)
-    I, _ = idx.query_batch(torch.from_numpy(Q).cuda())
+    I, D, st = idx.query_batch(torch.from_numpy(Q).cuda(), with_stats=True)
     torch.cuda.synchronize()
     assert np.array_equal(I.cpu().numpy(), ri)
+    assert np.array_equal(D.cpu().numpy(), np.sqrt(rd))
+    assert st["lb_survivors"] < 0.2 * N * len(Q)      # the projected screen prunes most pairs
     idx.close()
+
+
+def test_projected_screen_bound_and_lower_bound():
+    """n = 1024 is screened on means of 4-point segments: the bfloat16 dot products obey the
+    screen's bound for the projected vectors, and 4 |p_q - p_x|^2 <= |q - x|^2."""
+    _need_gpu()
+    import paper_2009_00166_amd as paris
+    n, P = 1024, 4
+    X = synth.random_walks(3000, n, seed=13)
+    Q, _, _ = synth.noisy_queries(X, 64, seed=14, sigma=(0.0, 1.0))
+    idx = paris.build(torch.from_numpy(X).cuda())
+    idx.attach_batch(max_batch=64)
+    dots = idx.screen_dots(torch.from_numpy(Q).cuda()).cpu().numpy().astype(np.float64)
+    px = X.astype(np.float64).reshape(3000, n // P, P).mean(axis=2)
+    pq = Q.astype(np.float64).reshape(64, n // P, P).mean(axis=2)
+    exact = pq @ px.T
+    qn = (pq ** 2).sum(1)[:, None]
+    xn = (px ** 2).sum(1)[None, :]
+    c = _screen_margin(n // P, n // P)
+    assert np.all(np.abs((qn + xn - 2 * dots) - (qn + xn - 2 * exact)) <= c * (qn + xn))
+    d2 = ((Q.astype(np.float64)[:, None, :] - X.astype(np.float64)[None, :, :]) ** 2).sum(-1)
+    assert np.all(P * (qn + xn - 2 * exact) <= d2 * (1 + 1e-12) + 1e-9)
+    idx.close()
+
+
+def test_query_batch_multi_mixed_lengths(oracle_native):
+    """Three collections of lengths 128, 512 and 1024 in one call, each with its own tuned
+    screen; answers identical to the oracle."""
+    _need_gpu()
+    import paper_2009_00166_amd as paris
+    specs = [(30_000, 128, 1), (8_000, 512, 2), (4_000, 1024, 3)]
+    idxs, Qs, refs = [], [], []
+    for N, n, seed in specs:
+        X = synth.random_walks(N, n, seed=seed)
+        m = {128: 120, 512: 80, 1024: 56}[n]
+        Q, _, _ = synth.noisy_queries(X, m, seed=seed + 10, sigma=(0.05, 0.5))
+        ri, rd, _ = oracle_native.nn_many(Q, X, threads=16)
+        ix = paris.build(torch.from_numpy(X).cuda())
+        ix.attach_batch(max_batch=64)     # chunks of 64 plus a partial chunk per collection
+        idxs.append(ix)
+        Qs.append(torch.from_numpy(Q).cuda())
+        refs.append((ri, np.sqrt(rd)))
+    outs, st = paris.query_batch_multi(idxs, Qs, with_stats=True)
+    torch.cuda.synchronize()
+    for (I, D), (ri, rdist) in zip(outs, refs):
+        assert np.array_equal(I.cpu().numpy(), ri)
+        assert np.array_equal(D.cpu().numpy(), rdist)
+    assert st["lb_survivors"] > 0
+    for ix in idxs:
+        ix.close()
