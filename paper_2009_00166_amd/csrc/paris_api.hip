@@ -712,6 +712,12 @@ paris_status tune_screen(paris_index* h, hipStream_t st)
     ScreenShape pick{64, cus, 4, 16};
     const ScreenShape cands[] = {{32, cus * 2, 2, 16}, {64, cus * 2, 2, 16}, {32, cus, 4, 16}, {64, cus, 4, 16},
                                  {32, cus * 2, 2, 32}, {64, cus * 2, 1, 32}, {32, cus * 2, 1, 32}};
+    if (h->np > 256) {   // one form serves more than 256 dimensions
+        h->screen = ScreenShape{32, cus * 2, 1, 32};
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+        return PARIS_OK;
+    }
     for (const ScreenShape& sh : cands) {
         float t[3];
         for (int r = 0; r < 4; ++r) {
@@ -822,9 +828,9 @@ paris_status paris_batch_attach(paris_index* h, void* workspace_dev, size_t work
         release_batch(h);
         return PARIS_EHIP;
     }
-    // the screen keeps a query tile's k-steps in registers: up to 256 dimensions (longer series
-    // are screened on segment means, see batch_dims)
-    h->screen_ok = h->np <= 256;
+    // the screen keeps a wave's series fragments in registers: up to 512 dimensions (longer
+    // series are screened on segment means)
+    h->screen_ok = h->np <= 512;
     if (!h->screen_ok) return PARIS_OK;  // batches then use the per-query path
     paris_status s = PARIS_OK;
     if (launch_to_bf16(h->X, h->N, h->n, h->np, h->proj, reinterpret_cast<uint16_t*>(h->bws + h->bp.xb),
@@ -953,7 +959,7 @@ paris_status paris_build(const float* series_dev, int64_t n_series, int32_t leng
     h->bws_bytes = 0;
     h->max_batch = 0;
     h->proj = 1;
-    while (length / h->proj > 256 || length % h->proj != 0) ++h->proj;   // n / P <= 256 dimensions
+    while (length / h->proj > 512 || length % h->proj != 0) ++h->proj;   // n / P <= 512 dimensions
     h->np = (length / h->proj + 31) / 32 * 32;
     h->screen_ok = false;
     std::memset(&h->bp, 0, sizeof(h->bp));

@@ -73,8 +73,8 @@ __device__ __forceinline__ uint2 bias_pair(float t)
 // ------------------------------------------------------------------------------------------
 // Collection -> zero-padded bfloat16 rows [N][np] and float32 squared norms (one wave per row).
 // ------------------------------------------------------------------------------------------
-// Series longer than the screen's 256 dimensions are screened on their segment means over
-// segments of P points (P the smallest divisor of n with n / P <= 256): for the mean vectors p,
+// Series longer than the screen's 512 dimensions are screened on their segment means over
+// segments of P points (P the smallest divisor of n with n / P <= 512): for the mean vectors p,
 // P ||p_q - p_x||^2 <= ||q - x||^2 (Cauchy-Schwarz on every segment), so the projected distance
 // is a lower bound and pruning on it stays exact; the threshold is divided by P instead of
 // scaling the vectors (k_batch_thresholds). P = 1 is the series itself.
@@ -575,11 +575,17 @@ template <int KS16>
 static hipError_t launch_screen32_ks(const ScreenArgs& s, ScreenShape shape, hipStream_t st)
 {
     const int grid = shape.grid > 0 ? shape.grid : 512;
-    if (shape.subs == 1) {
-        if (shape.qt == 64) k_screen32<KS16, 64, 1><<<grid, 256, 0, st>>>(s);
-        else k_screen32<KS16, 32, 1><<<grid, 256, 0, st>>>(s);
+    if constexpr (KS16 > 16) {
+        // more than 256 dimensions: one 32-series subtile per wave and 32-row query tiles (the
+        // series fragments alone take 4 (KS16 + 1) registers)
+        k_screen32<KS16, 32, 1><<<grid, 256, 0, st>>>(s);
     } else {
-        k_screen32<KS16, 32, 2><<<grid, 256, 0, st>>>(s);
+        if (shape.subs == 1) {
+            if (shape.qt == 64) k_screen32<KS16, 64, 1><<<grid, 256, 0, st>>>(s);
+            else k_screen32<KS16, 32, 1><<<grid, 256, 0, st>>>(s);
+        } else {
+            k_screen32<KS16, 32, 2><<<grid, 256, 0, st>>>(s);
+        }
     }
     return hipGetLastError();
 }
@@ -610,9 +616,18 @@ hipError_t launch_screen(const ScreenArgs& s, int np, ScreenShape shape, hipStre
         case 6: return launch_screen32_ks<12>(s, shape, st);
         case 7: return launch_screen32_ks<14>(s, shape, st);
         case 8: return launch_screen32_ks<16>(s, shape, st);
+        case 9: return launch_screen32_ks<18>(s, shape, st);
+        case 10: return launch_screen32_ks<20>(s, shape, st);
+        case 11: return launch_screen32_ks<22>(s, shape, st);
+        case 12: return launch_screen32_ks<24>(s, shape, st);
+        case 13: return launch_screen32_ks<26>(s, shape, st);
+        case 14: return launch_screen32_ks<28>(s, shape, st);
+        case 15: return launch_screen32_ks<30>(s, shape, st);
+        case 16: return launch_screen32_ks<32>(s, shape, st);
         default: return hipErrorInvalidValue;
         }
     }
+    if (np > 256) return hipErrorInvalidValue;   // the 16-wide form holds at most 256 dimensions
     switch (np / 32) {
     case 1: return launch_screen_ks<1>(s, shape, st);
     case 2: return launch_screen_ks<2>(s, shape, st);

@@ -162,11 +162,11 @@ def test_long_series_screened_on_segment_means(n, oracle_native):
 
 
 def test_projected_screen_bound_and_lower_bound():
-    """n = 1024 is screened on means of 4-point segments: the bfloat16 dot products obey the
+    """n = 2048 is screened on means of 4-point segments: the bfloat16 dot products obey the
     screen's bound for the projected vectors, and 4 |p_q - p_x|^2 <= |q - x|^2."""
     _need_gpu()
     import paper_2009_00166_amd as paris
-    n, P = 1024, 4
+    n, P = 2048, 4
     X = synth.random_walks(3000, n, seed=13)
     Q, _, _ = synth.noisy_queries(X, 64, seed=14, sigma=(0.0, 1.0))
     idx = paris.build(torch.from_numpy(X).cuda())
@@ -181,6 +181,24 @@ def test_projected_screen_bound_and_lower_bound():
     assert np.all(np.abs((qn + xn - 2 * dots) - (qn + xn - 2 * exact)) <= c * (qn + xn))
     d2 = ((Q.astype(np.float64)[:, None, :] - X.astype(np.float64)[None, :, :]) ** 2).sum(-1)
     assert np.all(P * (qn + xn - 2 * exact) <= d2 * (1 + 1e-12) + 1e-9)
+    idx.close()
+
+
+def test_screen_dot_error_bound_512_dimensions():
+    """Lengths 257..512 run the 32-wide screen with all dimensions: the bound on 512-point rows."""
+    _need_gpu()
+    import paper_2009_00166_amd as paris
+    X = synth.random_walks(4000, 512, seed=15)
+    Q, _, _ = synth.noisy_queries(X, 64, seed=16, sigma=(0.0, 1.0))
+    idx = paris.build(torch.from_numpy(X).cuda())
+    idx.attach_batch(max_batch=64)
+    dots = idx.screen_dots(torch.from_numpy(Q).cuda()).cpu().numpy().astype(np.float64)
+    Xf, Qf = X.astype(np.float64), Q.astype(np.float64)
+    exact = Qf @ Xf.T
+    qn = (Qf ** 2).sum(1)[:, None]
+    xn = (Xf ** 2).sum(1)[None, :]
+    c = _screen_margin(512, 512)
+    assert np.all(np.abs(2 * dots - 2 * exact) <= c * (qn + xn))
     idx.close()
 
 
