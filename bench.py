@@ -103,6 +103,9 @@ def main() -> int:
     ap.add_argument("--train-queries", type=int, default=200_000)
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--eval-queries", type=int, default=1000)
+    ap.add_argument("--learned-series", type=int, default=0,
+                    help="collection size of the learned-seed section (0: the main collection)")
+    ap.add_argument("--learned-only", action="store_true", help="run only the learned-seed section")
     ap.add_argument("--multi", action="store_true",
                     help="the mixed-length workload instead: 100M x 128 + 20M x 512 + 5M x 1024")
     ap.add_argument("--multi-scale", type=float, default=1.0,
@@ -127,6 +130,13 @@ def main() -> int:
     dev = torch.device("cuda:0")
     if args.multi:
         rec = multi_section(args)
+        print(json.dumps(rec), flush=True)
+        return 0
+    if args.learned_only:
+        args._plain_qps = None
+        N = args.learned_series or args.series
+        X = synth.random_walks(N, args.length, seed=0, threads=16)
+        rec = {"metric": "learned best-so-far seed", "learned": learned_section(torch.from_numpy(X).to(dev), X, args)}
         print(json.dumps(rec), flush=True)
         return 0
     N, n, M = args.series, args.length, args.queries
@@ -222,7 +232,12 @@ def main() -> int:
     if not args.no_batched:
         rec["batched"] = batched_section(index, X, args)
     if not args.no_learned:
-        rec["learned"] = learned_section(Xd, X, args)
+        if args.learned_series and args.learned_series != N:
+            index.close()   # frees the library state; the workspace goes with the object
+            XL = synth.random_walks(args.learned_series, n, seed=0, threads=16)
+            rec["learned"] = learned_section(torch.from_numpy(XL).to(dev), XL, args)
+        else:
+            rec["learned"] = learned_section(Xd, X, args)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")
         rec["cpu_baseline"] = cpu_baseline(X, Q, answers, min(args.cpu_queries, M), args.cpu_threads)
@@ -373,6 +388,14 @@ def learned_section(Xd, X, args):
     a0, plain = per_query(False)
     a1, learned = per_query(True)
     log(f"hard queries: plain {plain['queries_per_s']:.0f} q/s, learned {learned['queries_per_s']:.0f} q/s")
+    oracle_check = None
+    if not args.no_cpu_baseline:
+        from oracle import native
+        native.build(force=False)
+        k = min(8, len(rows))
+        ri, _, _ = native.nn_many(Qe[:k], X, threads=args.cpu_threads)
+        oracle_check = {"queries": k, "learned_answers_equal_oracle": bool(np.array_equal(ri, np.array(a1[:k]))),
+                        "plain_answers_equal_oracle": bool(np.array_equal(ri, np.array(a0[:k])))}
 
     B = args.batch
     Qb, _, _ = synth.noisy_queries(X, B, seed=1, sigma=(0.01, 0.5))
@@ -405,7 +428,8 @@ def learned_section(Xd, X, args):
         "label_s": label_s, "train_s": train_s, "train_steps": steps, "loss_first_epoch": hist[0],
         "loss_last_epoch": hist[-1],
         "hard_queries": {"count": len(rows), "plain_seed": plain, "learned_seed": learned,
-                         "answers_identical": bool(np.array_equal(np.array(a0), np.array(a1)))},
+                         "answers_identical": bool(np.array_equal(np.array(a0), np.array(a1))),
+                         "oracle_sample": oracle_check},
         "batched": {"plain_seed": res[False], "learned_seed": res[True], "answers_identical": same_batch,
                     "learned_vs_plain_per_query_path": (res[True]["queries_per_s"] / args._plain_qps
                                                         if args._plain_qps else None)},

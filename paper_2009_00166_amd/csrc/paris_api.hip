@@ -698,8 +698,8 @@ paris_status tune_screen(paris_index* h, hipStream_t st)
             h->screen = ScreenShape{qt, cus * (subs == 2 ? 2 : 1), subs, 16};
             return PARIS_OK;
         }
-        if (got == 3 && mf == 32 && ((qt == 32 && (subs == 1 || subs == 2)) || (qt == 64 && subs == 1))) {
-            h->screen = ScreenShape{qt, cus * 2, subs, 32};
+        if (got == 3 && mf == 32 && (qt == 32 || qt == 64) && (subs == 1 || subs == 2)) {
+            h->screen = ScreenShape{qt, cus * (qt * subs > 64 ? 1 : 2), subs, 32};
             return PARIS_OK;
         }
     }
@@ -711,7 +711,8 @@ paris_status tune_screen(paris_index* h, hipStream_t st)
     float best = 1e30f;
     ScreenShape pick{64, cus, 4, 16};
     const ScreenShape cands[] = {{32, cus * 2, 2, 16}, {64, cus * 2, 2, 16}, {32, cus, 4, 16}, {64, cus, 4, 16},
-                                 {32, cus * 2, 2, 32}, {64, cus * 2, 1, 32}, {32, cus * 2, 1, 32}};
+                                 {32, cus * 2, 2, 32}, {64, cus * 2, 1, 32}, {32, cus * 2, 1, 32},
+                                 {64, cus, 2, 32}};
     if (h->np > 256) {   // one form serves more than 256 dimensions
         h->screen = ScreenShape{32, cus * 2, 1, 32};
         (void)hipEventDestroy(e0);

@@ -373,7 +373,7 @@ __global__ __launch_bounds__(256, SUBS == 2 ? 2 : 1) void k_screen(ScreenArgs S)
 // l % 32. Bias step: query rows carry [hi(-a_q), lo(-a_q), 1, 1] and series rows
 // [1, 1, hi(-b_x), lo(-b_x)] in k-elements 0..3, zeros elsewhere.
 template <int KS16, int QT, int S>
-__global__ __launch_bounds__(256, 2) void k_screen32(ScreenArgs Sa)
+__global__ __launch_bounds__(256, (QT * S > 64) ? 1 : 2) void k_screen32(ScreenArgs Sa)
 {
     constexpr int XW = 32 * S;          // series per wave (kept in registers)
     constexpr int XB = 4 * XW;          // series per work item (block)
@@ -584,7 +584,8 @@ static hipError_t launch_screen32_ks(const ScreenArgs& s, ScreenShape shape, hip
             if (shape.qt == 64) k_screen32<KS16, 64, 1><<<grid, 256, 0, st>>>(s);
             else k_screen32<KS16, 32, 1><<<grid, 256, 0, st>>>(s);
         } else {
-            k_screen32<KS16, 32, 2><<<grid, 256, 0, st>>>(s);
+            if (shape.qt == 64) k_screen32<KS16, 64, 2><<<grid, 256, 0, st>>>(s);
+            else k_screen32<KS16, 32, 2><<<grid, 256, 0, st>>>(s);
         }
     }
     return hipGetLastError();
