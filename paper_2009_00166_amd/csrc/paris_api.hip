@@ -28,7 +28,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 // Workspace layout. The radix-sort scratch (alternate keys / positions / histograms) is only
 // needed during the build and aliases the survivor and completed-candidate buffers.
 struct Plan {
-    size_t hdr, sax, keys, perm, roff, qs, t8, t5, surv, done, total;
+    size_t hdr, sax, saxs, keys, perm, roff, qs, t8, t5, surv, done, total;
     size_t keys_alt, perm_alt, hist;
 };
 
@@ -38,6 +38,7 @@ void make_plan(long long N, Plan* p)
     auto take = [&off](size_t bytes) { const size_t at = off; off = align_up(off + bytes); return at; };
     p->hdr = take(256);
     p->sax = take((size_t)N * 16);
+    p->saxs = take((size_t)N * 16);
     p->keys = take((size_t)N * 8);
     p->perm = take((size_t)N * 4);
     p->roff = take(65537 * 4);
@@ -206,6 +207,7 @@ QueryArgs args_for(const paris_index* h)
     a.N = h->N;
     a.n = h->n;
     a.sax = ws + h->plan.sax;
+    a.saxs = ws + h->plan.saxs;
     a.keys = reinterpret_cast<const unsigned long long*>(ws + h->plan.keys);
     a.perm = reinterpret_cast<const uint32_t*>(ws + h->plan.perm);
     a.roff = reinterpret_cast<const uint32_t*>(ws + h->plan.roff);
@@ -711,8 +713,7 @@ paris_status tune_screen(paris_index* h, hipStream_t st)
     float best = 1e30f;
     ScreenShape pick{64, cus, 4, 16};
     const ScreenShape cands[] = {{32, cus * 2, 2, 16}, {64, cus * 2, 2, 16}, {32, cus, 4, 16}, {64, cus, 4, 16},
-                                 {32, cus * 2, 2, 32}, {64, cus * 2, 1, 32}, {32, cus * 2, 1, 32},
-                                 {64, cus, 2, 32}};
+                                 {32, cus * 2, 2, 32}, {64, cus * 2, 1, 32}, {32, cus * 2, 1, 32}};
     if (h->np > 256) {   // one form serves more than 256 dimensions
         h->screen = ScreenShape{32, cus * 2, 1, 32};
         (void)hipEventDestroy(e0);
@@ -916,6 +917,7 @@ paris_status paris_build(const float* series_dev, int64_t n_series, int32_t leng
                              reinterpret_cast<uint32_t*>(ws + plan.perm_alt),
                              reinterpret_cast<uint32_t*>(ws + plan.hist), n_series, st));
     HIP_TRY(launch_root_offsets(keys, n_series, reinterpret_cast<uint32_t*>(ws + plan.roff), st));
+    HIP_TRY(launch_gather_sax(ws + plan.sax, perm, n_series, ws + plan.saxs, st));
     uint32_t herr = 0;
     HIP_TRY(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));

@@ -276,6 +276,24 @@ __global__ __launch_bounds__(256) void k_root_offsets(const unsigned long long* 
     roff[r] = (uint32_t)lo;
 }
 
+// iSAX words in leaf order (saxs[p] = sax[perm[p]]): the approximate search reads a window of
+// consecutive sorted positions, which this copy turns into contiguous reads.
+__global__ __launch_bounds__(256) void k_gather_sax(const uint4* __restrict__ sax, const uint32_t* __restrict__ perm,
+                                                    long long N, uint4* __restrict__ saxs)
+{
+    for (long long p = (long long)blockIdx.x * 256 + threadIdx.x; p < N; p += (long long)gridDim.x * 256)
+        saxs[p] = sax[perm[p]];
+}
+
+hipError_t launch_gather_sax(const uint8_t* sax, const uint32_t* perm, long long N, uint8_t* saxs, hipStream_t st)
+{
+    long long blocks = (N + 255) / 256;
+    if (blocks > 8192) blocks = 8192;
+    k_gather_sax<<<(unsigned)blocks, 256, 0, st>>>(reinterpret_cast<const uint4*>(sax), perm, N,
+                                                   reinterpret_cast<uint4*>(saxs));
+    return hipGetLastError();
+}
+
 hipError_t launch_root_offsets(const unsigned long long* keys, long long N, uint32_t* roff, hipStream_t st)
 {
     k_root_offsets<<<(65537 + 255) / 256, 256, 0, st>>>(keys, N, roff);

@@ -76,6 +76,7 @@ hipError_t launch_sort_keys(unsigned long long* keys, uint32_t* perm, unsigned l
                             uint32_t* perm_alt, uint32_t* hist, long long N, hipStream_t st);
 hipError_t launch_root_offsets(const unsigned long long* keys, long long N, uint32_t* roff,
                                hipStream_t st);
+hipError_t launch_gather_sax(const uint8_t* sax, const uint32_t* perm, long long N, uint8_t* saxs, hipStream_t st);
 
 // ---- query kernels ----
 struct QueryArgs {
@@ -83,6 +84,7 @@ struct QueryArgs {
     long long N;
     int n;
     const uint8_t* sax;
+    const uint8_t* saxs;          // the same words in leaf order (saxs[p] = sax[perm[p]])
     const unsigned long long* keys;
     const uint32_t* perm;
     const uint32_t* roff;

@@ -358,7 +358,7 @@ __global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* 
     unsigned long long best = ~0ull;  // (lb bits, row)
     for (long long p = c0 + tid; p < c1; p += 256) {
         const uint32_t row = A.perm[p];
-        const uint4 w = reinterpret_cast<const uint4*>(A.sax)[row];
+        const uint4 w = reinterpret_cast<const uint4*>(A.saxs)[p];   // leaf-order copy: contiguous
         const float lb = fine_lb(w, t8);
         const unsigned long long k = pack_key(lb, row);
         best = k < best ? k : best;

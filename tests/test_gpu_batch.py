@@ -227,3 +227,25 @@ def test_query_batch_multi_mixed_lengths(oracle_native):
     assert st["lb_survivors"] > 0
     for ix in idxs:
         ix.close()
+
+
+SCREEN_SHAPES = ["32,2,16", "64,2,16", "32,4,16", "64,4,16", "32,2,32", "64,1,32", "32,1,32", "64,2,32"]
+
+
+def test_every_screen_shape_gives_exact_answers(oracle_native, monkeypatch):
+    """Every launch shape the screen tuner may choose (both MFMA forms) answers exactly."""
+    _need_gpu()
+    import paper_2009_00166_amd as paris
+    X = synth.random_walks(30_000, 256, seed=17)
+    Q, _, _ = synth.noisy_queries(X, 150, seed=18, sigma=(0.01, 0.5))
+    ri, rd, _ = oracle_native.nn_many(Q, X, threads=16)
+    Xd, Qd = torch.from_numpy(X).cuda(), torch.from_numpy(Q).cuda()
+    idx = paris.build(Xd)
+    for shape in SCREEN_SHAPES:
+        monkeypatch.setenv("PARIS_SCREEN_SHAPE", shape)
+        idx.attach_batch(max_batch=128)      # a full chunk (graph) and a partial one
+        I, D = idx.query_batch(Qd)
+        torch.cuda.synchronize()
+        assert np.array_equal(I.cpu().numpy(), ri), shape
+        assert np.array_equal(D.cpu().numpy(), np.sqrt(rd)), shape
+    idx.close()
