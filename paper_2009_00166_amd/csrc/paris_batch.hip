@@ -18,6 +18,8 @@
 // bfloat16 values (hi rounded down, the exact float32 remainder rounded up: bias_pair), so
 // every accumulator ends as dot - a_q - b_x or more, within about 2^-16 relative of it, and a
 // series survives iff its accumulator is >= 0.
+#include <type_traits>
+
 #include "paris_internal.h"
 
 namespace paris {
@@ -373,17 +375,25 @@ __global__ __launch_bounds__(256, SUBS == 2 ? 2 : 1) void k_screen(ScreenArgs S)
 // l % 32. Bias step: query rows carry [hi(-a_q), lo(-a_q), 1, 1] and series rows
 // [1, 1, hi(-b_x), lo(-b_x)] in k-elements 0..3, zeros elsewhere.
 template <int KS16, int QT, int S>
-__global__ __launch_bounds__(256, (QT * S > 64) ? 1 : 2) void k_screen32(ScreenArgs Sa)
+__global__ __launch_bounds__(256, 2) void k_screen32(ScreenArgs Sa)
 {
     constexpr int XW = 32 * S;          // series per wave (kept in registers)
     constexpr int XB = 4 * XW;          // series per work item (block)
     constexpr int NP = KS16 * 16;
     constexpr int KT = KS16 + 1;        // k-steps including the bias step
-    constexpr int RS = KT * 16 + 8;     // LDS row stride (bfloat16): an odd multiple of 16 bytes
     constexpr int QS = QT / 32;         // query subtiles per tile
-    constexpr int V8 = NP / 8;          // 16-byte vectors per data row
-    constexpr int STAGE = (QT * V8 + 255) / 256;
-    __shared__ __attribute__((aligned(16))) uint16_t qtile[2][QT * RS];
+    constexpr int CH = NP / 8;          // 16-byte chunks per query row
+    constexpr int SWM = CH >= 8 ? 7 : CH - 1;   // chunk swizzle mask (rows of a bank group)
+    constexpr int TCH = QT * CH;        // chunks per query tile
+    constexpr int LOADS = (TCH + 255) / 256;    // direct-to-LDS loads per lane per tile
+    // Query tiles go from global memory straight into LDS (global_load_lds_dwordx4: no staging
+    // registers, so nothing holds the MFMAs back while the next tile is in flight). A row's
+    // 16-byte chunk c sits at chunk c ^ (row & SWM) of the row, so the 8 rows that one LDS cycle
+    // serves hit 8 distinct bank groups. The bias columns live in their own small array.
+    __shared__ __attribute__((aligned(16))) uint16_t qd0[QT * NP];
+    __shared__ __attribute__((aligned(16))) uint16_t qd1[QT * NP];
+    __shared__ __attribute__((aligned(16))) uint16_t qb0[QT * 16];
+    __shared__ __attribute__((aligned(16))) uint16_t qb1[QT * 16];
     __shared__ long long s_item;
     __shared__ uint2 cbuf[kCandStage];
     __shared__ uint32_t ccount, cbase;
@@ -409,41 +419,47 @@ __global__ __launch_bounds__(256, (QT * S > 64) ? 1 : 2) void k_screen32(ScreenA
     const long long n_items = (N + XB - 1) / XB;
     const bool dump = Sa.dump != nullptr;
 
-    // bias block of every row (16 bfloat16 after the data): [hi, lo, 1, 1, 0 ...], the first
-    // 4 rewritten with each tile, the rest stays zero
-    for (int e = tid; e < 2 * QT * 2; e += 256) {
-        const int buf = e / (QT * 2), rem = e - buf * QT * 2, row = rem >> 1, ch = rem & 1;
-        *reinterpret_cast<uint4*>(&qtile[buf][row * RS + NP + ch * 8]) = make_uint4(0, 0, 0, 0);
+    // bias rows: [hi, lo, 1, 1, 0 ...]; the last 12 stay zero
+    for (int e = tid; e < QT * 2; e += 256) {
+        *reinterpret_cast<uint4*>(&qb0[e * 8]) = make_uint4(0, 0, 0, 0);
+        *reinterpret_cast<uint4*>(&qb1[e * 8]) = make_uint4(0, 0, 0, 0);
     }
 
-    auto stage_load = [&](int t, uint4* pre, uint2& bias) {
+    // tile t's data into qdata[buf] (asynchronous: complete after the next full wait) and its
+    // raw bias constants into registers; rows past the batch read row 0 (their bias never passes)
+    // The two tile buffers are distinct arrays addressed with a compile-time index (the tile loop
+    // is unrolled by two), so the compiler can see that the next tile's direct loads never write
+    // the buffer being read and need not wait for them before the LDS reads.
+    auto tile_load = [&](int t, auto BUF, uint2& bias) {
+        uint16_t* dst = decltype(BUF)::value == 0 ? qd0 : qd1;
 #pragma unroll
-        for (int s = 0; s < STAGE; ++s) {
-            const int e = tid + s * 256;
-            const int row = e / V8, v = e - row * V8;
-            const int q = t * QT + row;
-            pre[s] = (e < QT * V8 && q < M)
-                         ? *reinterpret_cast<const uint4*>(Sa.Qb + (long long)q * NP + v * 8)
-                         : make_uint4(0, 0, 0, 0);
+        for (int j = 0; j < LOADS; ++j) {
+            const int pos = (j * 4 + w) * 64 + l;             // chunk position in the tile
+            if (pos < TCH) {
+                const int row = pos / CH, pc = pos - row * CH;
+                const int c = pc ^ (row & SWM);
+                const int q = t * QT + row;
+                const uint16_t* src = Sa.Qb + (long long)(q < M ? q : 0) * NP + c * 8;
+                __builtin_amdgcn_global_load_lds(
+                    (__attribute__((address_space(1))) const void*)src,
+                    (__attribute__((address_space(3))) void*)(dst + (j * 4 + w) * 64 * 8), 16, 0, 0);
+            }
         }
         if (tid < QT) {
             const int q = t * QT + tid;
-            const float a = (q < M && !dump) ? Sa.bq[q].a : (dump ? 0.f : __builtin_inff());
-            const float t1 = a < __builtin_inff() ? -a : kNoPass;
-            bias = bias_pair(t1);  // [hi(-a_q), lo(-a_q), 1.0, 1.0]
-            bias.y = 0x3F803F80u;
+            bias.x = __float_as_uint(Sa.bq[q < M ? q : 0].a);
+            bias.y = dump ? 2u : (q < M ? 1u : 0u);
         }
     };
-    auto stage_store = [&](int buf, const uint4* pre, uint2 bias) {
-#pragma unroll
-        for (int s = 0; s < STAGE; ++s) {
-            const int e = tid + s * 256;
-            if (e < QT * V8) {
-                const int row = e / V8, v = e - row * V8;
-                *reinterpret_cast<uint4*>(&qtile[buf][row * RS + v * 8]) = pre[s];
-            }
+    auto bias_store = [&](auto BUF, uint2 bias) {
+        uint16_t* dst = decltype(BUF)::value == 0 ? qb0 : qb1;
+        if (tid < QT) {
+            const float a = bias.y == 1u ? __uint_as_float(bias.x) : (bias.y == 2u ? 0.f : __builtin_inff());
+            const float t1 = a < __builtin_inff() ? -a : kNoPass;
+            uint2 bp = bias_pair(t1);  // [hi(-a_q), lo(-a_q), 1.0, 1.0]
+            bp.y = 0x3F803F80u;
+            *reinterpret_cast<uint2*>(&dst[tid * 16]) = bp;
         }
-        if (tid < QT) *reinterpret_cast<uint2*>(&qtile[buf][tid * RS + NP]) = bias;
     };
 
     for (;;) {
@@ -475,19 +491,19 @@ __global__ __launch_bounds__(256, (QT * S > 64) ? 1 : 2) void k_screen32(ScreenA
         }
 
         {
-            uint4 pre[STAGE];
             uint2 bias = make_uint2(0u, 0u);
-            stage_load(0, pre, bias);
-            stage_store(0, pre, bias);
+            tile_load(0, std::integral_constant<int, 0>{}, bias);
+            bias_store(std::integral_constant<int, 0>{}, bias);
+            __builtin_amdgcn_s_waitcnt(0);
         }
         __syncthreads();
 
-        for (int t = 0; t < n_qt; ++t) {
-            const int buf = t & 1;
-            uint4 pre[STAGE];
+        auto tile = [&](int t, auto CUR) {
+            constexpr int B = decltype(CUR)::value;
+            const std::integral_constant<int, 1 - B> NEXT{};
             uint2 bias = make_uint2(0u, 0u);
             const bool more = t + 1 < n_qt;
-            if (more) stage_load(t + 1, pre, bias);  // in flight during the MFMAs
+            if (more) tile_load(t + 1, NEXT, bias);  // lands in LDS during the MFMAs
 
             f32x16 acc[QS][S];
 #pragma unroll
@@ -496,16 +512,22 @@ __global__ __launch_bounds__(256, (QT * S > 64) ? 1 : 2) void k_screen32(ScreenA
                 for (int sub = 0; sub < S; ++sub)
 #pragma unroll
                     for (int i = 0; i < 16; ++i) acc[qs][sub][i] = 0.f;
-            const uint16_t* tb = qtile[buf] + col * RS + kh * 8;
+            const uint16_t* tb = B == 0 ? qd0 : qd1;
+            const uint16_t* tbb = (B == 0 ? qb0 : qb1) + col * 16 + kh * 8;
+            auto a_frag = [&](int qs, int ks) -> bf16x8 {
+                const int row = qs * 32 + col;
+                if (ks == KS16) return *reinterpret_cast<const bf16x8*>(tbb + qs * 32 * 16);
+                const int c = (2 * ks + kh) ^ (row & SWM);
+                return *reinterpret_cast<const bf16x8*>(tb + row * NP + c * 8);
+            };
             bf16x8 a[QS], an[QS];
 #pragma unroll
-            for (int qs = 0; qs < QS; ++qs) a[qs] = *reinterpret_cast<const bf16x8*>(tb + qs * 32 * RS);
+            for (int qs = 0; qs < QS; ++qs) a[qs] = a_frag(qs, 0);
 #pragma unroll
             for (int ks = 0; ks < KT; ++ks) {
                 if (ks + 1 < KT) {
 #pragma unroll
-                    for (int qs = 0; qs < QS; ++qs)
-                        an[qs] = *reinterpret_cast<const bf16x8*>(tb + qs * 32 * RS + (ks + 1) * 16);
+                    for (int qs = 0; qs < QS; ++qs) an[qs] = a_frag(qs, ks + 1);
                 }
 #pragma unroll
                 for (int qs = 0; qs < QS; ++qs)
@@ -562,9 +584,14 @@ __global__ __launch_bounds__(256, (QT * S > 64) ? 1 : 2) void k_screen32(ScreenA
                             }
                 }
             }
-            if (more) stage_store(buf ^ 1, pre, bias);
+            if (more) bias_store(NEXT, bias);
+            __builtin_amdgcn_s_waitcnt(0);   // this wave's direct-to-LDS loads have landed
             __syncthreads();
             if (ccount >= (uint32_t)(kCandStage / 2)) flush_cands();  // uniform: read after the barrier
+        };
+        for (int t = 0; t < n_qt; t += 2) {
+            tile(t, std::integral_constant<int, 0>{});
+            if (t + 1 < n_qt) tile(t + 1, std::integral_constant<int, 1>{});
         }
     }
     __syncthreads();
