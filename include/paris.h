@@ -145,10 +145,13 @@ paris_status paris_query_exact(paris_index *idx, const float *query_dev, int64_t
  *   queries_dev   float32 [n_queries][length] on the device, finite.
  *   nn_index_dev  int64 [n_queries] device out;  nn_dist_dev  float64 [n_queries] device out.
  *   stats         optional host out, summed over the batch (may be NULL).
- * With a batch workspace attached (paris_batch_attach) and length <= 256, the queries go in
- * chunks of max_batch through the batched pipeline (one HIP graph per chunk): per-query seeds,
- * the bfloat16 MFMA distance screen with a certified margin over every (query, series) pair,
- * float32 re-scoring of its survivors and the float64 resolve; each chunk is synchronised
+ * With a batch workspace attached (paris_batch_attach), the queries go in chunks of max_batch
+ * through the batched pipeline (one HIP graph per chunk): per-query seeds; a block bound that
+ * drops every (query, run of 128 or 256 consecutive series in leaf order) pair whose iSAX
+ * lower bound (Section 3.3.1) over the run's symbol envelope exceeds the query's seed distance;
+ * the bfloat16 MFMA distance screen with a certified margin over the remaining pairs (series
+ * longer than 512 points are screened on segment means); float32 re-scoring of its survivors
+ * and the float64 resolve; each chunk is synchronised
  * once, and a query whose candidate or resolve buffers overflow is answered by the per-query
  * path. Without one, the queries run one after another through the per-query kernels and the
  * call is asynchronous unless stats is requested. A NaN/Inf query yields index -1 and distance
@@ -176,12 +179,16 @@ paris_status paris_query_batch_multi(paris_index *const *idx, int32_t n_idx, con
 /*
  * Batched pipeline resources (the batched pattern of the paper's worker pools: many queries,
  * one launch). paris_batch_workspace_size gives the bytes for chunks of up to max_batch queries
- * (1 .. 65536): a bfloat16 copy of the collection [N][roundup(length, 32)], its norms, the
- * query buffers, per-query states, a candidate list of min(4096 * max_batch, 2^32 - 16) entries
- * (12 bytes each: query, series, float32 re-scored distance) and per-query learned-seed leaves.
+ * (1 .. 65536): a bfloat16 copy of the collection in leaf order [N][np] (np = the screened
+ * dimensions rounded up to 32), its norms, the query buffers, per-query states, a candidate
+ * list of min(4096 * max_batch, 2^32 - 16) entries (12 bytes each: query, series, float32
+ * re-scored distance), per-query learned-seed leaves and PAA, the symbol envelope of every
+ * run of 32 sorted positions (32 bytes) and the block bound's alive bits
+ * (ceil(N / 128) * ceil(max_batch / 64) words of 8 bytes).
  * paris_batch_attach borrows that device memory (256-byte aligned) for the life of the handle
- * (or until the next attach), converts the collection, times the screen's tile shapes and
- * captures the pipeline into a HIP graph. Synchronous on hip_stream.
+ * (or until the next attach), converts the collection, times the screen's tile shapes (on a
+ * screen of every pair) and captures the pipeline into a HIP graph. Synchronous on hip_stream.
+ * The environment variable PARIS_BLOCK_LB=0, read at attach, turns the block bound off.
  */
 paris_status paris_batch_workspace_size(const paris_index *idx, int32_t max_batch, size_t *bytes);
 paris_status paris_batch_attach(paris_index *idx, void *workspace_dev, size_t workspace_bytes,
@@ -194,6 +201,15 @@ paris_status paris_batch_attach(paris_index *idx, void *workspace_dev, size_t wo
  */
 paris_status paris_screen_dots(paris_index *idx, const float *queries_dev, int32_t n_queries,
                                float *dots_dev, void *hip_stream);
+
+/*
+ * Screen work counters of the batched pipeline since the last attach or reset (host outs):
+ * tiles_run = query tiles the MFMA screen ran, tiles_dense = tiles a screen of every pair
+ * would have run for the same chunks (their ratio is the share of pairs the block bound kept,
+ * rounded up to whole tiles). reset != 0 zeroes both after reading. Errors: PARIS_ESTATE
+ * (bad handle), PARIS_EINVAL (NULL out).
+ */
+paris_status paris_batch_screen_tiles(paris_index *idx, int64_t *tiles_run, int64_t *tiles_dense, int32_t reset);
 
 /*
  * Query summaries as the device computes them (Section 2.2 on the query; Section 3.3.1 table):
@@ -235,11 +251,11 @@ paris_status paris_get_timing(paris_index *idx, double *ms_out3, int64_t *n_quer
 
 /*
  * With timing on, paris_query_batch launches its pipeline directly (not through the captured
- * graph) with HIP events between the stages; ms_out4 receives the summed milliseconds of
- * [0] reset + seeds + screen thresholds, [1] bfloat16 MFMA screen, [2] float32 re-score,
- * [3] float64 resolve, and n_chunks the number of timed chunks.
+ * graph) with HIP events between the stages; ms_out5 receives the summed milliseconds of
+ * [0] reset + seeds + screen thresholds, [1] block bound (alive bits), [2] bfloat16 MFMA
+ * screen, [3] float32 re-score, [4] float64 resolve, and n_chunks the number of timed chunks.
  */
-paris_status paris_get_batch_timing(const paris_index *idx, double *ms_out4, int64_t *n_chunks);
+paris_status paris_get_batch_timing(const paris_index *idx, double *ms_out5, int64_t *n_chunks);
 
 /* Release the handle (the borrowed buffers are not touched). NULL is accepted. */
 paris_status paris_free(paris_index *idx);

@@ -137,6 +137,27 @@ def lower_bound_sq(qpaa: np.ndarray, sym: np.ndarray, L: int, bits: int = 8) -> 
     return np.float64(L) * acc
 
 
+def block_lower_bound_sq(qpaa: np.ndarray, sym_run: np.ndarray, L: int, bits: int = 8) -> np.float64:
+    """Squared lower bound of a query against a whole run of iSAX words (build decision of the
+    batched screen, lifted from the Section 3.3.1 bound).
+
+    In segment s every word of the run lies in a region between the lower edge of the run's
+    smallest symbol and the upper edge of its largest; ``delta_s`` is the distance from the
+    query's segment mean to that interval (the same three branches), and the bound is
+    ``L * sum_s delta_s^2`` (ascending s, float64). The interval contains each member's own
+    region, so this is at most ``lower_bound_sq`` of every member.
+    """
+    b = breakpoints_at_cardinality(bits)
+    sym_run = np.asarray(sym_run).astype(np.int64).reshape(-1, W)
+    lo = b[sym_run.min(axis=0)]
+    hi = b[sym_run.max(axis=0) + 1]
+    d = _delta(np.asarray(qpaa, dtype=np.float64), lo, hi)
+    acc = np.float64(0.0)
+    for s in range(W):
+        acc = acc + d[s] * d[s]
+    return np.float64(L) * acc
+
+
 def lb_table(qpaa: np.ndarray, L: int, bits: int = 8) -> np.ndarray:
     """float64[w][2^bits]: the per-segment lower-bound term ``L * delta(q_s, c)^2`` for every
     symbol c, i.e. the summand of ``lower_bound_sq`` tabulated over the alphabet."""

@@ -211,6 +211,15 @@ class Index:
                                                _stream_ptr(stream)), "paris_screen_dots")
         return out
 
+    def screen_tiles(self, reset: bool = False):
+        """(query tiles the batched screen ran, tiles a screen of every pair would have run)
+        since the attach or the last reset."""
+        run = ctypes.c_int64(0)
+        dense = ctypes.c_int64(0)
+        check(load_library().paris_batch_screen_tiles(self._h, ctypes.byref(run), ctypes.byref(dense),
+                                                      1 if reset else 0), "paris_batch_screen_tiles")
+        return int(run.value), int(dense.value)
+
     def set_timing(self, enable: bool = True, scan_only: bool = False) -> None:
         """Enable HIP-event timing of query() (all three phases, or the scan only) and zero
         the totals."""
@@ -225,8 +234,8 @@ class Index:
         return list(ms), int(n.value)
 
     def batch_timing(self):
-        """(summed ms per batch stage [seeds, screen, rescore, resolve], timed chunks)."""
-        ms = (ctypes.c_double * 4)()
+        """(summed ms per batch stage [seeds, block bound, screen, rescore, resolve], timed chunks)."""
+        ms = (ctypes.c_double * 5)()
         n = ctypes.c_int64(0)
         check(load_library().paris_get_batch_timing(self._h, ms, ctypes.byref(n)), "paris_get_batch_timing")
         return list(ms), int(n.value)

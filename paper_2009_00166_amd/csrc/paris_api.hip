@@ -178,7 +178,7 @@ struct paris_index {
     int proj;   // segment length of the screen's projection (1: n <= 256, the series itself)
     bool screen_ok;
     struct {
-        size_t hdr, xb, xn, qin, qb, bq, cand, cand_d2, oidx, odist, fb, leaves, total;
+        size_t hdr, xb, xn, qin, qb, bq, cand, cand_d2, oidx, odist, fb, leaves, env, qpaa, mask, total;
         uint32_t cand_cap;
     } bp;
     ScreenShape screen;
@@ -189,8 +189,10 @@ struct paris_index {
     BatchHdr* host_hdr;   // pinned read-back of the batch header
     uint32_t* host_fb;    // pinned read-back of the fallback list
     long long batch_candidates;
-    hipEvent_t bev[5];    // batch stage events (timing on): seeds | screen | re-score | resolve
-    double batch_ms[4];
+    bool block_lb;        // screen only the (query, work item) pairs that the block bound keeps
+    long long tiles_run, tiles_dense;   // screen query tiles run / a dense screen's count
+    hipEvent_t bev[6];    // batch stage events (timing on): seeds | block bound | screen | re-score | resolve
+    double batch_ms[5];
     long long timed_chunks;
     // learned seed (paris_set_seed_model): the network is borrowed, not owned
     paris_mlp* model;
@@ -440,6 +442,10 @@ void make_batch_plan(paris_index* h, int max_batch)
     h->bp.odist = take(M * 8);
     h->bp.fb = take(M * 4);
     h->bp.leaves = take(M * kTopLeaves * 4);
+    h->bp.env = take((N + kEnvRun - 1) / kEnvRun * 32);
+    h->bp.qpaa = take(M * kSeg * 8);
+    // alive bits for the smallest work item of the 32-wide screen (128 sorted positions)
+    h->bp.mask = take((N + 127) / 128 * ((M + 63) / 64) * 8);
     h->bp.total = off;
 }
 
@@ -451,7 +457,7 @@ bool batch_screen_usable(const paris_index* h)
 BatchHdr* bhdr(paris_index* h) { return reinterpret_cast<BatchHdr*>(h->bws + h->bp.hdr); }
 BQuery* bqs(paris_index* h) { return reinterpret_cast<BQuery*>(h->bws + h->bp.bq); }
 
-ScreenArgs screen_args(paris_index* h, int m, float* dump)
+ScreenArgs screen_args(paris_index* h, int m, float* dump, bool masked = true)
 {
     ScreenArgs s;
     s.Xb = reinterpret_cast<const uint16_t*>(h->bws + h->bp.xb);
@@ -465,6 +471,13 @@ ScreenArgs screen_args(paris_index* h, int m, float* dump)
     s.hdr = bhdr(h);
     s.c_screen = h->c_screen;
     s.dump = dump;
+    s.perm = reinterpret_cast<const uint32_t*>(h->ws + h->plan.perm);
+    s.mask = masked && h->block_lb ? reinterpret_cast<unsigned long long*>(h->bws + h->bp.mask) : nullptr;
+    s.env = h->bws + h->bp.env;
+    s.qpaa = reinterpret_cast<const double*>(h->bws + h->bp.qpaa);
+    s.seg_len = (double)(h->n / kSeg);
+    s.seed_rel = h->seed_rel;
+    s.prune_rel = h->mg.prune_rel;
     return s;
 }
 
@@ -599,6 +612,7 @@ paris_status launch_batch_pipeline(paris_index* h, int m, hipStream_t st, bool t
     sb.np = h->np;
     sb.P = h->proj;
     sb.leaves = nullptr;
+    sb.qpaa = reinterpret_cast<double*>(h->bws + h->bp.qpaa);
     if (timed) HIP_TRY(hipEventRecord(h->bev[0], st));
     HIP_TRY(launch_batch_init(bqs(h), m, bhdr(h), st));
     QueryArgs al = a;
@@ -612,14 +626,17 @@ paris_status launch_batch_pipeline(paris_index* h, int m, hipStream_t st, bool t
     HIP_TRY(launch_prepare_seed_batch(al, sb, m, st));
     HIP_TRY(launch_batch_thresholds(bqs(h), m, h->c_screen, h->seed_rel, h->proj, st));
     if (timed) HIP_TRY(hipEventRecord(h->bev[1], st));
-    HIP_TRY(launch_screen(screen_args(h, m, nullptr), h->np, h->screen, st));
+    const ScreenArgs sa = screen_args(h, m, nullptr);
+    HIP_TRY(launch_block_mask(sa, h->screen, st));
     if (timed) HIP_TRY(hipEventRecord(h->bev[2], st));
+    HIP_TRY(launch_screen(sa, h->np, h->screen, st));
+    if (timed) HIP_TRY(hipEventRecord(h->bev[3], st));
     const RescoreArgs r = rescore_args(h, m);
     HIP_TRY(launch_rescore(r, st));
-    if (timed) HIP_TRY(hipEventRecord(h->bev[3], st));
+    if (timed) HIP_TRY(hipEventRecord(h->bev[4], st));
     HIP_TRY(launch_batch_resolve(r, reinterpret_cast<long long*>(h->bws + h->bp.oidx),
                                  reinterpret_cast<double*>(h->bws + h->bp.odist), st));
-    if (timed) HIP_TRY(hipEventRecord(h->bev[4], st));
+    if (timed) HIP_TRY(hipEventRecord(h->bev[5], st));
     return PARIS_OK;
 }
 
@@ -660,7 +677,7 @@ paris_status run_batch_chunk(paris_index* h, const float* queries, long long q0,
     HIP_TRY(hipMemcpyAsync(h->host_hdr, bhdr(h), sizeof(BatchHdr), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     if (timed) {
-        for (int k = 0; k < 4; ++k) {
+        for (int k = 0; k < 5; ++k) {
             float ms = 0.f;
             HIP_TRY(hipEventElapsedTime(&ms, h->bev[k], h->bev[k + 1]));
             h->batch_ms[k] += ms;
@@ -669,6 +686,11 @@ paris_status run_batch_chunk(paris_index* h, const float* queries, long long q0,
     }
     const BatchHdr hd = *h->host_hdr;
     *cands += hd.n_cand;
+    {
+        const long long xb = screen_item_series(h->screen);
+        h->tiles_run += hd.n_tiles;
+        h->tiles_dense += (h->N + xb - 1) / xb * ((m + h->screen.qt - 1) / h->screen.qt);
+    }
     if (hd.n_fallback) {
         // queries whose screen candidates or resolve band overflowed: the per-query path
         HIP_TRY(hipMemcpyAsync(h->host_fb, h->bws + h->bp.fb, (size_t)hd.n_fallback * 4, hipMemcpyDeviceToHost, st));
@@ -684,8 +706,10 @@ paris_status run_batch_chunk(paris_index* h, const float* queries, long long q0,
 }
 
 // Screen autotuner: MFMA form (16x16x32 or 32x32x16) x query-tile height (32 or 64 rows) x
-// series per wave, every threshold at +inf (no candidate), timed over full-size batches; the
-// median of three runs decides. PARIS_SCREEN_SHAPE="qt,subs[,mfma]" overrides.
+// series per wave, every threshold at +inf (no candidate) and every pair screened (no block
+// bound: before the first batch there are no thresholds to bound against), timed over
+// full-size batches; the median of three runs decides. PARIS_SCREEN_SHAPE="qt,subs[,mfma]"
+// overrides. More than 256 dimensions always take the 32-wide form with one subtile per wave.
 paris_status tune_screen(paris_index* h, hipStream_t st)
 {
     const char* env = std::getenv("PARIS_SCREEN_SHAPE");
@@ -693,6 +717,10 @@ paris_status tune_screen(paris_index* h, hipStream_t st)
     if (hipGetDevice(&dev) != hipSuccess ||
         hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
         cus = 256;
+    if (h->np > 256) {   // one form serves more than 256 dimensions
+        h->screen = ScreenShape{32, cus * 2, 1, 32};
+        return PARIS_OK;
+    }
     if (env) {
         int qt = 0, subs = 0, mf = 16;
         const int got = std::sscanf(env, "%d,%d,%d", &qt, &subs, &mf);
@@ -711,21 +739,16 @@ paris_status tune_screen(paris_index* h, hipStream_t st)
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
     float best = 1e30f;
-    ScreenShape pick{64, cus, 4, 16};
+    ScreenShape pick{32, cus * 2, 2, 32};
     const ScreenShape cands[] = {{32, cus * 2, 2, 16}, {64, cus * 2, 2, 16}, {32, cus, 4, 16}, {64, cus, 4, 16},
                                  {32, cus * 2, 2, 32}, {64, cus * 2, 1, 32}, {32, cus * 2, 1, 32}};
-    if (h->np > 256) {   // one form serves more than 256 dimensions
-        h->screen = ScreenShape{32, cus * 2, 1, 32};
-        (void)hipEventDestroy(e0);
-        (void)hipEventDestroy(e1);
-        return PARIS_OK;
-    }
     for (const ScreenShape& sh : cands) {
+        if (h->block_lb && sh.mfma != 32) continue;   // the block bound needs the 32-wide form
         float t[3];
         for (int r = 0; r < 4; ++r) {
             HIP_TRY(launch_batch_init(bqs(h), m, bhdr(h), st));  // thresholds +inf
             HIP_TRY(hipEventRecord(e0, st));
-            HIP_TRY(launch_screen(screen_args(h, m, nullptr), h->np, sh, st));
+            HIP_TRY(launch_screen(screen_args(h, m, nullptr, false), h->np, sh, st));
             HIP_TRY(hipEventRecord(e1, st));
             HIP_TRY(hipEventSynchronize(e1));
             float ms = 0.f;
@@ -835,8 +858,13 @@ paris_status paris_batch_attach(paris_index* h, void* workspace_dev, size_t work
     h->screen_ok = h->np <= 512;
     if (!h->screen_ok) return PARIS_OK;  // batches then use the per-query path
     paris_status s = PARIS_OK;
-    if (launch_to_bf16(h->X, h->N, h->n, h->np, h->proj, reinterpret_cast<uint16_t*>(h->bws + h->bp.xb),
-                       reinterpret_cast<float*>(h->bws + h->bp.xn), st) != hipSuccess)
+    const char* blb = std::getenv("PARIS_BLOCK_LB");
+    h->block_lb = !(blb && blb[0] == '0');
+    h->tiles_run = h->tiles_dense = 0;
+    if (launch_to_bf16(h->X, reinterpret_cast<const uint32_t*>(h->ws + h->plan.perm), h->N, h->n, h->np, h->proj,
+                       reinterpret_cast<uint16_t*>(h->bws + h->bp.xb), reinterpret_cast<float*>(h->bws + h->bp.xn),
+                       st) != hipSuccess ||
+        launch_block_env(h->ws + h->plan.saxs, h->N, h->bws + h->bp.env, st) != hipSuccess)
         s = PARIS_EHIP;
     if (s == PARIS_OK) s = tune_screen(h, st);
     if (s == PARIS_OK && hipStreamSynchronize(st) != hipSuccess) s = PARIS_EHIP;
@@ -863,11 +891,22 @@ paris_status paris_screen_dots(paris_index* h, const float* queries_dev, int32_t
     sb.np = h->np;
     sb.P = h->proj;
     sb.leaves = nullptr;
+    sb.qpaa = reinterpret_cast<double*>(h->bws + h->bp.qpaa);
     HIP_TRY(hipMemcpyAsync(h->bws + h->bp.qin, queries_dev, (size_t)m * h->n * 4, hipMemcpyDeviceToDevice, st));
     HIP_TRY(launch_batch_init(bqs(h), m, bhdr(h), st));
     HIP_TRY(launch_prepare_seed_batch(a, sb, m, st));  // bfloat16 queries and norms (thresholds stay +inf)
     HIP_TRY(launch_screen(screen_args(h, m, dots_dev), h->np, h->screen, st));
     HIP_TRY(hipStreamSynchronize(st));
+    return PARIS_OK;
+}
+
+paris_status paris_batch_screen_tiles(paris_index* h, int64_t* tiles_run, int64_t* tiles_dense, int32_t reset)
+{
+    if (!handle_ok(h)) return PARIS_ESTATE;
+    if (!tiles_run || !tiles_dense) return PARIS_EINVAL;
+    *tiles_run = h->tiles_run;
+    *tiles_dense = h->tiles_dense;
+    if (reset) h->tiles_run = h->tiles_dense = 0;
     return PARIS_OK;
 }
 
@@ -975,8 +1014,8 @@ paris_status paris_build(const float* series_dev, int64_t n_series, int32_t leng
     h->host_hdr = nullptr;
     h->host_fb = nullptr;
     h->batch_candidates = 0;
-    for (int k = 0; k < 5; ++k) h->bev[k] = nullptr;
-    for (int k = 0; k < 4; ++k) h->batch_ms[k] = 0.0;
+    for (int k = 0; k < 6; ++k) h->bev[k] = nullptr;
+    for (int k = 0; k < 5; ++k) h->batch_ms[k] = 0.0;
     h->timed_chunks = 0;
     h->model = nullptr;
     h->learned = false;
@@ -1186,7 +1225,7 @@ paris_status paris_set_timing(paris_index* h, int32_t enable)
     if (enable && !h->ev[0][0]) {
         for (int set = 0; set < 2; ++set)
             for (int k = 0; k < 4; ++k) HIP_TRY(hipEventCreate(&h->ev[set][k]));
-        for (int k = 0; k < 5; ++k) HIP_TRY(hipEventCreate(&h->bev[k]));
+        for (int k = 0; k < 6; ++k) HIP_TRY(hipEventCreate(&h->bev[k]));
     }
     h->timing = enable != 0;
     h->timing_mode = enable;
@@ -1194,16 +1233,16 @@ paris_status paris_set_timing(paris_index* h, int32_t enable)
     h->ev_set = 0;
     for (int k = 0; k < 3; ++k) h->phase_ms[k] = 0.0;
     h->timed_queries = 0;
-    for (int k = 0; k < 4; ++k) h->batch_ms[k] = 0.0;
+    for (int k = 0; k < 5; ++k) h->batch_ms[k] = 0.0;
     h->timed_chunks = 0;
     return PARIS_OK;
 }
 
-paris_status paris_get_batch_timing(const paris_index* h, double* ms_out4, int64_t* n_chunks)
+paris_status paris_get_batch_timing(const paris_index* h, double* ms_out5, int64_t* n_chunks)
 {
     if (!handle_ok(h)) return PARIS_ESTATE;
-    if (!ms_out4 || !n_chunks) return PARIS_EINVAL;
-    for (int k = 0; k < 4; ++k) ms_out4[k] = h->batch_ms[k];
+    if (!ms_out5 || !n_chunks) return PARIS_EINVAL;
+    for (int k = 0; k < 5; ++k) ms_out5[k] = h->batch_ms[k];
     *n_chunks = h->timed_chunks;
     return PARIS_OK;
 }
@@ -1235,7 +1274,7 @@ paris_status paris_free(paris_index* h)
     for (int set = 0; set < 2; ++set)
         for (int k = 0; k < 4; ++k)
             if (h->ev[set][k]) (void)hipEventDestroy(h->ev[set][k]);
-    for (int k = 0; k < 5; ++k)
+    for (int k = 0; k < 6; ++k)
         if (h->bev[k]) (void)hipEventDestroy(h->bev[k]);
     delete h;
     return PARIS_OK;

@@ -24,6 +24,12 @@
 
 namespace paris {
 
+// Gaussian region boundaries beta_1..beta_255 (index 0 unused): the k/256 quantiles of N(0,1).
+static __constant__ double c_beta[256] = {
+    0.0,
+#include "breakpoints.inc"
+};
+
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -88,7 +94,10 @@ __device__ __forceinline__ float seg_mean(const float* __restrict__ x, int j, in
     return (float)(acc / (double)P);
 }
 
-__global__ __launch_bounds__(256) void k_to_bf16(const float* __restrict__ X, long long N, int n, int np, int P,
+// Row p of the copy is series perm[p] (leaf order), so that a run of consecutive rows shares
+// long iSAX prefixes and the block bound of the screen (k_block_mask) stays tight.
+__global__ __launch_bounds__(256) void k_to_bf16(const float* __restrict__ X, const uint32_t* __restrict__ perm,
+                                                 long long N, int n, int np, int P,
                                                  uint16_t* __restrict__ Xb, float* __restrict__ xn)
 {
     const int lane = threadIdx.x & 63;
@@ -96,7 +105,7 @@ __global__ __launch_bounds__(256) void k_to_bf16(const float* __restrict__ X, lo
     const long long nw = (long long)gridDim.x * 4;
     const int nd = n / P;
     for (long long i = wave; i < N; i += nw) {
-        const float* row = X + i * n;
+        const float* row = X + (long long)perm[i] * n;
         uint16_t* out = Xb + i * np;
         float sq = 0.f;
         for (int j = lane; j < np; j += 64) {
@@ -109,12 +118,139 @@ __global__ __launch_bounds__(256) void k_to_bf16(const float* __restrict__ X, lo
     }
 }
 
-hipError_t launch_to_bf16(const float* X, long long N, int n, int np, int P, uint16_t* Xb, float* xn, hipStream_t st)
+hipError_t launch_to_bf16(const float* X, const uint32_t* perm, long long N, int n, int np, int P, uint16_t* Xb,
+                          float* xn, hipStream_t st)
 {
     long long blocks = (N + 3) / 4;
     if (blocks > 65536) blocks = 65536;
-    k_to_bf16<<<(unsigned)blocks, 256, 0, st>>>(X, N, n, np, P, Xb, xn);
+    k_to_bf16<<<(unsigned)blocks, 256, 0, st>>>(X, perm, N, n, np, P, Xb, xn);
     return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
+// Block bound of the screen.
+// Every series of a run of consecutive sorted positions has, in each segment, a symbol between
+// the run's smallest and largest symbol of that segment, so its PAA value lies in the union of
+// those regions. The distance from the query's PAA value to that union is at most the distance
+// to the series' own region, and the iSAX lower bound (Section 3.3.1: L times the sum over the
+// 16 segments of the squared distance from the query mean to the region) built from it is at
+// most the bound of every series of the run, hence at most their Euclidean distances. A (query,
+// run) pair whose block bound exceeds the query's threshold U_q holds no series that the screen
+// would have to keep: the screen skips it.
+// ------------------------------------------------------------------------------------------
+// Symbol envelope of every run of kEnvRun sorted positions: bytes 0..15 the smallest symbol of
+// each segment, bytes 16..31 the largest. One wave per run: lane l reads the 8 symbols of
+// segments 8 (l / 32) .. +7 of position l % 32 of the run.
+__global__ __launch_bounds__(256) void k_block_env(const uint8_t* __restrict__ saxs, long long N,
+                                                   uint8_t* __restrict__ env)
+{
+    const int lane = threadIdx.x & 63, half = lane >> 5;
+    const long long runs = (N + kEnvRun - 1) / kEnvRun;
+    const long long run = ((long long)blockIdx.x * 256 + threadIdx.x) >> 6;
+    if (run >= runs) return;   // whole waves leave together
+    const long long p = run * kEnvRun + (lane & 31);
+    uint32_t mn[8], mx[8];
+    const uint2 v = p < N ? *reinterpret_cast<const uint2*>(saxs + p * 16 + half * 8) : make_uint2(0u, 0u);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const uint32_t b = ((k < 4 ? v.x : v.y) >> (8 * (k & 3))) & 0xFFu;
+        mn[k] = p < N ? b : 255u;
+        mx[k] = p < N ? b : 0u;
+    }
+#pragma unroll
+    for (int o = 1; o < 32; o <<= 1) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            mn[k] = min(mn[k], (uint32_t)__shfl_xor((int)mn[k], o));
+            mx[k] = max(mx[k], (uint32_t)__shfl_xor((int)mx[k], o));
+        }
+    }
+    if ((lane & 31) == 0) {
+        uint2 lo = make_uint2(0u, 0u), hi = make_uint2(0u, 0u);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            lo.x |= mn[k] << (8 * k);
+            lo.y |= mn[k + 4] << (8 * k);
+            hi.x |= mx[k] << (8 * k);
+            hi.y |= mx[k + 4] << (8 * k);
+        }
+        *reinterpret_cast<uint2*>(env + run * 32 + half * 8) = lo;
+        *reinterpret_cast<uint2*>(env + run * 32 + 16 + half * 8) = hi;
+    }
+}
+
+hipError_t launch_block_env(const uint8_t* saxs, long long N, uint8_t* env, hipStream_t st)
+{
+    const long long runs = (N + kEnvRun - 1) / kEnvRun;
+    const long long blocks = (runs + 3) / 4;
+    k_block_env<<<(unsigned)blocks, 256, 0, st>>>(saxs, N, env);
+    return hipGetLastError();
+}
+
+// Alive bits of every (work item of XB sorted positions, query): bit q % 64 of word
+// item * ceil(M / 64) + q / 64 is set iff the item's block bound, evaluated in float64, is at
+// most U_q (1 + prune_rel) (U_q as in k_batch_thresholds, before any projection). A query
+// without a threshold (non-finite, or no seed) has no bits. One thread per query (so a wave
+// ballot is one word); a block takes kMaskItems items, whose envelopes it stages in LDS as
+// region edges.
+constexpr int kMaskItems = 64;
+
+__global__ __launch_bounds__(256) void k_block_mask(ScreenArgs Sa, int XB)
+{
+    __shared__ double beta[257];
+    __shared__ double s_lo[kMaskItems][kSeg], s_hi[kMaskItems][kSeg];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int M = Sa.M, words = (M + 63) >> 6;
+    const long long N = Sa.N;
+    const long long n_items = (N + XB - 1) / XB;
+    const long long it0 = (long long)blockIdx.x * kMaskItems;
+    const long long runs = (N + kEnvRun - 1) / kEnvRun;
+    const int rpi = XB / kEnvRun;
+    if (tid == 0) { beta[0] = -__builtin_inf(); beta[256] = __builtin_inf(); }
+    if (tid >= 1) beta[tid] = c_beta[tid];
+    __syncthreads();
+    for (int e = tid; e < kMaskItems * kSeg; e += 256) {
+        const int ii = e >> 4, sg = e & 15;
+        const long long item = it0 + ii;
+        uint32_t mn = 255u, mx = 0u;
+        for (int r = 0; r < rpi; ++r) {
+            const long long run = item * rpi + r;
+            if (item < n_items && run < runs) {
+                mn = min(mn, (uint32_t)Sa.env[run * 32 + sg]);
+                mx = max(mx, (uint32_t)Sa.env[run * 32 + 16 + sg]);
+            }
+        }
+        s_lo[ii][sg] = beta[mn];       // lower edge of the smallest symbol's region
+        s_hi[ii][sg] = beta[mx + 1];   // upper edge of the largest symbol's region
+    }
+    const int q = blockIdx.y * 256 + tid;
+    double pq[kSeg];
+    double thr = -1.0;   // no bit
+#pragma unroll
+    for (int sg = 0; sg < kSeg; ++sg) pq[sg] = 0.0;
+    if (q < M) {
+        const BQuery& b = Sa.bq[q];
+        if (!b.err && b.bsf_key != kBsfInit) {
+            thr = ((double)key_dist_b(b.bsf_key) * (1.0 + Sa.seed_rel) + 1e-20) * (1.0 + Sa.prune_rel);
+#pragma unroll
+            for (int sg = 0; sg < kSeg; ++sg) pq[sg] = Sa.qpaa[(long long)q * kSeg + sg];
+        }
+    }
+    __syncthreads();
+    const int word = (blockIdx.y * 256 + (tid & ~63)) >> 6;
+    for (int ii = 0; ii < kMaskItems; ++ii) {
+        const long long item = it0 + ii;
+        if (item >= n_items) break;   // uniform
+        double acc = 0.0;
+#pragma unroll
+        for (int sg = 0; sg < kSeg; ++sg) {
+            const double g = fmax(fmax(s_lo[ii][sg] - pq[sg], pq[sg] - s_hi[ii][sg]), 0.0);
+            acc = fma(g, g, acc);
+        }
+        const bool alive = thr >= 0.0 && acc * Sa.seg_len <= thr;
+        const unsigned long long bits = __ballot(alive);
+        if (lane == 0 && word < words) Sa.mask[item * words + word] = bits;
+    }
 }
 
 // ------------------------------------------------------------------------------------------
@@ -137,6 +273,7 @@ __global__ void k_batch_init(BQuery* __restrict__ bq, int M, BatchHdr* __restric
         hdr->n_cand = 0;
         hdr->n_fallback = 0;
         hdr->flags = 0;
+        hdr->n_tiles = 0;
     }
 }
 
@@ -248,6 +385,7 @@ __global__ __launch_bounds__(256, SUBS == 2 ? 2 : 1) void k_screen(ScreenArgs S)
         const long long item = s_item;
         if (item >= n_items) break;  // uniform: every wave reaches this exit
         const long long xb0 = item * XB + w * XW;
+        if (tid == 0) atomicAdd(&S.hdr->n_tiles, (uint32_t)n_qt);
 
         bf16x8 bfr[SUBS][KT];
 #pragma unroll
@@ -323,7 +461,7 @@ __global__ __launch_bounds__(256, SUBS == 2 ? 2 : 1) void k_screen(ScreenArgs S)
                         for (int r = 0; r < 4; ++r) {
                             const int q = t * QT + qs * 16 + kg * 4 + r;
                             const long long x = xb0 + sub * 16 + col;
-                            if (q < M && x < N) S.dump[(long long)q * N + x] = acc[qs][sub][r];
+                            if (q < M && x < N) S.dump[(long long)q * N + (S.perm ? S.perm[x] : x)] = acc[qs][sub][r];
                         }
             } else {
                 float m = kNoPass;
@@ -345,12 +483,13 @@ __global__ __launch_bounds__(256, SUBS == 2 ? 2 : 1) void k_screen(ScreenArgs S)
                                     const int q = t * QT + qs * 16 + kg * 4 + r;
                                     const long long x = xb0 + sub * 16 + col;
                                     if (q < M && x < N) {
+                                        const uint2 c = make_uint2((uint32_t)q, S.perm ? S.perm[x] : (uint32_t)x);
                                         const uint32_t p = atomicAdd(&ccount, 1u);
                                         if (p < (uint32_t)kCandStage) {
-                                            cbuf[p] = make_uint2((uint32_t)q, (uint32_t)x);
+                                            cbuf[p] = c;
                                         } else {  // more than the stage holds in one tile
                                             const uint32_t pos = atomicAdd(&S.hdr->n_cand, 1u);
-                                            if (pos < S.cand_cap) S.cand[pos] = make_uint2((uint32_t)q, (uint32_t)x);
+                                            if (pos < S.cand_cap) S.cand[pos] = c;
                                         }
                                     }
                                 }
@@ -383,9 +522,14 @@ __global__ __launch_bounds__(256, 2) void k_screen32(ScreenArgs Sa)
     constexpr int KT = KS16 + 1;        // k-steps including the bias step
     constexpr int QS = QT / 32;         // query subtiles per tile
     constexpr int CH = NP / 8;          // 16-byte chunks per query row
-    constexpr int SWM = CH >= 8 ? 7 : CH - 1;   // chunk swizzle mask (rows of a bank group)
+    // chunk swizzle mask: c ^ (row & SWM) must stay inside the row, so SWM + 1 divides CH
+    // (CH = 2 KS16 is a multiple of 4; a multiple of 8 takes the 8-row mask)
+    constexpr int SWM = CH % 8 == 0 ? 7 : 3;
+    static_assert(CH % (SWM + 1) == 0, "the swizzle must permute the chunks of a row");
     constexpr int TCH = QT * CH;        // chunks per query tile
     constexpr int LOADS = (TCH + 255) / 256;    // direct-to-LDS loads per lane per tile
+    // queries per alive list: two blocks per CU must fit in LDS next to the two tile buffers
+    constexpr int GROUP = QT * NP >= 64 * 256 ? kScreenGroup / 2 : kScreenGroup;
     // Query tiles go from global memory straight into LDS (global_load_lds_dwordx4: no staging
     // registers, so nothing holds the MFMAs back while the next tile is in flight). A row's
     // 16-byte chunk c sits at chunk c ^ (row & SWM) of the row, so the 8 rows that one LDS cycle
@@ -394,6 +538,9 @@ __global__ __launch_bounds__(256, 2) void k_screen32(ScreenArgs Sa)
     __shared__ __attribute__((aligned(16))) uint16_t qd1[QT * NP];
     __shared__ __attribute__((aligned(16))) uint16_t qb0[QT * 16];
     __shared__ __attribute__((aligned(16))) uint16_t qb1[QT * 16];
+    // queries of the current group whose block bound did not prune the item (ascending)
+    __shared__ uint16_t s_list[GROUP];
+    __shared__ uint32_t s_cnt;
     __shared__ long long s_item;
     __shared__ uint2 cbuf[kCandStage];
     __shared__ uint32_t ccount, cbase;
@@ -415,9 +562,16 @@ __global__ __launch_bounds__(256, 2) void k_screen32(ScreenArgs Sa)
     const int col = l & 31, kh = l >> 5;
     const int M = Sa.M;
     const long long N = Sa.N;
-    const int n_qt = (M + QT - 1) / QT;
     const long long n_items = (N + XB - 1) / XB;
     const bool dump = Sa.dump != nullptr;
+    const bool masked = Sa.mask != nullptr && !dump;
+    const int words = (M + 63) >> 6;
+    int g0 = 0, cnt = 0;   // current query group and its number of listed queries
+
+    // query of list entry i of the current group (i < cnt)
+    auto query_of = [&](int i) -> int { return g0 + (masked ? (int)s_list[i] : i); };
+    // series index of sorted position p (the bfloat16 rows are stored in leaf order)
+    auto series_of = [&](long long p) -> uint32_t { return Sa.perm ? Sa.perm[p] : (uint32_t)p; };
 
     // bias rows: [hi, lo, 1, 1, 0 ...]; the last 12 stay zero
     for (int e = tid; e < QT * 2; e += 256) {
@@ -425,11 +579,12 @@ __global__ __launch_bounds__(256, 2) void k_screen32(ScreenArgs Sa)
         *reinterpret_cast<uint4*>(&qb1[e * 8]) = make_uint4(0, 0, 0, 0);
     }
 
-    // tile t's data into qdata[buf] (asynchronous: complete after the next full wait) and its
-    // raw bias constants into registers; rows past the batch read row 0 (their bias never passes)
-    // The two tile buffers are distinct arrays addressed with a compile-time index (the tile loop
-    // is unrolled by two), so the compiler can see that the next tile's direct loads never write
-    // the buffer being read and need not wait for them before the LDS reads.
+    // tile t of the current list into qdata[buf] (asynchronous: complete after the next full
+    // wait) and its raw bias constants into registers; rows past the list read query g0 (their
+    // bias never passes). The two tile buffers are distinct arrays addressed with a compile-time
+    // index (the tile loop is unrolled by two), so the compiler can see that the next tile's
+    // direct loads never write the buffer being read and need not wait for them before the LDS
+    // reads.
     auto tile_load = [&](int t, auto BUF, uint2& bias) {
         uint16_t* dst = decltype(BUF)::value == 0 ? qd0 : qd1;
 #pragma unroll
@@ -438,17 +593,20 @@ __global__ __launch_bounds__(256, 2) void k_screen32(ScreenArgs Sa)
             if (pos < TCH) {
                 const int row = pos / CH, pc = pos - row * CH;
                 const int c = pc ^ (row & SWM);
-                const int q = t * QT + row;
-                const uint16_t* src = Sa.Qb + (long long)(q < M ? q : 0) * NP + c * 8;
+                const int i = t * QT + row;
+                const int q = i < cnt ? query_of(i) : g0;
+                const uint16_t* src = Sa.Qb + (long long)q * NP + c * 8;
                 __builtin_amdgcn_global_load_lds(
                     (__attribute__((address_space(1))) const void*)src,
                     (__attribute__((address_space(3))) void*)(dst + (j * 4 + w) * 64 * 8), 16, 0, 0);
             }
         }
         if (tid < QT) {
-            const int q = t * QT + tid;
-            bias.x = __float_as_uint(Sa.bq[q < M ? q : 0].a);
-            bias.y = dump ? 2u : (q < M ? 1u : 0u);
+            const int i = t * QT + tid;
+            const bool ok = i < cnt;
+            const int q = ok ? query_of(i) : g0;
+            bias.x = __float_as_uint(Sa.bq[q].a);
+            bias.y = dump ? 2u : (ok ? 1u : 0u);
         }
     };
     auto bias_store = [&](auto BUF, uint2 bias) {
@@ -471,128 +629,167 @@ __global__ __launch_bounds__(256, 2) void k_screen32(ScreenArgs Sa)
         const long long xb0 = item * XB + w * XW;
 
         bf16x8 bfr[S][KT];
+        bool loaded = false;   // uniform: the series rows are read at the first non-empty group
+        uint32_t tiles = 0;
+        for (g0 = 0; g0 < M; g0 += GROUP) {
+            if (masked) {
+                // the group's alive bits -> ascending list of queries (one wave, prefix sum of
+                // the word popcounts); the barrier first: every wave has read the last count
+                __syncthreads();
+                if (w == 0) {
+                    const int w0 = g0 >> 6, gw = min(GROUP / 64, words - w0);
+                    unsigned long long bits = l < gw ? Sa.mask[item * words + w0 + l] : 0ull;
+                    const uint32_t pc = (uint32_t)__popcll(bits);
+                    uint32_t inc = pc;
 #pragma unroll
-        for (int sub = 0; sub < S; ++sub) {
-            const long long x = xb0 + sub * 32 + col;
-            const bool ok = x < N;
-#pragma unroll
-            for (int ks = 0; ks < KS16; ++ks) {
-                if (ok) bfr[sub][ks] = *reinterpret_cast<const bf16x8*>(Sa.Xb + x * NP + ks * 16 + kh * 8);
-                else bfr[sub][ks] = bf16x8{};
-            }
-            float t2 = kNoPass;
-            if (ok) t2 = dump ? 0.f : -__double2float_rd((1.0 - (double)Sa.c_screen) * (double)Sa.xn[x] * 0.5);
-            uint4 bb = make_uint4(0, 0, 0, 0);
-            if (kh == 0) {
-                bb.x = 0x3F803F80u;   // [1.0, 1.0, hi(-b_x), lo(-b_x)]
-                bb.y = bias_pair(t2).x;
-            }
-            bfr[sub][KS16] = __builtin_bit_cast(bf16x8, bb);
-        }
-
-        {
-            uint2 bias = make_uint2(0u, 0u);
-            tile_load(0, std::integral_constant<int, 0>{}, bias);
-            bias_store(std::integral_constant<int, 0>{}, bias);
-            __builtin_amdgcn_s_waitcnt(0);
-        }
-        __syncthreads();
-
-        auto tile = [&](int t, auto CUR) {
-            constexpr int B = decltype(CUR)::value;
-            const std::integral_constant<int, 1 - B> NEXT{};
-            uint2 bias = make_uint2(0u, 0u);
-            const bool more = t + 1 < n_qt;
-            if (more) tile_load(t + 1, NEXT, bias);  // lands in LDS during the MFMAs
-
-            f32x16 acc[QS][S];
-#pragma unroll
-            for (int qs = 0; qs < QS; ++qs)
-#pragma unroll
-                for (int sub = 0; sub < S; ++sub)
-#pragma unroll
-                    for (int i = 0; i < 16; ++i) acc[qs][sub][i] = 0.f;
-            const uint16_t* tb = B == 0 ? qd0 : qd1;
-            const uint16_t* tbb = (B == 0 ? qb0 : qb1) + col * 16 + kh * 8;
-            auto a_frag = [&](int qs, int ks) -> bf16x8 {
-                const int row = qs * 32 + col;
-                if (ks == KS16) return *reinterpret_cast<const bf16x8*>(tbb + qs * 32 * 16);
-                const int c = (2 * ks + kh) ^ (row & SWM);
-                return *reinterpret_cast<const bf16x8*>(tb + row * NP + c * 8);
-            };
-            bf16x8 a[QS], an[QS];
-#pragma unroll
-            for (int qs = 0; qs < QS; ++qs) a[qs] = a_frag(qs, 0);
-#pragma unroll
-            for (int ks = 0; ks < KT; ++ks) {
-                if (ks + 1 < KT) {
-#pragma unroll
-                    for (int qs = 0; qs < QS; ++qs) an[qs] = a_frag(qs, ks + 1);
+                    for (int o = 1; o < 64; o <<= 1) {
+                        const uint32_t v = __shfl_up(inc, o);
+                        if (l >= o) inc += v;
+                    }
+                    uint32_t pos = inc - pc;
+                    while (bits) {
+                        s_list[pos++] = (uint16_t)(l * 64 + __builtin_ctzll(bits));
+                        bits &= bits - 1ull;
+                    }
+                    if (l == 63) s_cnt = inc;
                 }
-#pragma unroll
-                for (int qs = 0; qs < QS; ++qs)
-#pragma unroll
-                    for (int sub = 0; sub < S; ++sub)
-                        acc[qs][sub] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[qs], bfr[sub][ks], acc[qs][sub],
-                                                                               0, 0, 0);
-                if (ks + 1 < KT) {
-#pragma unroll
-                    for (int qs = 0; qs < QS; ++qs) a[qs] = an[qs];
-                }
-            }
-
-            if (dump) {
-#pragma unroll
-                for (int qs = 0; qs < QS; ++qs)
-#pragma unroll
-                    for (int sub = 0; sub < S; ++sub)
-#pragma unroll
-                        for (int i = 0; i < 16; ++i) {
-                            const int q = t * QT + qs * 32 + 8 * (i >> 2) + 4 * kh + (i & 3);
-                            const long long x = xb0 + sub * 32 + col;
-                            if (q < M && x < N) Sa.dump[(long long)q * N + x] = acc[qs][sub][i];
-                        }
+                __syncthreads();
+                cnt = (int)s_cnt;
             } else {
-                float m = kNoPass;
+                cnt = min(GROUP, M - g0);
+            }
+            if (cnt == 0) continue;   // uniform
+            if (!loaded) {
+                loaded = true;
+#pragma unroll
+                for (int sub = 0; sub < S; ++sub) {
+                    const long long x = xb0 + sub * 32 + col;
+                    const bool ok = x < N;
+#pragma unroll
+                    for (int ks = 0; ks < KS16; ++ks) {
+                        if (ok) bfr[sub][ks] = *reinterpret_cast<const bf16x8*>(Sa.Xb + x * NP + ks * 16 + kh * 8);
+                        else bfr[sub][ks] = bf16x8{};
+                    }
+                    float t2 = kNoPass;
+                    if (ok) t2 = dump ? 0.f : -__double2float_rd((1.0 - (double)Sa.c_screen) * (double)Sa.xn[x] * 0.5);
+                    uint4 bb = make_uint4(0, 0, 0, 0);
+                    if (kh == 0) {
+                        bb.x = 0x3F803F80u;   // [1.0, 1.0, hi(-b_x), lo(-b_x)]
+                        bb.y = bias_pair(t2).x;
+                    }
+                    bfr[sub][KS16] = __builtin_bit_cast(bf16x8, bb);
+                }
+            }
+            const int n_qt = (cnt + QT - 1) / QT;
+            tiles += (uint32_t)n_qt;
+
+            {
+                uint2 bias = make_uint2(0u, 0u);
+                tile_load(0, std::integral_constant<int, 0>{}, bias);
+                bias_store(std::integral_constant<int, 0>{}, bias);
+                __builtin_amdgcn_s_waitcnt(0);
+            }
+            __syncthreads();
+
+            auto tile = [&](int t, auto CUR) {
+                constexpr int B = decltype(CUR)::value;
+                const std::integral_constant<int, 1 - B> NEXT{};
+                uint2 bias = make_uint2(0u, 0u);
+                const bool more = t + 1 < n_qt;
+                if (more) tile_load(t + 1, NEXT, bias);  // lands in LDS during the MFMAs
+
+                f32x16 acc[QS][S];
 #pragma unroll
                 for (int qs = 0; qs < QS; ++qs)
 #pragma unroll
                     for (int sub = 0; sub < S; ++sub)
 #pragma unroll
-                        for (int i = 0; i < 16; ++i) m = fmaxf(m, acc[qs][sub][i]);
-                const bool hit = m >= 0.f;
-                if (__ballot(hit) && hit) {
+                        for (int i = 0; i < 16; ++i) acc[qs][sub][i] = 0.f;
+                const uint16_t* tb = B == 0 ? qd0 : qd1;
+                const uint16_t* tbb = (B == 0 ? qb0 : qb1) + col * 16 + kh * 8;
+                auto a_frag = [&](int qs, int ks) -> bf16x8 {
+                    const int row = qs * 32 + col;
+                    if (ks == KS16) return *reinterpret_cast<const bf16x8*>(tbb + qs * 32 * 16);
+                    const int c = (2 * ks + kh) ^ (row & SWM);
+                    return *reinterpret_cast<const bf16x8*>(tb + row * NP + c * 8);
+                };
+                bf16x8 a[QS], an[QS];
+#pragma unroll
+                for (int qs = 0; qs < QS; ++qs) a[qs] = a_frag(qs, 0);
+#pragma unroll
+                for (int ks = 0; ks < KT; ++ks) {
+                    if (ks + 1 < KT) {
+#pragma unroll
+                        for (int qs = 0; qs < QS; ++qs) an[qs] = a_frag(qs, ks + 1);
+                    }
+#pragma unroll
+                    for (int qs = 0; qs < QS; ++qs)
+#pragma unroll
+                        for (int sub = 0; sub < S; ++sub)
+                            acc[qs][sub] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[qs], bfr[sub][ks], acc[qs][sub],
+                                                                                   0, 0, 0);
+                    if (ks + 1 < KT) {
+#pragma unroll
+                        for (int qs = 0; qs < QS; ++qs) a[qs] = an[qs];
+                    }
+                }
+
+                if (dump) {
 #pragma unroll
                     for (int qs = 0; qs < QS; ++qs)
 #pragma unroll
                         for (int sub = 0; sub < S; ++sub)
 #pragma unroll
                             for (int i = 0; i < 16; ++i) {
-                                if (acc[qs][sub][i] >= 0.f) {
-                                    const int q = t * QT + qs * 32 + 8 * (i >> 2) + 4 * kh + (i & 3);
-                                    const long long x = xb0 + sub * 32 + col;
-                                    if (q < M && x < N) {
-                                        const uint32_t p = atomicAdd(&ccount, 1u);
-                                        if (p < (uint32_t)kCandStage) {
-                                            cbuf[p] = make_uint2((uint32_t)q, (uint32_t)x);
-                                        } else {  // more than the stage holds in one tile
-                                            const uint32_t pos = atomicAdd(&Sa.hdr->n_cand, 1u);
-                                            if (pos < Sa.cand_cap) Sa.cand[pos] = make_uint2((uint32_t)q, (uint32_t)x);
+                                const int r = t * QT + qs * 32 + 8 * (i >> 2) + 4 * kh + (i & 3);
+                                const long long p = xb0 + sub * 32 + col;
+                                if (r < cnt && p < N)
+                                    Sa.dump[(long long)query_of(r) * N + series_of(p)] = acc[qs][sub][i];
+                            }
+                } else {
+                    float m = kNoPass;
+#pragma unroll
+                    for (int qs = 0; qs < QS; ++qs)
+#pragma unroll
+                        for (int sub = 0; sub < S; ++sub)
+#pragma unroll
+                            for (int i = 0; i < 16; ++i) m = fmaxf(m, acc[qs][sub][i]);
+                    const bool hit = m >= 0.f;
+                    if (__ballot(hit) && hit) {
+#pragma unroll
+                        for (int qs = 0; qs < QS; ++qs)
+#pragma unroll
+                            for (int sub = 0; sub < S; ++sub)
+#pragma unroll
+                                for (int i = 0; i < 16; ++i) {
+                                    if (acc[qs][sub][i] >= 0.f) {
+                                        const int r = t * QT + qs * 32 + 8 * (i >> 2) + 4 * kh + (i & 3);
+                                        const long long p = xb0 + sub * 32 + col;
+                                        if (r < cnt && p < N) {
+                                            const uint2 c = make_uint2((uint32_t)query_of(r), series_of(p));
+                                            const uint32_t k = atomicAdd(&ccount, 1u);
+                                            if (k < (uint32_t)kCandStage) {
+                                                cbuf[k] = c;
+                                            } else {  // more than the stage holds in one tile
+                                                const uint32_t pos = atomicAdd(&Sa.hdr->n_cand, 1u);
+                                                if (pos < Sa.cand_cap) Sa.cand[pos] = c;
+                                            }
                                         }
                                     }
                                 }
-                            }
+                    }
                 }
+                if (more) bias_store(NEXT, bias);
+                __builtin_amdgcn_s_waitcnt(0);   // this wave's direct-to-LDS loads have landed
+                __syncthreads();
+                if (ccount >= (uint32_t)(kCandStage / 2)) flush_cands();  // uniform: read after the barrier
+            };
+            for (int t = 0; t < n_qt; t += 2) {
+                tile(t, std::integral_constant<int, 0>{});
+                if (t + 1 < n_qt) tile(t + 1, std::integral_constant<int, 1>{});
             }
-            if (more) bias_store(NEXT, bias);
-            __builtin_amdgcn_s_waitcnt(0);   // this wave's direct-to-LDS loads have landed
-            __syncthreads();
-            if (ccount >= (uint32_t)(kCandStage / 2)) flush_cands();  // uniform: read after the barrier
-        };
-        for (int t = 0; t < n_qt; t += 2) {
-            tile(t, std::integral_constant<int, 0>{});
-            if (t + 1 < n_qt) tile(t + 1, std::integral_constant<int, 1>{});
         }
+        if (tid == 0 && tiles) atomicAdd(&Sa.hdr->n_tiles, tiles);
     }
     __syncthreads();
     if (ccount) flush_cands();
@@ -632,8 +829,26 @@ static hipError_t launch_screen_ks(const ScreenArgs& s, ScreenShape shape, hipSt
     return hipGetLastError();
 }
 
-hipError_t launch_screen(const ScreenArgs& s, int np, ScreenShape shape, hipStream_t st)
+// Work-item size (sorted positions) of a screen shape.
+int screen_item_series(ScreenShape shape) { return shape.mfma == 32 ? 128 * shape.subs : 64 * shape.subs; }
+
+// The block bound serves the 32-wide form (the 16-wide one screens every pair).
+bool screen_uses_mask(const ScreenArgs& s, ScreenShape shape) { return s.mask && !s.dump && shape.mfma == 32; }
+
+hipError_t launch_block_mask(const ScreenArgs& s, ScreenShape shape, hipStream_t st)
 {
+    if (!screen_uses_mask(s, shape)) return hipSuccess;
+    const int XB = screen_item_series(shape);
+    const long long items = (s.N + XB - 1) / XB;
+    const dim3 grid((unsigned)((items + kMaskItems - 1) / kMaskItems), (unsigned)((s.M + 255) / 256));
+    k_block_mask<<<grid, 256, 0, st>>>(s, XB);
+    return hipGetLastError();
+}
+
+hipError_t launch_screen(const ScreenArgs& s_in, int np, ScreenShape shape, hipStream_t st)
+{
+    ScreenArgs s = s_in;
+    if (!screen_uses_mask(s, shape)) s.mask = nullptr;
     if (shape.mfma == 32) {
         switch (np / 32) {
         case 1: return launch_screen32_ks<2>(s, shape, st);

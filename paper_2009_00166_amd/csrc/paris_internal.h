@@ -129,14 +129,20 @@ struct SeedBatch {
     int np;               // screened dimensions (n / P) rounded up to a multiple of 32
     int P;                // segment length of the screen's projection (1: the series itself)
     const int32_t* leaves;  // learned seed: [M][kTopLeaves] leaf ids (used when learned_cpl > 0)
+    double* qpaa;         // [M][16] float64 PAA of every query (for the screen's block bound)
 };
 
 struct BatchHdr {
-    uint32_t next_item;    // screen work counter (series tiles of 256)
+    uint32_t next_item;    // screen work counter (series work items)
     uint32_t n_cand;       // screen candidates appended (may exceed the capacity)
     uint32_t n_fallback;   // queries handed back to the per-query path
     uint32_t flags;
+    uint32_t n_tiles;      // query tiles the screen ran (summed over its work items)
+    uint32_t pad;
 };
+
+constexpr int kEnvRun = 32;          // sorted positions per stored symbol envelope
+constexpr int kScreenGroup = 4096;   // queries per alive list of the screen
 
 struct ScreenArgs {
     const uint16_t* Xb;    // [N][np] bfloat16 collection
@@ -150,6 +156,13 @@ struct ScreenArgs {
     BatchHdr* hdr;
     float c_screen;        // relative margin c of E = c (qn + xn)
     float* dump;           // optional [M][N] float32 dot products (tests)
+    const uint32_t* perm;  // [N] series at each sorted position (Xb and xn are in leaf order)
+    // block bound (nullptr mask: every pair is screened)
+    unsigned long long* mask;  // [items][ceil(M / 64)] alive bits, written by k_block_mask
+    const uint8_t* env;    // [ceil(N / kEnvRun)][32] symbol envelopes (min[16], max[16])
+    const double* qpaa;    // [M][16] float64 query PAA
+    double seg_len;        // L = n / 16
+    double seed_rel, prune_rel;
 };
 
 struct RescoreArgs {
@@ -172,9 +185,14 @@ struct ScreenShape {
     int mfma;   // 16: v_mfma_f32_16x16x32_bf16; 32: v_mfma_f32_32x32x16_bf16
 };
 
-hipError_t launch_to_bf16(const float* X, long long N, int n, int np, int P, uint16_t* Xb, float* xn, hipStream_t st);
+hipError_t launch_to_bf16(const float* X, const uint32_t* perm, long long N, int n, int np, int P, uint16_t* Xb,
+                          float* xn, hipStream_t st);
+hipError_t launch_block_env(const uint8_t* saxs, long long N, uint8_t* env, hipStream_t st);
+int screen_item_series(ScreenShape shape);
 hipError_t launch_batch_init(BQuery* bq, int M, BatchHdr* hdr, hipStream_t st);
 hipError_t launch_batch_thresholds(BQuery* bq, int M, float c_screen, double seed_rel, int P, hipStream_t st);
+// alive bits of the block bound (no launch when the shape or arguments do not use them)
+hipError_t launch_block_mask(const ScreenArgs& s, ScreenShape shape, hipStream_t st);
 hipError_t launch_screen(const ScreenArgs& s, int np, ScreenShape shape, hipStream_t st);
 hipError_t launch_rescore(const RescoreArgs& r, hipStream_t st);
 hipError_t launch_batch_resolve(const RescoreArgs& r, long long* out_idx, double* out_dist, hipStream_t st);

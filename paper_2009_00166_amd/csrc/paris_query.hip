@@ -210,6 +210,7 @@ __global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* 
         // bfloat16 copy of the query (zero padded to np) and its float32 squared norm
         // (segment means over B.P points when the screen works on a projection of the series)
         uint16_t* qb = B.qb + (long long)blockIdx.y * B.np;
+        if (tid < kSeg && B.qpaa) B.qpaa[(long long)blockIdx.y * kSeg + tid] = qpaa[tid];
         const int nd = n / B.P;
         float sq = 0.f;
         for (int j = tid; j < B.np; j += 256) {
@@ -398,7 +399,7 @@ int seed_grid(const QueryArgs& a)
 
 hipError_t launch_prepare_seed(const QueryArgs& a, const float* q, hipStream_t st)
 {
-    SeedBatch none{nullptr, nullptr, nullptr, 0, 1, nullptr};
+    SeedBatch none{nullptr, nullptr, nullptr, 0, 1, nullptr, nullptr};
     k_prepare_seed<<<seed_grid(a), 256, (size_t)a.n * sizeof(float), st>>>(a, q, none);
     return hipGetLastError();
 }

@@ -184,11 +184,13 @@ def test_projected_screen_bound_and_lower_bound():
     idx.close()
 
 
-def test_screen_dot_error_bound_512_dimensions():
-    """Lengths 257..512 run the 32-wide screen with all dimensions: the bound on 512-point rows."""
+@pytest.mark.parametrize("n", [96, 160, 272, 400, 512])
+def test_screen_dot_error_bound_row_widths(n):
+    """The 32-wide screen's rows of np = roundup(n, 32) dimensions (np / 8 = 12, 20, 36, 52 or
+    64 chunks of 16 bytes, swizzled in LDS): the bound on every (query, series) pair."""
     _need_gpu()
     import paper_2009_00166_amd as paris
-    X = synth.random_walks(4000, 512, seed=15)
+    X = synth.random_walks(4000, n, seed=15)
     Q, _, _ = synth.noisy_queries(X, 64, seed=16, sigma=(0.0, 1.0))
     idx = paris.build(torch.from_numpy(X).cuda())
     idx.attach_batch(max_batch=64)
@@ -197,7 +199,8 @@ def test_screen_dot_error_bound_512_dimensions():
     exact = Qf @ Xf.T
     qn = (Qf ** 2).sum(1)[:, None]
     xn = (Xf ** 2).sum(1)[None, :]
-    c = _screen_margin(512, 512)
+    np_ = (n + 31) // 32 * 32
+    c = _screen_margin(n, np_)
     assert np.all(np.abs(2 * dots - 2 * exact) <= c * (qn + xn))
     idx.close()
 
@@ -248,4 +251,56 @@ def test_every_screen_shape_gives_exact_answers(oracle_native, monkeypatch):
         torch.cuda.synchronize()
         assert np.array_equal(I.cpu().numpy(), ri), shape
         assert np.array_equal(D.cpu().numpy(), np.sqrt(rd)), shape
+    idx.close()
+
+
+def test_block_bound_prunes_and_changes_no_answer(oracle_native, monkeypatch):
+    """The block bound (iSAX lower bound of each query against the symbol envelope of runs of
+    consecutive series in leaf order, Section 3.3.1) keeps the screen away from most
+    (query, run) pairs, and every answer stays the oracle's: the same with the bound off."""
+    _need_gpu()
+    import paper_2009_00166_amd as paris
+    X = synth.random_walks(200_000, 256, seed=21)
+    Q, _, _ = synth.noisy_queries(X, 300, seed=22, sigma=(0.01, 0.5))
+    ri, rd, _ = oracle_native.nn_many(Q, X, threads=16)
+    Xd, Qd = torch.from_numpy(X).cuda(), torch.from_numpy(Q).cuda()
+    idx = paris.build(Xd)
+    res = {}
+    for flag in ("0", "1"):
+        monkeypatch.setenv("PARIS_BLOCK_LB", flag)
+        idx.attach_batch(max_batch=256)
+        I, D = idx.query_batch(Qd)
+        torch.cuda.synchronize()
+        res[flag] = (I.cpu().numpy(), D.cpu().numpy(), idx.screen_tiles(reset=True))
+    for flag, (I, D, _) in res.items():
+        assert np.array_equal(I, ri), flag
+        assert np.array_equal(D, np.sqrt(rd)), flag
+    run0, dense0 = res["0"][2]
+    run1, dense1 = res["1"][2]
+    assert run0 == dense0 > 0
+    assert dense1 == dense0
+    print(f"screen tiles with the block bound: {run1} of {dense1} ({run1 / dense1:.3f})")
+    assert run1 < 0.75 * dense1
+    idx.close()
+
+
+@pytest.mark.parametrize("shape", ["32,2,32", "64,1,32"])
+def test_block_bound_over_several_query_groups(shape, oracle_native, monkeypatch):
+    """A chunk of 4,500 queries: the 32-wide screen walks its alive lists in groups (4,096 or
+    2,048 queries), with a ragged last group and series tail."""
+    _need_gpu()
+    import paper_2009_00166_amd as paris
+    X = synth.random_walks(8_000, 256, seed=25)
+    Q, _, _ = synth.noisy_queries(X, 4500, seed=26, sigma=(0.01, 0.5))
+    ri, rd, _ = oracle_native.nn_many(Q, X, threads=16)
+    Xd, Qd = torch.from_numpy(X).cuda(), torch.from_numpy(Q).cuda()
+    idx = paris.build(Xd)
+    monkeypatch.setenv("PARIS_SCREEN_SHAPE", shape)
+    idx.attach_batch(max_batch=4500)
+    I, D = idx.query_batch(Qd)
+    torch.cuda.synchronize()
+    assert np.array_equal(I.cpu().numpy(), ri)
+    assert np.array_equal(D.cpu().numpy(), np.sqrt(rd))
+    run, dense = idx.screen_tiles()
+    assert 0 < run < dense
     idx.close()

@@ -142,3 +142,48 @@ def test_nn_matches_library_argmin_and_ties():
     assert i == 35 and d == 0.0
     q = X2[35] + np.float32(1e-3)
     assert nn_bruteforce(q, X2)[0] == 35
+
+
+def test_block_bound_hand_worked_and_special_cases():
+    """The run bound: one member reduces it to that member's bound; a query inside the run's
+    symbol envelope in every segment gets 0; a hand-worked two-member run."""
+    from oracle import block_lower_bound_sq
+    b = breakpoints()
+    rng = np.random.default_rng(31)
+    L = 16
+    for _ in range(20):
+        sym = rng.integers(0, 256, 16).astype(np.uint8)
+        qp = rng.standard_normal(16)
+        assert block_lower_bound_sq(qp, sym[None, :], L) == lower_bound_sq(qp, sym[None, :], L)[0]
+    lo_sym = np.full(16, 100, np.uint8)
+    hi_sym = np.full(16, 140, np.uint8)
+    run = np.stack([lo_sym, hi_sym])
+    inside = np.full(16, 0.5 * (b[120] + b[121]))
+    assert block_lower_bound_sq(inside, run, L) == 0.0
+    # segment 0 below the envelope by 0.25, segment 1 above it by 0.5, the rest inside:
+    # L * (0.25^2 + 0.5^2) by hand
+    q = inside.copy()
+    q[0] = b[100] - 0.25
+    q[1] = b[141] + 0.5
+    assert block_lower_bound_sq(q, run, L) == pytest.approx(L * (0.25 ** 2 + 0.5 ** 2), rel=1e-14)
+
+
+@pytest.mark.parametrize("run", [2, 32, 256])
+def test_block_bound_below_every_member(run):
+    """Brute force over every member: the run bound never exceeds a member's bound or its
+    squared Euclidean distance, and adding members never raises it."""
+    from oracle import block_lower_bound_sq
+    rng = np.random.default_rng(40 + run)
+    n = 64
+    X = _walks(rng, 4 * run, n)
+    Q = _walks(rng, 10, n)
+    L = n // 16
+    S = isax(paa(X))
+    for q in Q:
+        qp = paa(q)
+        for r0 in range(0, X.shape[0], run):
+            members = S[r0:r0 + run]
+            blb = block_lower_bound_sq(qp, members, L)
+            assert np.all(blb <= lower_bound_sq(qp, members, L))
+            assert np.all(blb <= ed_sq(q, X[r0:r0 + run]))
+            assert block_lower_bound_sq(qp, members[: max(1, run // 2)], L) >= blb

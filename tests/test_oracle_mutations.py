@@ -125,3 +125,27 @@ def test_mlp_dropped_bias_gradient_is_caught(monkeypatch):
 def test_mlp_output_gradient_sign_is_caught(monkeypatch):
     _patched_grad(monkeypatch, lambda p: p.__setitem__("W3", -p["W3"]))
     _fails(T_mlp.test_gradient_matches_finite_differences)
+
+
+def test_block_bound_lower_edge_of_largest_symbol_is_caught(monkeypatch):
+    """Envelope closed at the lower edge of the largest symbol instead of its upper edge."""
+    real_b = R.breakpoints_at_cardinality
+
+    def bad(qpaa, sym_run, L, bits=8):
+        b = real_b(bits)
+        sym_run = np.asarray(sym_run).astype(np.int64).reshape(-1, R.W)
+        d = R._delta(np.asarray(qpaa, np.float64), b[sym_run.min(0)], b[sym_run.max(0)])
+        return np.float64(L) * float(np.sum(d * d))
+    monkeypatch.setattr(R, "block_lower_bound_sq", bad)
+    import oracle
+    monkeypatch.setattr(oracle, "block_lower_bound_sq", bad)
+    _fails(T_lb.test_block_bound_hand_worked_and_special_cases)
+
+
+def test_block_bound_from_first_member_only_is_caught(monkeypatch):
+    """The envelope taken from one member instead of the whole run."""
+    real = R.lower_bound_sq
+    bad = lambda qpaa, sym_run, L, bits=8: real(qpaa, np.asarray(sym_run).reshape(-1, R.W)[:1], L, bits)[0]
+    import oracle
+    monkeypatch.setattr(oracle, "block_lower_bound_sq", bad)
+    _fails(T_lb.test_block_bound_below_every_member, 32)
