@@ -13,6 +13,7 @@ constexpr int kSym = 256;          // 8-bit symbols
 constexpr int kCoarse = 32;        // 5-bit prefix alphabet of the coarse lower-bound table
 constexpr int kMaxLength = 2048;   // longest series the summarise kernel stages in LDS
 constexpr int kSeedChunk = 512;    // sorted positions per seed block: its smallest bound is refined
+constexpr int kSeedBatchChunks = 32;  // seed chunks per block of the batched seed
 constexpr int kResolveList = 256;  // in-band candidates resolved block-cooperatively
 constexpr int kRefineBlocks = 512; // default refine grid (16 lane groups of 16 lanes per block)
 constexpr int kRefineMinBlocks = 128;  // refine blocks taking part with few survivors
@@ -130,6 +131,7 @@ struct SeedBatch {
     int P;                // segment length of the screen's projection (1: the series itself)
     const int32_t* leaves;  // learned seed: [M][kTopLeaves] leaf ids (used when learned_cpl > 0)
     double* qpaa;         // [M][16] float64 PAA of every query (for the screen's block bound)
+    int chunks;           // seed chunks of a query's window(s) (set by the launcher)
 };
 
 struct BatchHdr {

@@ -164,6 +164,7 @@ __global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* 
     __shared__ unsigned long long red_key[4];
     __shared__ int32_t s_leaves[kTopLeaves];
     __shared__ unsigned long long s_keys[(kMaxLeaves / 256) * kTopLeaves];
+    __shared__ unsigned long long s_best[kSeedBatchChunks];
 
     const int tid = threadIdx.x, lane = tid & 63;
     const int n = A.n, L = n >> 4;
@@ -251,15 +252,25 @@ __global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* 
         }
     }
 
-    // approximate-search window (sorted positions), computed by every block
+    // approximate-search window (sorted positions), numbered in chunks of kSeedChunk positions
+    // ("virtual chunks"). Per-query path: block b scans virtual chunk b. Learned seed: virtual
+    // chunk v is chunk v % cpl of the (v / cpl)-th best-scoring leaf; the per-query path merges
+    // the network blocks' 8 best (logit, leaf) keys here. Batched path: block b of a query takes
+    // virtual chunks [b kSeedBatchChunks, (b + 1) kSeedBatchChunks), so the query summary, its
+    // tables and the window search are paid once per block rather than once per chunk.
     long long lo = 0, hi = 0;
     const unsigned long long kq = s_k64;
     const bool learned = A.learned_cpl > 0;
-    long long chunk0 = (long long)blockIdx.x * kSeedChunk;
+    const int32_t* lv = nullptr;
+    auto leaf_window = [&](int slot, long long& wl, long long& wh) {
+        const long long N = A.N, nl = A.n_leaves;
+        long long ell = lv[slot];
+        if (ell < 0) ell = 0;
+        if (ell > nl - 1) ell = nl - 1;
+        wl = ell * N / nl;
+        wh = (ell + 1) * N / nl;
+    };
     if (learned) {
-        // learned seed: block (slot, chunk) scans chunk `chunk` of the slot-th best-scoring leaf.
-        // Per-query path: the 8 best of the network blocks' (logit, leaf) keys, merged here.
-        const int32_t* lv;
         if (batch) {
             lv = B.leaves + (long long)blockIdx.y * kTopLeaves;
         } else {
@@ -276,14 +287,7 @@ __global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* 
             __syncthreads();
             lv = s_leaves;
         }
-        const int slot = (int)blockIdx.x / A.learned_cpl;
-        const long long N = A.N, nl = A.n_leaves;
-        long long ell = lv[slot];
-        if (ell < 0) ell = 0;
-        if (ell > nl - 1) ell = nl - 1;
-        lo = ell * N / nl;
-        hi = (ell + 1) * N / nl;
-        chunk0 = (long long)((int)blockIdx.x - slot * A.learned_cpl) * kSeedChunk;
+        leaf_window(0, lo, hi);
     } else if (A.leaf_mode == 0) {
         if (A.seed_cap > 0) {
             uint32_t R = s_root;
@@ -351,29 +355,42 @@ __global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* 
         qs->win_hi = hi;
         if (s_bad) atomicOr(&qs->err, (uint32_t)kErrNonFinite);
     }
+    if (s_bad) return;  // uniform across the block
 
-    // seed: the smallest fine bound of this block's chunk, then its real distance
-    const long long c0 = lo + chunk0;
-    if (c0 >= hi || s_bad) return;  // uniform across the block
-    const long long c1 = (c0 + kSeedChunk < hi) ? c0 + kSeedChunk : hi;
-    unsigned long long best = ~0ull;  // (lb bits, row)
-    for (long long p = c0 + tid; p < c1; p += 256) {
-        const uint32_t row = A.perm[p];
-        const uint4 w = reinterpret_cast<const uint4*>(A.saxs)[p];   // leaf-order copy: contiguous
-        const float lb = fine_lb(w, t8);
-        const unsigned long long k = pack_key(lb, row);
-        best = k < best ? k : best;
-    }
-    for (int off = 32; off > 0; off >>= 1) {
-        const unsigned long long o = __shfl_xor(best, off);
-        best = o < best ? o : best;
-    }
-    if (lane == 0) red_key[tid >> 6] = best;
-    __syncthreads();
-    if (tid < 64) {
+    // positions [c0, c1) of virtual chunk v
+    auto chunk_range = [&](int v, long long& c0, long long& c1) {
+        long long wl = lo, wh = hi, ch = (long long)v * kSeedChunk;
+        if (learned) {
+            const int slot = v / A.learned_cpl;
+            leaf_window(slot, wl, wh);
+            ch = (long long)(v - slot * A.learned_cpl) * kSeedChunk;
+        }
+        c0 = wl + ch;
+        c1 = (c0 + kSeedChunk < wh) ? c0 + kSeedChunk : wh;
+    };
+    // the chunk member with the smallest fine bound, as a (bound, row) key (whole block)
+    auto chunk_best = [&](long long c0, long long c1) -> unsigned long long {
+        unsigned long long best = ~0ull;
+        for (long long p = c0 + tid; p < c1; p += 256) {
+            const uint32_t row = A.perm[p];
+            const uint4 w = reinterpret_cast<const uint4*>(A.saxs)[p];   // leaf-order copy: contiguous
+            const float lb = fine_lb(w, t8);
+            const unsigned long long k = pack_key(lb, row);
+            best = k < best ? k : best;
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const unsigned long long o = __shfl_xor(best, off);
+            best = o < best ? o : best;
+        }
+        if (lane == 0) red_key[tid >> 6] = best;
+        __syncthreads();
         best = red_key[0];
         for (int k = 1; k < 4; ++k) best = red_key[k] < best ? red_key[k] : best;
-        const uint32_t row = (uint32_t)(best & 0xFFFFFFFFu);
+        __syncthreads();   // red_key is rewritten by the next chunk
+        return best;
+    };
+    // float32 squared distance of the query to series `row` (one wave; every lane gets it)
+    auto wave_dist = [&](uint32_t row) -> float {
         const float4* r4 = reinterpret_cast<const float4*>(A.X + (long long)row * n);
         const float4* q4 = reinterpret_cast<const float4*>(qv);
         float acc = 0.f;
@@ -382,9 +399,42 @@ __global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* 
             const float dx = b.x - a.x, dy = b.y - a.y, dz = b.z - a.z, dw = b.w - a.w;
             acc += (dx * dx + dy * dy) + (dz * dz + dw * dw);
         }
-        acc = wave_sum(acc);
-        if (lane == 0) atomicMin(bsf, pack_key(acc, row));
+        return wave_sum(acc);
+    };
+
+    if (!batch) {
+        long long c0, c1;
+        chunk_range((int)blockIdx.x, c0, c1);
+        if (c0 >= c1) return;  // uniform
+        const unsigned long long best = chunk_best(c0, c1);
+        if (tid < 64) {
+            const uint32_t row = (uint32_t)(best & 0xFFFFFFFFu);
+            const float acc = wave_dist(row);
+            if (lane == 0) atomicMin(bsf, pack_key(acc, row));
+        }
+        return;
     }
+    // batched: the best key of every chunk of this block staged in LDS, then their real
+    // distances one row per wave at a time, one atomicMin per wave
+    const int v0 = (int)blockIdx.x * kSeedBatchChunks;
+    const int v1 = (v0 + kSeedBatchChunks < B.chunks) ? v0 + kSeedBatchChunks : B.chunks;
+    int nb = 0;
+    for (int v = v0; v < v1; ++v) {
+        long long c0, c1;
+        chunk_range(v, c0, c1);
+        if (c0 >= c1) continue;  // uniform
+        const unsigned long long best = chunk_best(c0, c1);
+        if (tid == 0) s_best[nb] = best;
+        ++nb;
+    }
+    __syncthreads();
+    unsigned long long mine = ~0ull;
+    for (int k = tid >> 6; k < nb; k += 4) {
+        const uint32_t row = (uint32_t)(s_best[k] & 0xFFFFFFFFu);
+        const unsigned long long key = pack_key(wave_dist(row), row);
+        mine = key < mine ? key : mine;
+    }
+    if (lane == 0 && mine != ~0ull) atomicMin(bsf, mine);
 }
 
 int seed_grid(const QueryArgs& a)
@@ -399,14 +449,16 @@ int seed_grid(const QueryArgs& a)
 
 hipError_t launch_prepare_seed(const QueryArgs& a, const float* q, hipStream_t st)
 {
-    SeedBatch none{nullptr, nullptr, nullptr, 0, 1, nullptr, nullptr};
+    SeedBatch none{nullptr, nullptr, nullptr, 0, 1, nullptr, nullptr, 0};
     k_prepare_seed<<<seed_grid(a), 256, (size_t)a.n * sizeof(float), st>>>(a, q, none);
     return hipGetLastError();
 }
 
-hipError_t launch_prepare_seed_batch(const QueryArgs& a, const SeedBatch& b, int n_queries, hipStream_t st)
+hipError_t launch_prepare_seed_batch(const QueryArgs& a, const SeedBatch& b_in, int n_queries, hipStream_t st)
 {
-    dim3 grid((unsigned)seed_grid(a), (unsigned)n_queries);
+    SeedBatch b = b_in;
+    b.chunks = seed_grid(a);
+    dim3 grid((unsigned)((b.chunks + kSeedBatchChunks - 1) / kSeedBatchChunks), (unsigned)n_queries);
     k_prepare_seed<<<grid, 256, (size_t)a.n * sizeof(float), st>>>(a, nullptr, b);
     return hipGetLastError();
 }

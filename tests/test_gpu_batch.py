@@ -265,6 +265,7 @@ def test_block_bound_prunes_and_changes_no_answer(oracle_native, monkeypatch):
     ri, rd, _ = oracle_native.nn_many(Q, X, threads=16)
     Xd, Qd = torch.from_numpy(X).cuda(), torch.from_numpy(Q).cuda()
     idx = paris.build(Xd)
+    monkeypatch.setenv("PARIS_SCREEN_SHAPE", "32,2,32")   # the same work items either way
     res = {}
     for flag in ("0", "1"):
         monkeypatch.setenv("PARIS_BLOCK_LB", flag)
