@@ -58,6 +58,7 @@ __device__ __forceinline__ unsigned long long pack_key_b(float d2, uint32_t idx)
 
 constexpr float kNoPass = -1.0e30f;  // bias of absent rows / columns: never >= 0
 constexpr int kCandStage = 512;      // screen candidates staged per block in LDS
+constexpr int kRescoreBlocks = 2048;  // re-score blocks (8 per CU: latency-bound row reads)
 
 // bfloat16 of a finite float32, rounded toward -inf
 __device__ __forceinline__ uint16_t to_bf16_down(float f)
@@ -906,15 +907,18 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs R)
     const uint32_t grp = (blockIdx.x * 256u + tid) >> 4;
     const uint32_t ngrp = gridDim.x * 16u;
     const int n = R.n, nv = n >> 2;
+    // the next candidate's entry is fetched while the current one is scored
+    uint2 e = grp < count ? R.cand[grp] : make_uint2(0u, 0u);
     for (uint32_t c = grp; c < count; c += ngrp) {
-        const uint2 e = R.cand[c];
-        BQuery& b = R.bq[e.x];
+        const uint2 cur = e;
+        if (c + ngrp < count) e = R.cand[c + ngrp];
+        BQuery& b = R.bq[cur.x];
         unsigned long long key = 0;
         if (l == 0) key = __hip_atomic_load(&b.bsf_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         key = __shfl(key, lane & ~15);
         const float thr = __double2float_ru((double)key_dist_b(key) * (1.0 + R.prune_rel) + 1e-25);
-        const float4* r4 = reinterpret_cast<const float4*>(R.X + (long long)e.y * n);
-        const float4* q4 = reinterpret_cast<const float4*>(R.Q + (long long)e.x * n);
+        const float4* r4 = reinterpret_cast<const float4*>(R.X + (long long)cur.y * n);
+        const float4* q4 = reinterpret_cast<const float4*>(R.Q + (long long)cur.x * n);
         float acc = 0.f;
         bool ab = false;
         for (int v0 = 0; v0 < nv; v0 += 16) {
@@ -930,7 +934,7 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs R)
         }
         if (l != 0) continue;
         R.cand_d2[c] = ab ? __builtin_inff() : acc;
-        if (!ab) atomicMin(&b.bsf_key, pack_key_b(acc, e.y));
+        if (!ab) atomicMin(&b.bsf_key, pack_key_b(acc, cur.y));
     }
 }
 
@@ -951,7 +955,7 @@ __global__ __launch_bounds__(256) void k_band(RescoreArgs R)
 
 hipError_t launch_rescore(const RescoreArgs& r, hipStream_t st)
 {
-    k_rescore<<<512, 256, 0, st>>>(r);
+    k_rescore<<<kRescoreBlocks, 256, 0, st>>>(r);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     k_band<<<256, 256, 0, st>>>(r);
