@@ -756,28 +756,54 @@ __global__ __launch_bounds__(256, 2) void k_screen32(ScreenArgs Sa)
 #pragma unroll
                             for (int i = 0; i < 16; ++i) m = fmaxf(m, acc[qs][sub][i]);
                     const bool hit = m >= 0.f;
-                    if (__ballot(hit) && hit) {
+                    if (__ballot(hit)) {
+                        // this lane's passing pairs as bits (qs S + sub) 16 + i, one LDS atomic per
+                        // wave for their slots (wave prefix sum), then each lane writes its own
+                        static_assert(QS * S * 16 <= 64, "one 64-bit mask per lane");
+                        unsigned long long bits = 0ull;
 #pragma unroll
                         for (int qs = 0; qs < QS; ++qs)
 #pragma unroll
                             for (int sub = 0; sub < S; ++sub)
 #pragma unroll
                                 for (int i = 0; i < 16; ++i) {
-                                    if (acc[qs][sub][i] >= 0.f) {
-                                        const int r = t * QT + qs * 32 + 8 * (i >> 2) + 4 * kh + (i & 3);
-                                        const long long p = xb0 + sub * 32 + col;
-                                        if (r < cnt && p < N) {
-                                            const uint2 c = make_uint2((uint32_t)query_of(r), series_of(p));
-                                            const uint32_t k = atomicAdd(&ccount, 1u);
-                                            if (k < (uint32_t)kCandStage) {
-                                                cbuf[k] = c;
-                                            } else {  // more than the stage holds in one tile
-                                                const uint32_t pos = atomicAdd(&Sa.hdr->n_cand, 1u);
-                                                if (pos < Sa.cand_cap) Sa.cand[pos] = c;
-                                            }
-                                        }
-                                    }
+                                    const int r = t * QT + qs * 32 + 8 * (i >> 2) + 4 * kh + (i & 3);
+                                    const long long p = xb0 + sub * 32 + col;
+                                    if (acc[qs][sub][i] >= 0.f && r < cnt && p < N)
+                                        bits |= 1ull << ((qs * S + sub) * 16 + i);
                                 }
+                        uint32_t xs[S];
+#pragma unroll
+                        for (int sub = 0; sub < S; ++sub) {
+                            const long long p = xb0 + sub * 32 + col;
+                            xs[sub] = (bits >> (sub * 16)) & 0xFFFFull || (QS > 1 && ((bits >> ((S + sub) * 16)) & 0xFFFFull))
+                                          ? series_of(p) : 0u;
+                        }
+                        const uint32_t nb = (uint32_t)__popcll(bits);
+                        uint32_t inc = nb;
+#pragma unroll
+                        for (int o = 1; o < 64; o <<= 1) {
+                            const uint32_t v = __shfl_up(inc, o);
+                            if (l >= o) inc += v;
+                        }
+                        uint32_t base = 0;
+                        if (l == 63) base = atomicAdd(&ccount, inc);
+                        base = __shfl(base, 63);
+                        uint32_t k = base + inc - nb;
+                        while (bits) {
+                            const int bi = __builtin_ctzll(bits);
+                            bits &= bits - 1ull;
+                            const int qs = bi / (S * 16), sub = (bi >> 4) % S, i = bi & 15;
+                            const int r = t * QT + qs * 32 + 8 * (i >> 2) + 4 * kh + (i & 3);
+                            const uint2 c = make_uint2((uint32_t)query_of(r), S == 1 || sub == 0 ? xs[0] : xs[S - 1]);
+                            if (k < (uint32_t)kCandStage) {
+                                cbuf[k] = c;
+                            } else {  // more than the stage holds in one tile
+                                const uint32_t pos = atomicAdd(&Sa.hdr->n_cand, 1u);
+                                if (pos < Sa.cand_cap) Sa.cand[pos] = c;
+                            }
+                            ++k;
+                        }
                     }
                 }
                 if (more) bias_store(NEXT, bias);
