@@ -75,19 +75,28 @@ __global__ __launch_bounds__(256) void k_l1_fwd(MlpNet net, const float* __restr
 }
 
 // ---- dW1 = G1^T P (float32 on the vector units) ----------------------------------------------
-__global__ __launch_bounds__(256) void k_l1_bwd(const float* __restrict__ G1, const float* __restrict__ P,
-                                                const int32_t* __restrict__ sel, int rows_real,
-                                                float* __restrict__ dW1)
+// dW1[j][i] = sum_r G1[r][j] P[sel(r)][i] (float32: the features enter unrounded). A block
+// takes 64 outputs (4 hidden units x 16 features); its 16 waves split the rows (wave w sums
+// rows w, w + 16, ...) and the 16 partial sums are added in wave order (deterministic).
+__global__ __launch_bounds__(1024) void k_l1_bwd(const float* __restrict__ G1, const float* __restrict__ P,
+                                                 const int32_t* __restrict__ sel, int rows_real,
+                                                 float* __restrict__ dW1)
 {
-    const int e = blockIdx.x * 256 + threadIdx.x;
-    if (e >= kMlpHid * kMlpIn) return;
-    const int j = e >> 4, i = e & 15;
+    __shared__ float part[16][64];
+    const int tid = threadIdx.x, o = tid & 63, rw = tid >> 6;
+    const int j = blockIdx.x * 4 + (o >> 4), i = o & 15;
     float acc = 0.f;
-    for (int r = 0; r < rows_real; ++r) {
+    for (int r = rw; r < rows_real; r += 16) {
         const long long pr = sel ? (long long)sel[r] : (long long)r;
         acc = acc + G1[(long long)r * kMlpHid + j] * P[pr * kMlpIn + i];
     }
-    dW1[e] = acc;
+    part[rw][o] = acc;
+    __syncthreads();
+    if (tid < 64) {
+        float t = 0.f;
+        for (int k = 0; k < 16; ++k) t = t + part[k][o];
+        dW1[j * kMlpIn + i] = t;
+    }
 }
 
 // ---- generic product on the MFMA: C[m][n] = sum_k A(m,k) B(n,k) ----------------------------
@@ -226,14 +235,25 @@ __global__ __launch_bounds__(256) void k_softmax_ce(const float* __restrict__ Z,
 }
 
 // ---- column sums (bias gradients) and the mean loss -----------------------------------------
-__global__ __launch_bounds__(256) void k_colsum(const float* __restrict__ G, int rows, int cols,
-                                                float* __restrict__ out)
+// Column sums of G [rows][cols] (bias gradients). A block takes 64 columns; its 16 waves
+// split the rows (wave w sums rows w, w + 16, ...) and the partial sums are added in wave
+// order, so the result does not depend on scheduling.
+__global__ __launch_bounds__(1024) void k_colsum(const float* __restrict__ G, int rows, int cols,
+                                                 float* __restrict__ out)
 {
-    const int c = blockIdx.x * 256 + threadIdx.x;
-    if (c >= cols) return;
+    __shared__ float part[16][64];
+    const int tid = threadIdx.x, cl = tid & 63, rw = tid >> 6;
+    const int c = blockIdx.x * 64 + cl;
     float acc = 0.f;
-    for (int r = 0; r < rows; ++r) acc += G[(long long)r * cols + c];
-    out[c] = acc;
+    if (c < cols)
+        for (int r = rw; r < rows; r += 16) acc += G[(long long)r * cols + c];
+    part[rw][cl] = acc;
+    __syncthreads();
+    if (tid < 64 && c < cols) {
+        float t = 0.f;
+        for (int k = 0; k < 16; ++k) t += part[k][cl];
+        out[c] = t;
+    }
 }
 
 __global__ __launch_bounds__(256) void k_mean_loss(const float* __restrict__ lr, int rows, float* __restrict__ out)
@@ -496,7 +516,7 @@ hipError_t launch_l1_fwd(const MlpNet& net, const float* P, const int32_t* sel, 
 hipError_t launch_l1_bwd(const float* G1, const float* P, const int32_t* sel, int rows_real, float* dW1,
                          hipStream_t st)
 {
-    k_l1_bwd<<<(kMlpHid * kMlpIn + 255) / 256, 256, 0, st>>>(G1, P, sel, rows_real, dW1);
+    k_l1_bwd<<<kMlpHid / 4, 1024, 0, st>>>(G1, P, sel, rows_real, dW1);
     return hipGetLastError();
 }
 
@@ -519,7 +539,7 @@ hipError_t launch_softmax_ce(const float* Z, int n_out, const int32_t* y, const 
 
 hipError_t launch_colsum(const float* G, int rows, int cols, float* out, hipStream_t st)
 {
-    k_colsum<<<(cols + 255) / 256, 256, 0, st>>>(G, rows, cols, out);
+    k_colsum<<<(cols + 63) / 64, 1024, 0, st>>>(G, rows, cols, out);
     return hipGetLastError();
 }
 
