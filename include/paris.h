@@ -212,6 +212,23 @@ paris_status paris_screen_dots(paris_index *idx, const float *queries_dev, int32
 paris_status paris_batch_screen_tiles(paris_index *idx, int64_t *tiles_run, int64_t *tiles_dense, int32_t reset);
 
 /*
+ * The block bound's alive bits for given thresholds (inspection and tests; the Section 3.3.1
+ * lower bound taken over the symbol envelope of a run of item_series consecutive sorted
+ * positions, 128 or 256):
+ *   queries_dev  float32 [n_queries][length] on the device, 16-byte aligned;
+ *   sqdist_dev   float32 [n_queries] on the device: U_q, each query's threshold as a squared
+ *                distance (it takes the place of the seed's distance);
+ *   bits_dev     uint64 [ceil(N / item_series)][ceil(n_queries / 64)] device out: bit q % 64 of
+ *                word (run, q / 64) is set iff the run's bound, in float64, is at most
+ *                U_q (1 + seed margin)(1 + prune margin) (both margins below 1e-4 relative);
+ *                non-finite queries have no bits.
+ * Needs an attached batch workspace (n_queries <= max_batch); overwrites its query buffers.
+ * Synchronous. Errors: PARIS_ESTATE (bad handle, no workspace), PARIS_EINVAL (arguments).
+ */
+paris_status paris_block_bound_bits(paris_index *idx, const float *queries_dev, const float *sqdist_dev,
+                                    int32_t n_queries, int32_t item_series, uint64_t *bits_dev, void *hip_stream);
+
+/*
  * Query summaries as the device computes them (Section 2.2 on the query; Section 3.3.1 table):
  *   info          host out (may be NULL).
  *   table_dev     optional device out float32 [16][256]: per-segment lower-bound terms

@@ -220,6 +220,22 @@ class Index:
                                                       1 if reset else 0), "paris_batch_screen_tiles")
         return int(run.value), int(dense.value)
 
+    def block_bound_bits(self, Q, sqdist, item_series: int = 256, stream=None):
+        """uint64 [ceil(N / item_series), ceil(M / 64)] alive bits of the screen's block bound for
+        queries Q (float32 [M, length]) with thresholds sqdist (float32 [M], squared distances)."""
+        torch = _torch()
+        qp = _dev_ptr(Q, torch.float32, 2, "queries")
+        up = _dev_ptr(sqdist, torch.float32, 1, "thresholds")
+        M = Q.shape[0]
+        if sqdist.shape[0] != M:
+            raise ValueError("one threshold per query")
+        out = torch.zeros(((self.n_series + item_series - 1) // item_series, (M + 63) // 64),
+                          dtype=torch.int64, device=Q.device)
+        check(load_library().paris_block_bound_bits(self._h, qp, up, int(M), int(item_series),
+                                                    ctypes.c_void_p(out.data_ptr()), _stream_ptr(stream)),
+              "paris_block_bound_bits")
+        return out
+
     def set_timing(self, enable: bool = True, scan_only: bool = False) -> None:
         """Enable HIP-event timing of query() (all three phases, or the scan only) and zero
         the totals."""

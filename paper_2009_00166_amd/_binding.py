@@ -69,6 +69,7 @@ SIGNATURES = [
     ("paris_batch_attach", ctypes.c_int, [_P, _P, ctypes.c_size_t, _I32, _P]),
     ("paris_screen_dots", ctypes.c_int, [_P, _P, _I32, _P, _P]),
     ("paris_batch_screen_tiles", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), _I32]),
+    ("paris_block_bound_bits", ctypes.c_int, [_P, _P, _P, _I32, _I32, _P, _P]),
     ("paris_set_timing", ctypes.c_int, [_P, _I32]),
     ("paris_get_timing", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     ("paris_get_batch_timing", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),

@@ -900,6 +900,36 @@ paris_status paris_screen_dots(paris_index* h, const float* queries_dev, int32_t
     return PARIS_OK;
 }
 
+paris_status paris_block_bound_bits(paris_index* h, const float* queries_dev, const float* sqdist_dev,
+                                    int32_t n_queries, int32_t item_series, uint64_t* bits_dev, void* hip_stream)
+{
+    if (!handle_ok(h)) return PARIS_ESTATE;
+    if (!h->bws || !h->screen_ok) return PARIS_ESTATE;
+    if (!queries_dev || !sqdist_dev || !bits_dev || n_queries < 1 || n_queries > h->max_batch ||
+        (item_series != 128 && item_series != 256) || reinterpret_cast<uintptr_t>(queries_dev) % 16 != 0)
+        return PARIS_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    const int m = n_queries;
+    const QueryArgs a = args_for(h);
+    SeedBatch sb;
+    sb.Q = reinterpret_cast<const float*>(h->bws + h->bp.qin);
+    sb.bq = bqs(h);
+    sb.qb = reinterpret_cast<uint16_t*>(h->bws + h->bp.qb);
+    sb.np = h->np;
+    sb.P = h->proj;
+    sb.leaves = nullptr;
+    sb.qpaa = reinterpret_cast<double*>(h->bws + h->bp.qpaa);
+    HIP_TRY(hipMemcpyAsync(h->bws + h->bp.qin, queries_dev, (size_t)m * h->n * 4, hipMemcpyDeviceToDevice, st));
+    HIP_TRY(launch_batch_init(bqs(h), m, bhdr(h), st));
+    HIP_TRY(launch_prepare_seed_batch(a, sb, m, st));   // query PAA (and a seed, replaced below)
+    HIP_TRY(launch_set_bsf(bqs(h), sqdist_dev, m, st));
+    ScreenArgs s = screen_args(h, m, nullptr, true);
+    s.mask = reinterpret_cast<unsigned long long*>(bits_dev);
+    HIP_TRY(launch_block_mask(s, ScreenShape{32, 0, item_series / 128, 32}, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    return PARIS_OK;
+}
+
 paris_status paris_batch_screen_tiles(paris_index* h, int64_t* tiles_run, int64_t* tiles_dense, int32_t reset)
 {
     if (!handle_ok(h)) return PARIS_ESTATE;

@@ -1051,6 +1051,20 @@ hipError_t launch_batch_init(BQuery* bq, int M, BatchHdr* hdr, hipStream_t st)
     return hipGetLastError();
 }
 
+// Inspection: a given squared distance per query as its best-so-far (series 0), in place of
+// the seed's.
+__global__ void k_set_bsf(BQuery* __restrict__ bq, const float* __restrict__ sqdist, int M)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q < M) bq[q].bsf_key = pack_key_b(sqdist[q], 0u);
+}
+
+hipError_t launch_set_bsf(BQuery* bq, const float* sqdist, int M, hipStream_t st)
+{
+    k_set_bsf<<<(M + 255) / 256, 256, 0, st>>>(bq, sqdist, M);
+    return hipGetLastError();
+}
+
 hipError_t launch_batch_thresholds(BQuery* bq, int M, float c_screen, double seed_rel, int P, hipStream_t st)
 {
     k_batch_thresholds<<<(M + 255) / 256, 256, 0, st>>>(bq, M, c_screen, seed_rel, P);

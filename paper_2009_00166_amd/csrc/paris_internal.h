@@ -193,6 +193,7 @@ hipError_t launch_block_env(const uint8_t* saxs, long long N, uint8_t* env, hipS
 int screen_item_series(ScreenShape shape);
 hipError_t launch_batch_init(BQuery* bq, int M, BatchHdr* hdr, hipStream_t st);
 hipError_t launch_batch_thresholds(BQuery* bq, int M, float c_screen, double seed_rel, int P, hipStream_t st);
+hipError_t launch_set_bsf(BQuery* bq, const float* sqdist, int M, hipStream_t st);
 // alive bits of the block bound (no launch when the shape or arguments do not use them)
 hipError_t launch_block_mask(const ScreenArgs& s, ScreenShape shape, hipStream_t st);
 hipError_t launch_screen(const ScreenArgs& s, int np, ScreenShape shape, hipStream_t st);

@@ -305,3 +305,46 @@ def test_block_bound_over_several_query_groups(shape, oracle_native, monkeypatch
     run, dense = idx.screen_tiles()
     assert 0 < run < dense
     idx.close()
+
+
+@pytest.mark.parametrize("item_series", [128, 256])
+def test_block_bound_bits_match_oracle(item_series, oracle_native):
+    """The block bound's alive bits against the oracle's run bound (block_lower_bound_sq over the
+    oracle's own leaf order, runs of 128 or 256 sorted positions with a ragged last run): every
+    pair clearly within its threshold is kept, every pair clearly beyond it is dropped; only
+    pairs within the kernel's margins (below 1e-4 relative) of the threshold may go either way.
+    Thresholds: 1.3 times each query's exact nearest squared distance."""
+    _need_gpu()
+    import paper_2009_00166_amd as paris
+    from oracle import reference as R
+    N, n, M = 20_000, 256, 100
+    X = synth.random_walks(N, n, seed=27)
+    Q, _, _ = synth.noisy_queries(X, M, seed=28, sigma=(0.01, 0.5))
+    _, rd, _ = oracle_native.nn_many(Q, X, threads=16)
+    U = (rd * 1.3).astype(np.float32)
+    idx = paris.build(torch.from_numpy(X).cuda())
+    idx.attach_batch(max_batch=128)
+    bits = idx.block_bound_bits(torch.from_numpy(Q).cuda(), torch.from_numpy(U).cuda(), item_series)
+    bits = bits.cpu().numpy().view(np.uint64)
+    n_items = (N + item_series - 1) // item_series
+    assert bits.shape == (n_items, 2)
+    perm, _ = R.sorted_order(R.isax(R.paa(X)))
+    syms = R.isax(R.paa(X))[perm]
+    L = n // 16
+    decided = kept = 0
+    for q in range(M):
+        qp = R.paa(Q[q])
+        for it in range(n_items):
+            lb = R.block_lower_bound_sq(qp, syms[it * item_series:(it + 1) * item_series], L)
+            g = int((int(bits[it, q >> 6]) >> (q & 63)) & 1)
+            if lb <= float(U[q]) * (1 - 1e-4):
+                assert g == 1, (q, it, lb, float(U[q]))
+                decided += 1
+                kept += 1
+            elif lb > float(U[q]) * (1 + 1e-3):
+                assert g == 0, (q, it, lb, float(U[q]))
+                decided += 1
+    assert decided >= 0.99 * M * n_items
+    assert 0 < kept < M * n_items            # the bound keeps some runs and drops others
+    assert np.all((bits[:, 1] >> np.uint64(M - 64)) == 0)   # no bits past the last query
+    idx.close()
