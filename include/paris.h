@@ -258,7 +258,9 @@ paris_status paris_lb_scan(paris_index *idx, const float *query_dev, float thres
  * around its kernels: [0] query summaries + approximate-search seed (+ the seed network),
  * [1] lower-bound scan, [2] refinement + float64 resolve. paris_lb_scan adds its scan time to
  * [1]. paris_set_timing(idx, 1) times all three phases, paris_set_timing(idx, 2) only the scan
- * (two events per query), 0 turns timing off; each call zeroes the totals. Events are read back
+ * (two events per query), paris_set_timing(idx, 3) only the scan of every 8th paris_query_exact
+ * call (a sample that leaves the other calls without event records), 0 turns timing off; each
+ * call zeroes the totals. Events are read back
  * one query late (two event sets alternate), so timing adds no synchronisation to a query.
  * paris_get_timing waits for the outstanding events and returns the summed milliseconds
  * (ms_out3[3]) and the number of timed calls.

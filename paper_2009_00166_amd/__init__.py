@@ -236,11 +236,11 @@ class Index:
               "paris_block_bound_bits")
         return out
 
-    def set_timing(self, enable: bool = True, scan_only: bool = False) -> None:
-        """Enable HIP-event timing of query() (all three phases, or the scan only) and zero
-        the totals."""
-        check(load_library().paris_set_timing(self._h, (2 if scan_only else 1) if enable else 0),
-              "paris_set_timing")
+    def set_timing(self, enable: bool = True, scan_only: bool = False, sampled: bool = False) -> None:
+        """Enable HIP-event timing of query() (all three phases, or the scan only; sampled: the
+        scan of every 8th query) and zero the totals."""
+        mode = (3 if sampled else 2 if scan_only else 1) if enable else 0
+        check(load_library().paris_set_timing(self._h, mode), "paris_set_timing")
 
     def timing(self):
         """(summed ms per phase [prepare+seed, lbscan, refine+resolve], timed calls)."""

@@ -164,7 +164,8 @@ struct paris_index {
     int refine_blocks;
     int refine_lanes;
     bool timing;
-    int timing_mode;        // paris_set_timing: 1 all three phases, 2 the scan only
+    int timing_mode;        // paris_set_timing: 1 all three phases, 2 the scan only, 3 the scan of every 8th call
+    long long timing_calls; // paris_query_exact calls since timing was set (mode 3 sampling)
     hipEvent_t ev[2][4];    // two event sets, used alternately: a set is read back one query later
     bool ev_pending[2];
     int ev_set;
@@ -1103,7 +1104,8 @@ paris_status paris_query_exact(paris_index* h, const float* query_dev, int64_t* 
     hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     volatile long long* flag = &h->host_res->idx;
     *flag = -2;  // overwritten by the resolve, last of the result's fields
-    paris_status s = run_query(h, query_dev, st, nullptr, nullptr, 0, h->timing, h->host_res_dev);
+    const bool timed = h->timing && (h->timing_mode != 3 || (h->timing_calls++ % kTimingEvery) == 0);
+    paris_status s = run_query(h, query_dev, st, nullptr, nullptr, 0, timed, h->host_res_dev);
     if (s != PARIS_OK) return s;
     // The result lands in mapped host memory: wait for it there (a stream synchronisation costs
     // a few microseconds more). Every 1024 polls the stream is asked whether it failed or
@@ -1251,7 +1253,7 @@ paris_status paris_lb_scan(paris_index* h, const float* query_dev, float thresho
 paris_status paris_set_timing(paris_index* h, int32_t enable)
 {
     if (!handle_ok(h)) return PARIS_ESTATE;
-    if (enable < 0 || enable > 2) return PARIS_EINVAL;
+    if (enable < 0 || enable > 3) return PARIS_EINVAL;
     if (enable && !h->ev[0][0]) {
         for (int set = 0; set < 2; ++set)
             for (int k = 0; k < 4; ++k) HIP_TRY(hipEventCreate(&h->ev[set][k]));
@@ -1259,6 +1261,7 @@ paris_status paris_set_timing(paris_index* h, int32_t enable)
     }
     h->timing = enable != 0;
     h->timing_mode = enable;
+    h->timing_calls = 0;
     h->ev_pending[0] = h->ev_pending[1] = false;
     h->ev_set = 0;
     for (int k = 0; k < 3; ++k) h->phase_ms[k] = 0.0;

@@ -274,6 +274,22 @@ def test_batch_equals_reference(small):
     assert st["lb_survivors"] >= 100
 
 
+@pytest.mark.parametrize("mode", ["all", "scan", "sampled"])
+def test_timing_modes_count_and_keep_answers(small, mode):
+    """Event timing (all phases, the scan of every query, the scan of every 8th query) changes
+    no answer and counts the calls it timed."""
+    idx = small["index"]
+    idx.set_timing(True, scan_only=(mode != "all"), sampled=(mode == "sampled"))
+    for m in range(40):
+        i, d = idx.query(small["Qd"][m])
+        _check_answer(i, d, small["ref_i"][m], small["ref_d2"][m])
+    ms, n = idx.timing()
+    idx.set_timing(False)
+    assert n == (5 if mode == "sampled" else 40)
+    assert ms[1] > 0.0
+    assert (ms[0] > 0.0) == (mode == "all")
+
+
 # ---------------------------------------------------------------------------------- errors
 def test_nonfinite_inputs_are_rejected():
     _need_gpu()
