@@ -189,17 +189,26 @@ hipError_t launch_block_env(const uint8_t* saxs, long long N, uint8_t* env, hipS
 }
 
 // Alive bits of every (work item of XB sorted positions, query): bit q % 64 of word
-// item * ceil(M / 64) + q / 64 is set iff the item's block bound, evaluated in float64, is at
-// most U_q (1 + prune_rel) (U_q as in k_batch_thresholds, before any projection). A query
-// without a threshold (non-finite, or no seed) has no bits. One thread per query (so a wave
-// ballot is one word); a block takes kMaskItems items, whose envelopes it stages in LDS as
-// region edges.
+// item * ceil(M / 64) + q / 64 is set unless the item's block bound provably exceeds
+// V_q = U_q (1 + seed_rel)(1 + prune_rel) (U_q the seed's squared distance, as in
+// k_batch_thresholds before any projection). A query without a threshold (non-finite, or no
+// seed) has no bits. One thread per query (so a wave ballot is one word); a block takes
+// kMaskItems items, whose envelopes it merges and stages in LDS.
+//
+// Arithmetic in float32, certified: region edges rounded outward (lower edge down, upper edge
+// up), the query's float64 segment means rounded to nearest (error at most u |p_s|, u = 2^-24),
+// gaps and their squares and the 16-term sum rounded to nearest. Then the computed bound B~
+// satisfies B~ <= (1 + e)(sqrt(B) + u sqrt(A))^2 (Cauchy-Schwarz on the cross term), with B
+// the exact bound over the widened intervals (at most the envelope's bound, hence at most
+// every member's distance), A = L sum_s p_s^2 and e = 24 u for the products, the sum and the
+// factor L. A pair is dropped only when B~ > T_q = RU((1 + e)(sqrt(V_q) + u sqrt(A))^2),
+// which implies B > V_q.
 constexpr int kMaskItems = 64;
 
 __global__ __launch_bounds__(256) void k_block_mask(ScreenArgs Sa, int XB)
 {
     __shared__ double beta[257];
-    __shared__ double s_lo[kMaskItems][kSeg], s_hi[kMaskItems][kSeg];
+    __shared__ float s_lo[kMaskItems][kSeg], s_hi[kMaskItems][kSeg];
     const int tid = threadIdx.x, lane = tid & 63;
     const int M = Sa.M, words = (M + 63) >> 6;
     const long long N = Sa.N;
@@ -221,34 +230,44 @@ __global__ __launch_bounds__(256) void k_block_mask(ScreenArgs Sa, int XB)
                 mx = max(mx, (uint32_t)Sa.env[run * 32 + 16 + sg]);
             }
         }
-        s_lo[ii][sg] = beta[mn];       // lower edge of the smallest symbol's region
-        s_hi[ii][sg] = beta[mx + 1];   // upper edge of the largest symbol's region
+        s_lo[ii][sg] = __double2float_rd(beta[mn]);       // lower edge of the smallest symbol, rounded down
+        s_hi[ii][sg] = __double2float_ru(beta[mx + 1]);   // upper edge of the largest symbol, rounded up
     }
     const int q = blockIdx.y * 256 + tid;
-    double pq[kSeg];
-    double thr = -1.0;   // no bit
+    float pq[kSeg];
+    float thr = -1.f;   // no bit
 #pragma unroll
-    for (int sg = 0; sg < kSeg; ++sg) pq[sg] = 0.0;
+    for (int sg = 0; sg < kSeg; ++sg) pq[sg] = 0.f;
     if (q < M) {
         const BQuery& b = Sa.bq[q];
         if (!b.err && b.bsf_key != kBsfInit) {
-            thr = ((double)key_dist_b(b.bsf_key) * (1.0 + Sa.seed_rel) + 1e-20) * (1.0 + Sa.prune_rel);
+            double A = 0.0;
 #pragma unroll
-            for (int sg = 0; sg < kSeg; ++sg) pq[sg] = Sa.qpaa[(long long)q * kSeg + sg];
+            for (int sg = 0; sg < kSeg; ++sg) {
+                const double p = Sa.qpaa[(long long)q * kSeg + sg];
+                pq[sg] = (float)p;
+                A = A + p * p;
+            }
+            A = A * Sa.seg_len;
+            const double u = 0x1p-24;
+            const double V = ((double)key_dist_b(b.bsf_key) * (1.0 + Sa.seed_rel) + 1e-20) * (1.0 + Sa.prune_rel);
+            const double r = sqrt(V) * (1.0 + 2.0 * u) + u * sqrt(A) * (1.0 + 2.0 * u);
+            thr = __double2float_ru((1.0 + 24.0 * u) * r * r * (1.0 + 4.0 * u));
         }
     }
+    const float L = (float)Sa.seg_len;
     __syncthreads();
     const int word = (blockIdx.y * 256 + (tid & ~63)) >> 6;
     for (int ii = 0; ii < kMaskItems; ++ii) {
         const long long item = it0 + ii;
         if (item >= n_items) break;   // uniform
-        double acc = 0.0;
+        float acc = 0.f;
 #pragma unroll
         for (int sg = 0; sg < kSeg; ++sg) {
-            const double g = fmax(fmax(s_lo[ii][sg] - pq[sg], pq[sg] - s_hi[ii][sg]), 0.0);
-            acc = fma(g, g, acc);
+            const float g = fmaxf(fmaxf(s_lo[ii][sg] - pq[sg], pq[sg] - s_hi[ii][sg]), 0.f);
+            acc = fmaf(g, g, acc);
         }
-        const bool alive = thr >= 0.0 && acc * Sa.seg_len <= thr;
+        const bool alive = thr >= 0.f && acc * L <= thr;
         const unsigned long long bits = __ballot(alive);
         if (lane == 0 && word < words) Sa.mask[item * words + word] = bits;
     }
