@@ -5,7 +5,7 @@ prepare -> approximate-search seed -> lower-bound scan -> early-abandoning refin
 resolve, one query at a time with its result back on the host), over an index built once before
 the timed region (the build time is reported beside). Inputs are resident in HBM before timing.
 
-Prints one JSON line. Options: --gpus N (only 1 is supported: this build measures one GPU),
+Prints one JSON line. Options: --gpus N (only 1 is supported: the benchmark measures one GPU),
 --steps K, --warmup W, --queries Q, --series N, --length n, --no-cpu-baseline, --no-batched,
 --batch B, --batch-steps K (the batched section: batches of B queries through paris_query_batch),
 --cold-queries C (the lower-bound scan timed with caches flushed before each of C queries),

@@ -24,7 +24,7 @@ The paper has no such network; its definition here is a build decision:
 Every rounding can be switched off (``rounding=False``): the result is then the exact float64
 gradient of the float64 loss, which the finite-difference pins in ``tests/test_oracle_mlp.py``
 check; bfloat16 rounding is pinned against torch's conversion, the loss and Adam against closed
-forms. The quality of the network's predictions is parity unpinned: it is judged only by the
+forms. The quality of the network's predictions is parity unpinned: it is assessed only by the
 seed's effect on the search (survivors, time), never by a stored value.
 """
 from __future__ import annotations
