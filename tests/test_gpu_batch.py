@@ -348,3 +348,23 @@ def test_block_bound_bits_match_oracle(item_series, oracle_native):
     assert 0 < kept < M * n_items            # the bound keeps some runs and drops others
     assert np.all((bits[:, 1] >> np.uint64(M - 64)) == 0)   # no bits past the last query
     idx.close()
+
+
+@pytest.mark.parametrize("N", [1, 5, 31, 33, 127, 129, 300, 1000])
+def test_batch_tiny_and_ragged_collections(N, oracle_native):
+    """Collections smaller than one symbol-envelope run, one work item or one tile, and sizes
+    just past those boundaries: the block bound's partial runs and items, the screen's partial
+    series tiles and the batched answers against the oracle."""
+    _need_gpu()
+    import paper_2009_00166_amd as paris
+    X = synth.random_walks(N, 256, seed=40 + N)
+    Q, _, _ = synth.noisy_queries(X, 37, seed=41, sigma=(0.01, 0.5))
+    Q = np.ascontiguousarray(np.concatenate([Q, synth.fresh_walk_queries(3, 256, seed=42)]))
+    ri, rd, _ = oracle_native.nn_many(Q, X, threads=16)
+    idx = paris.build(torch.from_numpy(X).cuda())
+    idx.attach_batch(max_batch=32)            # a full chunk and a partial one
+    I, D = idx.query_batch(torch.from_numpy(Q).cuda())
+    torch.cuda.synchronize()
+    assert np.array_equal(I.cpu().numpy(), ri)
+    assert np.array_equal(D.cpu().numpy(), np.sqrt(rd))
+    idx.close()
