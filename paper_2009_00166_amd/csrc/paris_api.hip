@@ -709,8 +709,8 @@ paris_status run_batch_chunk(paris_index* h, const float* queries, long long q0,
 // Screen autotuner: MFMA form (16x16x32 or 32x32x16) x query-tile height (32 or 64 rows) x
 // series per wave, every threshold at +inf (no candidate) and every pair screened (no block
 // bound: before the first batch there are no thresholds to bound against), timed over
-// full-size batches; the median of three runs decides. PARIS_SCREEN_SHAPE="qt,subs[,mfma]"
-// overrides. More than 256 dimensions always take the 32-wide form with one subtile per wave.
+// full-size batches; the median of three runs decides. PARIS_SCREEN_SHAPE="qt,subs[,mfma[,blocks
+// per CU]]" overrides. More than 256 dimensions always take the 32-wide form with one subtile per wave.
 paris_status tune_screen(paris_index* h, hipStream_t st)
 {
     const char* env = std::getenv("PARIS_SCREEN_SHAPE");
@@ -723,14 +723,15 @@ paris_status tune_screen(paris_index* h, hipStream_t st)
         return PARIS_OK;
     }
     if (env) {
-        int qt = 0, subs = 0, mf = 16;
-        const int got = std::sscanf(env, "%d,%d,%d", &qt, &subs, &mf);
+        int qt = 0, subs = 0, mf = 16, per_cu = 0;
+        const int got = std::sscanf(env, "%d,%d,%d,%d", &qt, &subs, &mf, &per_cu);
+        if (per_cu < 0 || per_cu > 8) per_cu = 0;
         if (got >= 2 && mf == 16 && (qt == 32 || qt == 64) && (subs == 2 || subs == 4)) {
-            h->screen = ScreenShape{qt, cus * (subs == 2 ? 2 : 1), subs, 16};
+            h->screen = ScreenShape{qt, cus * (per_cu ? per_cu : (subs == 2 ? 2 : 1)), subs, 16};
             return PARIS_OK;
         }
-        if (got == 3 && mf == 32 && (qt == 32 || qt == 64) && (subs == 1 || subs == 2)) {
-            h->screen = ScreenShape{qt, cus * (qt * subs > 64 ? 1 : 2), subs, 32};
+        if (got >= 3 && mf == 32 && (qt == 32 || qt == 64) && (subs == 1 || subs == 2)) {
+            h->screen = ScreenShape{qt, cus * (per_cu ? per_cu : (qt * subs > 64 ? 1 : 2)), subs, 32};
             return PARIS_OK;
         }
     }
