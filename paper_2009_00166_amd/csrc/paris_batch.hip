@@ -536,6 +536,7 @@ __global__ __launch_bounds__(256, SUBS == 2 ? 2 : 1) void k_screen(ScreenArgs S)
 template <int KS16, int QT, int S>
 __global__ __launch_bounds__(256, 2) void k_screen32(ScreenArgs Sa)
 {
+    static_assert(S == 1 || S == 2, "one or two 32-series subtiles per wave (the hit path picks between two)");
     constexpr int XW = 32 * S;          // series per wave (kept in registers)
     constexpr int XB = 4 * XW;          // series per work item (block)
     constexpr int NP = KS16 * 16;
