@@ -155,7 +155,9 @@ paris_status paris_query_exact(paris_index *idx, const float *query_dev, int64_t
  * once, and a query whose candidate or resolve buffers overflow is answered by the per-query
  * path. Without one, the queries run one after another through the per-query kernels and the
  * call is asynchronous unless stats is requested. A NaN/Inf query yields index -1 and distance
- * NaN. stats for the batched pipeline: lb_survivors = refined = screen survivors,
+ * NaN. stats for the batched pipeline: lb_survivors = screen survivors, refined = survivors
+ * whose rows the float32 re-score read (the others were skipped: their screened lower bound
+ * exceeded a certified upper bound on the query's nearest distance from the other survivors),
  * resolved = queries answered on the per-query fallback path.
  */
 paris_status paris_query_batch(paris_index *idx, const float *queries_dev, int64_t n_queries,

@@ -458,6 +458,10 @@ bool batch_screen_usable(const paris_index* h)
 BatchHdr* bhdr(paris_index* h) { return reinterpret_cast<BatchHdr*>(h->bws + h->bp.hdr); }
 BQuery* bqs(paris_index* h) { return reinterpret_cast<BQuery*>(h->bws + h->bp.bq); }
 
+// The screen's accumulators bound each candidate's distance (the re-score's skip test) when the
+// screen works on the series themselves (no projection) with the 32-wide form, which stores them.
+int candidate_bounds_on(const paris_index* h) { return h->proj == 1 && h->screen.mfma == 32 ? 1 : 0; }
+
 ScreenArgs screen_args(paris_index* h, int m, float* dump, bool masked = true)
 {
     ScreenArgs s;
@@ -468,6 +472,7 @@ ScreenArgs screen_args(paris_index* h, int m, float* dump, bool masked = true)
     s.bq = bqs(h);
     s.M = m;
     s.cand = reinterpret_cast<uint2*>(h->bws + h->bp.cand);
+    s.cand_d2 = reinterpret_cast<float*>(h->bws + h->bp.cand_d2);
     s.cand_cap = h->bp.cand_cap;
     s.hdr = bhdr(h);
     s.c_screen = h->c_screen;
@@ -497,6 +502,9 @@ RescoreArgs rescore_args(paris_index* h, int m)
     r.prune_rel = h->mg.prune_rel;
     r.band_rel = h->mg.band_rel;
     r.fallback = reinterpret_cast<uint32_t*>(h->bws + h->bp.fb);
+    r.ub_on = candidate_bounds_on(h);
+    r.c_screen = h->c_screen;
+    r.seed_rel = h->seed_rel;
     return r;
 }
 
@@ -662,7 +670,8 @@ paris_status capture_batch_graph(paris_index* h)
 }
 
 paris_status run_batch_chunk(paris_index* h, const float* queries, long long q0, int m, long long* out_idx,
-                             double* out_dist, hipStream_t st, long long* cands, long long* fallbacks)
+                             double* out_dist, hipStream_t st, long long* cands, long long* fallbacks,
+                             long long* rescored)
 {
     const size_t qbytes = (size_t)m * h->n * 4;
     HIP_TRY(hipMemcpyAsync(h->bws + h->bp.qin, queries + q0 * h->n, qbytes, hipMemcpyDeviceToDevice, st));
@@ -687,6 +696,7 @@ paris_status run_batch_chunk(paris_index* h, const float* queries, long long q0,
     }
     const BatchHdr hd = *h->host_hdr;
     *cands += hd.n_cand;
+    *rescored += hd.n_rescored;
     {
         const long long xb = screen_item_series(h->screen);
         h->tiles_run += hd.n_tiles;
@@ -787,16 +797,16 @@ paris_status batch_core(paris_index* h, const float* queries_dev, long long n_qu
                         double* nn_dist_dev, bool want_stats, paris_stats* agg, hipStream_t st)
 {
     if (batch_screen_usable(h)) {
-        long long cands = 0, fallbacks = 0;
+        long long cands = 0, fallbacks = 0, rescored = 0;
         for (long long q0 = 0; q0 < n_queries; q0 += h->max_batch) {
             const int m = (int)((n_queries - q0) < h->max_batch ? (n_queries - q0) : h->max_batch);
             paris_status s = run_batch_chunk(h, queries_dev, q0, m, reinterpret_cast<long long*>(nn_index_dev),
-                                             nn_dist_dev, st, &cands, &fallbacks);
+                                             nn_dist_dev, st, &cands, &fallbacks, &rescored);
             if (s != PARIS_OK) return s;
         }
         h->batch_candidates += cands;
         agg->lb_survivors += cands;
-        agg->refined += cands;
+        agg->refined += rescored;
         agg->resolved += fallbacks;
         return PARIS_OK;
     }
@@ -866,7 +876,8 @@ paris_status paris_batch_attach(paris_index* h, void* workspace_dev, size_t work
     if (launch_to_bf16(h->X, reinterpret_cast<const uint32_t*>(h->ws + h->plan.perm), h->N, h->n, h->np, h->proj,
                        reinterpret_cast<uint16_t*>(h->bws + h->bp.xb), reinterpret_cast<float*>(h->bws + h->bp.xn),
                        st) != hipSuccess ||
-        launch_block_env(h->ws + h->plan.saxs, h->N, h->bws + h->bp.env, st) != hipSuccess)
+        launch_block_env(h->ws + h->plan.saxs, h->N, h->bws + h->bp.env, st) != hipSuccess ||
+        launch_xn_max(reinterpret_cast<const float*>(h->bws + h->bp.xn), h->N, bhdr(h), st) != hipSuccess)
         s = PARIS_EHIP;
     if (s == PARIS_OK) s = tune_screen(h, st);
     if (s == PARIS_OK && hipStreamSynchronize(st) != hipSuccess) s = PARIS_EHIP;

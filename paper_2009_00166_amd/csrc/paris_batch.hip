@@ -286,7 +286,8 @@ __global__ void k_batch_init(BQuery* __restrict__ bq, int M, BatchHdr* __restric
         b.a = __builtin_inff();
         b.n_band = 0;
         b.err = 0;
-        b.n_cand = 0;
+        b.ub = 0u;   // largest survivor accumulator (bits) until k_query_ub
+        b.u_lo = 0.f;
     }
     if (q == 0) {
         hdr->next_item = 0;
@@ -294,6 +295,7 @@ __global__ void k_batch_init(BQuery* __restrict__ bq, int M, BatchHdr* __restric
         hdr->n_fallback = 0;
         hdr->flags = 0;
         hdr->n_tiles = 0;
+        hdr->n_rescored = 0;
     }
 }
 
@@ -309,6 +311,7 @@ __global__ void k_batch_thresholds(BQuery* __restrict__ bq, int M, float c_scree
     if (P > 1) U = U / (double)P * (1.0 + 0x1p-50);
     const double a = ((1.0 - (double)c_screen) * (double)b.qn - U) * 0.5;
     b.a = __double2float_rd(a);
+    b.u_lo = __double2float_rd(U);
 }
 
 // ------------------------------------------------------------------------------------------
@@ -536,7 +539,7 @@ __global__ __launch_bounds__(256, SUBS == 2 ? 2 : 1) void k_screen(ScreenArgs S)
 template <int KS16, int QT, int S>
 __global__ __launch_bounds__(256, 2) void k_screen32(ScreenArgs Sa)
 {
-    static_assert(S == 1 || S == 2, "one or two 32-series subtiles per wave (the hit path picks between two)");
+    static_assert(S == 1 || S == 2, "one or two 32-series subtiles per wave");
     constexpr int XW = 32 * S;          // series per wave (kept in registers)
     constexpr int XB = 4 * XW;          // series per work item (block)
     constexpr int NP = KS16 * 16;
@@ -565,16 +568,31 @@ __global__ __launch_bounds__(256, 2) void k_screen32(ScreenArgs Sa)
     __shared__ long long s_item;
     __shared__ uint2 cbuf[kCandStage];
     __shared__ uint32_t ccount, cbase;
+    // largest survivor accumulator of every query seen by this block (batches of at most
+    // kAmaxQueries; where two blocks per CU leave LDS room for it): gives the re-score a
+    // certified upper bound on the nearest distance
+    constexpr int LDS_BASE = 4 * QT * NP + 64 * QT + 2 * GROUP + 8 * kCandStage + 256;   // bytes
+    constexpr int AQ = LDS_BASE + 4 * kAmaxQueries <= 80 * 1024 - 512 ? kAmaxQueries : 1;
+    __shared__ uint32_t s_amax[AQ];
     const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
     if (tid == 0) ccount = 0;
+    const bool track = AQ > 1 && Sa.M <= AQ && Sa.dump == nullptr;
+    if (track)
+        for (int e = tid; e < Sa.M; e += 256) s_amax[e] = 0u;
+    // A candidate at list position pos: (query, series) and its accumulator truncated to the top
+    // 16 bits (so at most the accumulator), from which the re-score derives distance bounds.
+    // Staged entries carry (query | top 16 bits of the accumulator, sorted position).
+    auto store_cand = [&](uint32_t pos, uint32_t qa, uint32_t p) {
+        if (pos < Sa.cand_cap) {
+            Sa.cand[pos] = make_uint2(qa & 0xFFFFu, Sa.perm ? Sa.perm[p] : p);
+            Sa.cand_d2[pos] = __uint_as_float(qa & 0xFFFF0000u);
+        }
+    };
     auto flush_cands = [&]() {
         const uint32_t cnt = min(ccount, (uint32_t)kCandStage);
         if (tid == 0) cbase = atomicAdd(&Sa.hdr->n_cand, cnt);
         __syncthreads();
-        for (uint32_t k = tid; k < cnt; k += 256) {
-            const uint32_t pos = cbase + k;
-            if (pos < Sa.cand_cap) Sa.cand[pos] = cbuf[k];
-        }
+        for (uint32_t k = tid; k < cnt; k += 256) store_cand(cbase + k, cbuf[k].x, cbuf[k].y);
         __syncthreads();
         if (tid == 0) ccount = 0;
         __syncthreads();
@@ -792,13 +810,6 @@ __global__ __launch_bounds__(256, 2) void k_screen32(ScreenArgs Sa)
                                     if (acc[qs][sub][i] >= 0.f && r < cnt && p < N)
                                         bits |= 1ull << ((qs * S + sub) * 16 + i);
                                 }
-                        uint32_t xs[S];
-#pragma unroll
-                        for (int sub = 0; sub < S; ++sub) {
-                            const long long p = xb0 + sub * 32 + col;
-                            xs[sub] = (bits >> (sub * 16)) & 0xFFFFull || (QS > 1 && ((bits >> ((S + sub) * 16)) & 0xFFFFull))
-                                          ? series_of(p) : 0u;
-                        }
                         const uint32_t nb = (uint32_t)__popcll(bits);
                         uint32_t inc = nb;
 #pragma unroll
@@ -815,12 +826,22 @@ __global__ __launch_bounds__(256, 2) void k_screen32(ScreenArgs Sa)
                             bits &= bits - 1ull;
                             const int qs = bi / (S * 16), sub = (bi >> 4) % S, i = bi & 15;
                             const int r = t * QT + qs * 32 + 8 * (i >> 2) + 4 * kh + (i & 3);
-                            const uint2 c = make_uint2((uint32_t)query_of(r), S == 1 || sub == 0 ? xs[0] : xs[S - 1]);
+                            const long long p = xb0 + sub * 32 + col;
+                            float av = 0.f;   // the hit's accumulator (>= 0), selected without dynamic indexing
+#pragma unroll
+                            for (int qq = 0; qq < QS; ++qq)
+#pragma unroll
+                                for (int ss = 0; ss < S; ++ss)
+#pragma unroll
+                                    for (int ii = 0; ii < 16; ++ii)
+                                        if ((qq * S + ss) * 16 + ii == bi) av = acc[qq][ss][ii];
+                            const uint32_t qh = (uint32_t)query_of(r);
+                            if (track) atomicMax(&s_amax[qh], __float_as_uint(av));   // av >= 0: bits order as values
+                            const uint2 c = make_uint2(qh | (__float_as_uint(av) & 0xFFFF0000u), (uint32_t)p);
                             if (k < (uint32_t)kCandStage) {
                                 cbuf[k] = c;
                             } else {  // more than the stage holds in one tile
-                                const uint32_t pos = atomicAdd(&Sa.hdr->n_cand, 1u);
-                                if (pos < Sa.cand_cap) Sa.cand[pos] = c;
+                                store_cand(atomicAdd(&Sa.hdr->n_cand, 1u), c.x, c.y);
                             }
                             ++k;
                         }
@@ -840,6 +861,9 @@ __global__ __launch_bounds__(256, 2) void k_screen32(ScreenArgs Sa)
     }
     __syncthreads();
     if (ccount) flush_cands();
+    if (track)
+        for (int q = tid; q < Sa.M; q += 256)
+            if (s_amax[q]) atomicMax(&Sa.bq[q].ub, s_amax[q]);
 }
 
 template <int KS16>
@@ -946,6 +970,49 @@ __device__ __forceinline__ float group16_sum_b(float v)
     return v;
 }
 
+// Upper bound on every query's nearest squared distance from its screen survivors. A kept pair
+// with accumulator A has d^2 <= U_q - 2 A + 2 c (qn + xn) <= U_q - 2 A_max + 2 c (qn + xn_max)
+// for the query's largest survivor accumulator A_max (gathered by the screen) and the largest
+// series norm xn_max; evaluated in float64, rounded up, stored in place of A_max (+inf: none).
+__global__ void k_query_ub(RescoreArgs R)
+{
+    const int q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= R.M) return;
+    BQuery& b = R.bq[q];
+    const float amax = __uint_as_float(b.ub);
+    float ubf = __builtin_inff();
+    if (R.ub_on && amax > 0.f && !b.err && b.bsf_key != kBsfInit) {
+        const double xn_max = (double)__uint_as_float(R.hdr->xn_max);
+        const double U = (double)key_dist_b(b.bsf_key) * (1.0 + R.seed_rel) + 1e-20;
+        const double ub = (U - 2.0 * (double)amax + 2.0 * (double)R.c_screen * ((double)b.qn + xn_max)) * (1.0 + 0x1p-40);
+        if (ub >= 0.0) ubf = __double2float_ru(ub);
+    }
+    b.ub = __float_as_uint(ubf);
+}
+
+// Largest series squared norm of the screened copy (for the candidates' upper bounds).
+__global__ __launch_bounds__(256) void k_xn_max(const float* __restrict__ xn, long long N, uint32_t* __restrict__ out)
+{
+    float m = 0.f;
+    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < N; i += (long long)gridDim.x * 256)
+        m = fmaxf(m, xn[i]);
+    for (int off = 32; off > 0; off >>= 1) m = fmaxf(m, __shfl_xor(m, off));
+    if ((threadIdx.x & 63) == 0) atomicMax(out, __float_as_uint(m));   // non-negative: bits order as values
+}
+
+hipError_t launch_xn_max(const float* xn, long long N, BatchHdr* hdr, hipStream_t st)
+{
+    hipError_t e = hipMemsetAsync(&hdr->xn_max, 0, 4, st);
+    if (e != hipSuccess) return e;
+    long long blocks = (N + 255) / 256;
+    if (blocks > 2048) blocks = 2048;
+    k_xn_max<<<(unsigned)blocks, 256, 0, st>>>(xn, N, &hdr->xn_max);
+    return hipGetLastError();
+}
+
+// A candidate whose screened lower bound u_lo - 2 A (A: its accumulator, stored truncated, so
+// at most A (1 + 2^-7)) exceeds the query's certified upper bound ub is farther than the nearest
+// neighbour and is skipped without reading its row.
 __global__ __launch_bounds__(256) void k_rescore(RescoreArgs R)
 {
     const int tid = threadIdx.x, l = tid & 15, lane = tid & 63;
@@ -953,12 +1020,28 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs R)
     const uint32_t grp = (blockIdx.x * 256u + tid) >> 4;
     const uint32_t ngrp = gridDim.x * 16u;
     const int n = R.n, nv = n >> 2;
-    // the next candidate's entry is fetched while the current one is scored
+    uint32_t rescored = 0;
+    // the next candidate's entry (and screened accumulator) is fetched while the current one is scored
     uint2 e = grp < count ? R.cand[grp] : make_uint2(0u, 0u);
+    float ea = grp < count ? R.cand_d2[grp] : 0.f;
     for (uint32_t c = grp; c < count; c += ngrp) {
         const uint2 cur = e;
-        if (c + ngrp < count) e = R.cand[c + ngrp];
+        const float at = ea;
+        if (c + ngrp < count) {
+            e = R.cand[c + ngrp];
+            ea = R.cand_d2[c + ngrp];
+        }
         BQuery& b = R.bq[cur.x];
+        if (R.ub_on) {
+            // at keeps the top 16 bits of A, so A <= at(1 + 2^-7) when at > 0 and A <= at otherwise
+            const double a_hi = at > 0.f ? (double)at * (1.0 + 0x1p-7) : (double)at;
+            const double lb = (double)b.u_lo - 2.0 * a_hi;
+            if (lb > (double)__uint_as_float(b.ub)) {   // uniform in the group
+                if (l == 0) R.cand_d2[c] = __builtin_inff();
+                continue;
+            }
+        }
+        ++rescored;
         unsigned long long key = 0;
         if (l == 0) key = __hip_atomic_load(&b.bsf_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         key = __shfl(key, lane & ~15);
@@ -982,6 +1065,10 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs R)
         R.cand_d2[c] = ab ? __builtin_inff() : acc;
         if (!ab) atomicMin(&b.bsf_key, pack_key_b(acc, cur.y));
     }
+    // candidates read per block (lane 0 of every group counted its own)
+    uint32_t r = l == 0 ? rescored : 0u;
+    for (int off = 32; off > 0; off >>= 1) r += __shfl_xor(r, off);
+    if (lane == 0 && r) atomicAdd(&R.hdr->n_rescored, r);
 }
 
 __global__ __launch_bounds__(256) void k_band(RescoreArgs R)
@@ -1001,6 +1088,11 @@ __global__ __launch_bounds__(256) void k_band(RescoreArgs R)
 
 hipError_t launch_rescore(const RescoreArgs& r, hipStream_t st)
 {
+    k_query_ub<<<(r.M + 255) / 256, 256, 0, st>>>(r);
+    {
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     k_rescore<<<kRescoreBlocks, 256, 0, st>>>(r);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

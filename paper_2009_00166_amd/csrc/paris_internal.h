@@ -118,8 +118,10 @@ struct alignas(64) BQuery {
     float a;                       // screen threshold constant (see k_screen)
     uint32_t n_band;               // entries appended to band[] (may exceed kBandCap)
     uint32_t err;                  // kErrNonFinite
-    uint32_t n_cand;               // screen candidates of this query
-    uint32_t pad;
+    uint32_t ub;                   // float32 bits: the screen's largest survivor accumulator
+                                   // (atomicMax), then the certified upper bound on the nearest
+                                   // squared distance derived from it (+inf: none)
+    float u_lo;                    // the screen's threshold U_q, rounded down
     uint2 band[kBandCap];          // (index, ED^2 float32 bits) within the resolve band
 };
 
@@ -141,11 +143,14 @@ struct BatchHdr {
     uint32_t n_fallback;   // queries handed back to the per-query path
     uint32_t flags;
     uint32_t n_tiles;      // query tiles the screen ran (summed over its work items)
+    uint32_t n_rescored;   // candidates the re-score read rows for (the others were skipped)
+    uint32_t xn_max;       // float32 bits: largest series squared norm (set at attach, kept)
     uint32_t pad;
 };
 
 constexpr int kEnvRun = 32;          // sorted positions per stored symbol envelope
 constexpr int kScreenGroup = 4096;   // queries per alive list of the screen
+constexpr int kAmaxQueries = 4096;   // batch size up to which the screen gathers survivor maxima
 
 struct ScreenArgs {
     const uint16_t* Xb;    // [N][np] bfloat16 collection
@@ -155,6 +160,7 @@ struct ScreenArgs {
     BQuery* bq;
     int M;
     uint2* cand;           // (query, series)
+    float* cand_d2;        // per candidate: the screen's accumulator, truncated (re-score input)
     uint32_t cand_cap;
     BatchHdr* hdr;
     float c_screen;        // relative margin c of E = c (qn + xn)
@@ -179,6 +185,9 @@ struct RescoreArgs {
     BatchHdr* hdr;
     double prune_rel, band_rel;
     uint32_t* fallback;    // [M] queries to answer on the per-query path
+    int ub_on;             // skip candidates whose screened lower bound exceeds the query's ub
+    float c_screen;        // the screen's relative margin (for the candidates' upper bounds)
+    double seed_rel;
 };
 
 struct ScreenShape {
@@ -195,6 +204,7 @@ int screen_item_series(ScreenShape shape);
 hipError_t launch_batch_init(BQuery* bq, int M, BatchHdr* hdr, hipStream_t st);
 hipError_t launch_batch_thresholds(BQuery* bq, int M, float c_screen, double seed_rel, int P, hipStream_t st);
 hipError_t launch_set_bsf(BQuery* bq, const float* sqdist, int M, hipStream_t st);
+hipError_t launch_xn_max(const float* xn, long long N, BatchHdr* hdr, hipStream_t st);
 // alive bits of the block bound (no launch when the shape or arguments do not use them)
 hipError_t launch_block_mask(const ScreenArgs& s, ScreenShape shape, hipStream_t st);
 hipError_t launch_screen(const ScreenArgs& s, int np, ScreenShape shape, hipStream_t st);

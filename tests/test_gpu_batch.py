@@ -368,3 +368,26 @@ def test_batch_tiny_and_ragged_collections(N, oracle_native):
     assert np.array_equal(I.cpu().numpy(), ri)
     assert np.array_equal(D.cpu().numpy(), np.sqrt(rd))
     idx.close()
+
+
+def test_rescore_skips_candidates_beyond_the_screened_upper_bound(oracle_native):
+    """The re-score skips screen survivors whose screened lower bound exceeds the query's
+    certified upper bound from the other survivors (reported as refined < screen survivors),
+    and every answer stays the oracle's, hard queries and near-ties included."""
+    _need_gpu()
+    import paper_2009_00166_amd as paris
+    X = synth.random_walks(200_000, 256, seed=31)
+    for dst in (1000, 2000, 3000):
+        X[dst] = X[55]                                   # exact ties
+    Q1, _, _ = synth.noisy_queries(X, 300, seed=32, sigma=(0.2, 0.5))
+    Q = np.ascontiguousarray(np.concatenate([Q1, X[55:56], (X[55] + np.float32(1e-4)).astype(np.float32)[None, :]]))
+    ri, rd, _ = oracle_native.nn_many(Q, X, threads=16)
+    idx = paris.build(torch.from_numpy(X).cuda())
+    idx.attach_batch(max_batch=512)
+    I, D, st = idx.query_batch(torch.from_numpy(Q).cuda(), with_stats=True)
+    torch.cuda.synchronize()
+    assert np.array_equal(I.cpu().numpy(), ri)
+    assert np.array_equal(D.cpu().numpy(), np.sqrt(rd))
+    print(f"screen survivors {st['lb_survivors']}, re-scored {st['refined']}")
+    assert 0 < st["refined"] < st["lb_survivors"]
+    idx.close()
