@@ -168,16 +168,19 @@ def main() -> int:
         step(record=(w == 0))
         log(f"warmup step {w + 1}/{args.warmup} done")
 
-    # timed region: HIP events around the scan kernel of every 8th query (read back one timed
-    # query late; the other queries run without event records)
+    # timed region: a start and a stop HIP event bound to the scan kernel's dispatch in every 8th
+    # query (read back one timed query late; the other queries run without events)
     index.set_timing(True, scan_only=True, sampled=True)
     torch.cuda.synchronize()
+    w0 = time.clock_gettime_ns(time.CLOCK_MONOTONIC)
     t1 = time.perf_counter()
     for k in range(args.steps):
         step(record=False)
         log(f"timed step {k + 1}/{args.steps} done")
     torch.cuda.synchronize()
     elapsed = time.perf_counter() - t1
+    # the window in CLOCK_MONOTONIC nanoseconds, to pick this region's launches out of a trace
+    log(f"timed window monotonic ns {w0} {time.clock_gettime_ns(time.CLOCK_MONOTONIC)}")
     scan_ms, timed = index.timing()
     # one more pass, outside the timed region, with events around all three phases
     index.set_timing(True)
@@ -219,8 +222,10 @@ def main() -> int:
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": measured_traffic("k_lbscan"),
                      "bytes_per_launch": lb_bytes, "avg_launch_ms": lb_ms,
-                     "note": "16 B of iSAX word per series per launch; the 160 MB array fits the "
-                             "256 MB Infinity Cache, so back-to-back scans can exceed HBM rate"},
+                     "note": "16 B of iSAX word per series per launch; avg_launch_ms from HIP start/stop "
+                             "events bound to the scan kernel's dispatch (every 8th query of the timed "
+                             "region); phases_ms_per_query.lbscan adds the dispatch gap before the "
+                             "kernel; the 160 MB array fits the 256 MB Infinity Cache"},
         "lbscan_cold": cold,
         "phases_ms_per_query": dict(zip(["prepare_seed", "lbscan", "refine_resolve"],
                                         [p / max(phased, 1) for p in phase_ms])),
@@ -251,15 +256,15 @@ def cold_scan_section(index, rows, N, args):
     """The lower-bound scan with nothing of the iSAX array left in any cache: before each query
     a 1 GiB buffer is read (one reduction kernel), which replaces the contents of the 256 MB
     Infinity Cache and of the L2s with clean lines of that buffer, as the refinement's row reads
-    would in a long-running service. The per-phase HIP events then time the scan straight from
-    HBM. (A flush that writes leaves dirty lines behind, whose write-back the scan would then pay
+    would in a long-running service. HIP events bound to the scan kernel's dispatch then time
+    the scan straight from HBM. (A flush that writes leaves dirty lines behind, whose write-back the scan would then pay
     for.) The fill kernel (1 GiB written once) and the reduction (1 GiB read) are also the
     known-size references for the HBM byte counters."""
     import torch
     flush = torch.empty(1 << 28, dtype=torch.float32, device="cuda")   # 1 GiB
     flush.fill_(1.0)
     K = min(args.cold_queries, len(rows))
-    index.set_timing(True)
+    index.set_timing(True, scan_only=True)    # events bound to the scan kernel's dispatch
     for m in range(K):
         flush.sum()
         index.query(rows[m])

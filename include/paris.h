@@ -256,13 +256,15 @@ paris_status paris_lb_scan(paris_index *idx, const float *query_dev, float thres
                            void *hip_stream);
 
 /*
- * Per-phase device timing of paris_query_exact, with HIP events recorded on the call's stream
- * around its kernels: [0] query summaries + approximate-search seed (+ the seed network),
- * [1] lower-bound scan, [2] refinement + float64 resolve. paris_lb_scan adds its scan time to
- * [1]. paris_set_timing(idx, 1) times all three phases, paris_set_timing(idx, 2) only the scan
- * (two events per query), paris_set_timing(idx, 3) only the scan of every 8th paris_query_exact
- * call (a sample that leaves the other calls without event records), 0 turns timing off; each
- * call zeroes the totals. Events are read back
+ * Per-phase device timing of paris_query_exact, with HIP events on the call's stream:
+ * [0] query summaries + approximate-search seed (+ the seed network), [1] lower-bound scan,
+ * [2] refinement + float64 resolve. paris_set_timing(idx, 1) times all three phases with events
+ * recorded between them (each phase then includes the dispatch gap before its first kernel);
+ * paris_set_timing(idx, 2) times only the scan, with a start and a stop event bound to the scan
+ * kernel's own dispatch (its start-to-end duration); paris_set_timing(idx, 3) does the same for
+ * the scan of every 8th paris_query_exact call (a sample that leaves the other calls without
+ * events); 0 turns timing off; each call zeroes the totals. With timing on, paris_lb_scan adds
+ * its scan kernel's duration (events bound to its dispatch) to [1]. Events are read back
  * one query late (two event sets alternate), so timing adds no synchronisation to a query.
  * paris_get_timing waits for the outstanding events and returns the summed milliseconds
  * (ms_out3[3]) and the number of timed calls.

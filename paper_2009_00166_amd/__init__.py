@@ -237,8 +237,9 @@ class Index:
         return out
 
     def set_timing(self, enable: bool = True, scan_only: bool = False, sampled: bool = False) -> None:
-        """Enable HIP-event timing of query() (all three phases, or the scan only; sampled: the
-        scan of every 8th query) and zero the totals."""
+        """Enable HIP-event timing of query() and zero the totals: all three phases (events
+        between them), or the scan kernel alone (events bound to its dispatch; sampled: the scan
+        of every 8th query)."""
         mode = (3 if sampled else 2 if scan_only else 1) if enable else 0
         check(load_library().paris_set_timing(self._h, mode), "paris_set_timing")
 

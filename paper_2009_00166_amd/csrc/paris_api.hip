@@ -326,9 +326,12 @@ paris_status run_query(paris_index* h, const float* q, hipStream_t st, long long
         a.learned_cpl = learned_chunks(h);
     }
     HIP_TRY(launch_prepare_seed(a, q, st));
-    if (timed) HIP_TRY(hipEventRecord(ev[1], st));
-    HIP_TRY(launch_lbscan(a, -1.f, h->scan, st));
-    if (timed) HIP_TRY(hipEventRecord(ev[2], st));
+    // all phases: events recorded between the phases (each phase includes the gap before its
+    // first kernel); the scan alone: events bound to the scan kernel's dispatch
+    if (timed && all) HIP_TRY(hipEventRecord(ev[1], st));
+    const bool bind = timed && !all;
+    HIP_TRY(launch_lbscan(a, -1.f, h->scan, st, bind ? ev[1] : nullptr, bind ? ev[2] : nullptr));
+    if (timed && all) HIP_TRY(hipEventRecord(ev[2], st));
     HIP_TRY(launch_refine_resolve(a, q, out_idx, out_dist, qi, st));
     if (timed && all) HIP_TRY(hipEventRecord(ev[3], st));
     if (timed) {
@@ -1234,9 +1237,8 @@ paris_status paris_lb_scan(paris_index* h, const float* query_dev, float thresho
         if (ps != PARIS_OK) return ps;
     }
     HIP_TRY(launch_prepare_seed(a, query_dev, st));
-    if (h->timing) HIP_TRY(hipEventRecord(h->ev[0][1], st));
-    HIP_TRY(launch_lbscan(a, threshold_sq, h->scan, st));
-    if (h->timing) HIP_TRY(hipEventRecord(h->ev[0][2], st));
+    HIP_TRY(launch_lbscan(a, threshold_sq, h->scan, st, h->timing ? h->ev[0][1] : nullptr,
+                          h->timing ? h->ev[0][2] : nullptr));
     HIP_TRY(hipMemcpyAsync(h->host_qs, a.qs, sizeof(QState), hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
     const QState& q = *h->host_qs;

@@ -309,7 +309,10 @@ hipError_t launch_touch(const void* p, size_t bytes, uint32_t* sink, hipStream_t
 hipError_t launch_prepare_seed(const QueryArgs& a, const float* q, hipStream_t st);
 hipError_t launch_prepare_seed_batch(const QueryArgs& a, const SeedBatch& b, int n_queries, hipStream_t st);
 // threshold_sq < 0: use the best-so-far in QState; otherwise a fixed threshold.
-hipError_t launch_lbscan(const QueryArgs& a, float threshold_sq, ScanShape shape, hipStream_t st);
+// ev_start / ev_stop (optional): HIP events bound to the scan kernel's own dispatch, so that
+// their elapsed time is the kernel's start-to-end duration without the gaps around it.
+hipError_t launch_lbscan(const QueryArgs& a, float threshold_sq, ScanShape shape, hipStream_t st,
+                         hipEvent_t ev_start = nullptr, hipEvent_t ev_stop = nullptr);
 // refinement; its last block resolves in float64, writes the result (and element qi of
 // out_idx / out_dist when they are not null) and resets the state for the next query.
 hipError_t launch_refine_resolve(const QueryArgs& a, const float* q, long long* out_idx, double* out_dist,

@@ -3,6 +3,8 @@
 // resolve in its last block.
 #include "paris_internal.h"
 
+#include <hip/hip_ext.h>
+
 namespace paris {
 
 static __constant__ double c_beta[256] = {
@@ -597,17 +599,25 @@ hipError_t launch_touch(const void* p, size_t bytes, uint32_t* sink, hipStream_t
 }
 
 template <int U, int BS>
-static hipError_t launch_scan_t(const QueryArgs& a, float thr, int per_cu, int cus, hipStream_t st)
+static hipError_t launch_scan_t(const QueryArgs& a, float thr, int per_cu, int cus, hipStream_t st,
+                                hipEvent_t e0, hipEvent_t e1)
 {
     const long long need = (a.N + (long long)BS * U - 1) / ((long long)BS * U);
     long long grid = (long long)cus * (per_cu > 0 ? per_cu : 4);
     if (grid > need) grid = need;
     if (grid < 1) grid = 1;
+    if (e0 || e1) {
+        QueryArgs ka = a;
+        void* args[] = {&ka, &thr};
+        return hipExtLaunchKernel(reinterpret_cast<const void*>(&k_lbscan<U, BS>), dim3((unsigned)grid),
+                                  dim3(BS), args, 0, st, e0, e1, 0);
+    }
     k_lbscan<U, BS><<<(unsigned)grid, BS, 0, st>>>(a, thr);
     return hipGetLastError();
 }
 
-hipError_t launch_lbscan(const QueryArgs& a, float threshold_sq, ScanShape shape, hipStream_t st)
+hipError_t launch_lbscan(const QueryArgs& a, float threshold_sq, ScanShape shape, hipStream_t st,
+                         hipEvent_t e0, hipEvent_t e1)
 {
     static int cus = 0;
     if (cus == 0) {
@@ -618,13 +628,13 @@ hipError_t launch_lbscan(const QueryArgs& a, float threshold_sq, ScanShape shape
     }
     const bool wide = shape.threads == 512;
     if (shape.unroll == 8)
-        return wide ? launch_scan_t<8, 512>(a, threshold_sq, shape.per_cu, cus, st)
-                    : launch_scan_t<8, 256>(a, threshold_sq, shape.per_cu, cus, st);
+        return wide ? launch_scan_t<8, 512>(a, threshold_sq, shape.per_cu, cus, st, e0, e1)
+                    : launch_scan_t<8, 256>(a, threshold_sq, shape.per_cu, cus, st, e0, e1);
     if (shape.unroll == 2)
-        return wide ? launch_scan_t<2, 512>(a, threshold_sq, shape.per_cu, cus, st)
-                    : launch_scan_t<2, 256>(a, threshold_sq, shape.per_cu, cus, st);
-    return wide ? launch_scan_t<4, 512>(a, threshold_sq, shape.per_cu, cus, st)
-                : launch_scan_t<4, 256>(a, threshold_sq, shape.per_cu, cus, st);
+        return wide ? launch_scan_t<2, 512>(a, threshold_sq, shape.per_cu, cus, st, e0, e1)
+                    : launch_scan_t<2, 256>(a, threshold_sq, shape.per_cu, cus, st, e0, e1);
+    return wide ? launch_scan_t<4, 512>(a, threshold_sq, shape.per_cu, cus, st, e0, e1)
+                : launch_scan_t<4, 256>(a, threshold_sq, shape.per_cu, cus, st, e0, e1);
 }
 
 // ------------------------------------------------------------------------------------------

@@ -89,3 +89,29 @@ def test_batched_pipeline_at_scale(full, oracle_native):
     ref = np.sqrt(rd)
     assert np.all(np.abs(D.cpu().numpy() - ref) <= 1e-5 * ref)
     print(f"[scale] batched: {st['lb_survivors']} screen survivors, {st['resolved']} fallbacks", flush=True)
+
+
+def test_full_batch_at_scale(full, oracle_native):
+    """One whole batch of 4096 uneven-difficulty queries at 10M x 256, the batch size and tuned
+    launch shape the benchmark times: the brute-force oracle's answers on a sample of 32 of its
+    queries; for every query, the returned distance is bit-identical to the oracle's float64
+    distance to the returned series and no larger than the distance to the series the query was
+    made from."""
+    X, index = full["X"], full["index"]
+    index.attach_batch(max_batch=4096)
+    M = 4096
+    Q, src, _ = synth.noisy_queries(X, M, seed=3, sigma=(0.01, 0.5))
+    I, D, st = index.query_batch(torch.from_numpy(Q).cuda(), with_stats=True)
+    torch.cuda.synchronize()
+    I, D = I.cpu().numpy(), D.cpu().numpy()
+    pick = np.sort(np.random.default_rng(3).choice(M, 32, replace=False))
+    ri, rd, _ = oracle_native.nn_many(Q[pick], X, threads=16)
+    assert np.array_equal(I[pick], ri)
+    assert np.array_equal(D[pick], np.sqrt(rd))
+    assert np.all((I >= 0) & (I < N_FULL))
+    for m in range(M):
+        d_ret, d_src = oracle_native.ed2_at(Q[m], X, [I[m], src[m]])
+        assert D[m] == math.sqrt(d_ret), m
+        assert d_ret <= d_src, m
+    print(f"[scale] full batch: {st['lb_survivors']} screen survivors, {st['refined']} re-scored, "
+          f"{st['resolved']} fallbacks", flush=True)
