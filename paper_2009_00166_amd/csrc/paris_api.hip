@@ -508,6 +508,8 @@ RescoreArgs rescore_args(paris_index* h, int m)
     r.ub_on = candidate_bounds_on(h);
     r.c_screen = h->c_screen;
     r.seed_rel = h->seed_rel;
+    r.lb_on = h->screen.mfma == 32 ? 1 : 0;   // only the 32-wide screen stores accumulators
+    r.P = h->proj;
     return r;
 }
 

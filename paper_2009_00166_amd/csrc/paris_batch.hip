@@ -59,6 +59,7 @@ __device__ __forceinline__ unsigned long long pack_key_b(float d2, uint32_t idx)
 constexpr float kNoPass = -1.0e30f;  // bias of absent rows / columns: never >= 0
 constexpr int kCandStage = 512;      // screen candidates staged per block in LDS
 constexpr int kRescoreBlocks = 2048;  // re-score blocks (8 per CU: latency-bound row reads)
+constexpr int kHeadBlocks = 1024;     // head-pass blocks (one lane per candidate test)
 
 // bfloat16 of a finite float32, rounded toward -inf
 __device__ __forceinline__ uint16_t to_bf16_down(float f)
@@ -983,7 +984,9 @@ __global__ void k_query_ub(RescoreArgs R)
     float ubf = __builtin_inff();
     if (R.ub_on && amax > 0.f && !b.err && b.bsf_key != kBsfInit) {
         const double xn_max = (double)__uint_as_float(R.hdr->xn_max);
-        const double U = (double)key_dist_b(b.bsf_key) * (1.0 + R.seed_rel) + 1e-20;
+        // U_q from its rounded-down copy (u_lo <= U_q < u_lo (1 + 2^-23)); the best-so-far may
+        // already be lower than the seed the screen's thresholds came from (head pass)
+        const double U = (double)b.u_lo * (1.0 + 0x1p-23);
         const double ub = (U - 2.0 * (double)amax + 2.0 * (double)R.c_screen * ((double)b.qn + xn_max)) * (1.0 + 0x1p-40);
         if (ub >= 0.0) ubf = __double2float_ru(ub);
     }
@@ -1032,20 +1035,23 @@ __global__ __launch_bounds__(256) void k_rescore(RescoreArgs R)
             ea = R.cand_d2[c + ngrp];
         }
         BQuery& b = R.bq[cur.x];
-        if (R.ub_on) {
-            // at keeps the top 16 bits of A, so A <= at(1 + 2^-7) when at > 0 and A <= at otherwise
-            const double a_hi = at > 0.f ? (double)at * (1.0 + 0x1p-7) : (double)at;
-            const double lb = (double)b.u_lo - 2.0 * a_hi;
-            if (lb > (double)__uint_as_float(b.ub)) {   // uniform in the group
-                if (l == 0) R.cand_d2[c] = __builtin_inff();
-                continue;
-            }
+        // at keeps the top 16 bits of A, so A <= at(1 + 2^-7) when at > 0 and A <= at otherwise;
+        // P (u_lo - 2 A) <= P d_P^2 <= d^2 (d_P: the screened, projected distance)
+        const double a_hi = at > 0.f ? (double)at * (1.0 + 0x1p-7) : (double)at;
+        const double lb = (double)b.u_lo - 2.0 * a_hi;
+        if (R.ub_on && lb > (double)__uint_as_float(b.ub)) {   // uniform in the group
+            if (l == 0) R.cand_d2[c] = __builtin_inff();
+            continue;
         }
-        ++rescored;
         unsigned long long key = 0;
         if (l == 0) key = __hip_atomic_load(&b.bsf_key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         key = __shfl(key, lane & ~15);
         const float thr = __double2float_ru((double)key_dist_b(key) * (1.0 + R.prune_rel) + 1e-25);
+        if (R.lb_on && (double)R.P * lb * (1.0 - 0x1p-40) > (double)thr) {   // as an abandon at 0 points
+            if (l == 0) R.cand_d2[c] = __builtin_inff();
+            continue;
+        }
+        ++rescored;
         const float4* r4 = reinterpret_cast<const float4*>(R.X + (long long)cur.y * n);
         const float4* q4 = reinterpret_cast<const float4*>(R.Q + (long long)cur.x * n);
         float acc = 0.f;
@@ -1086,8 +1092,54 @@ __global__ __launch_bounds__(256) void k_band(RescoreArgs R)
     }
 }
 
+// Head pass (before the re-score): every survivor whose truncated accumulator equals the top 16
+// bits of its query's largest one (the smallest screened lower bound; usually the nearest
+// neighbour) gets its float32 distance computed by one wave and folded into the query's
+// best-so-far, so that the re-score's thresholds start near the answer. One lane per candidate
+// tests; the wave then scores the hits one after another (a few per query).
+__global__ __launch_bounds__(256) void k_heads(RescoreArgs R)
+{
+    const int lane = threadIdx.x & 63;
+    const uint32_t count = min(R.hdr->n_cand, R.cand_cap);
+    const uint32_t wid = (blockIdx.x * 256u + threadIdx.x) >> 6, nw = gridDim.x * 4u;
+    const int nv = R.n >> 2;
+    for (uint32_t c0 = wid * 64u; c0 < count; c0 += nw * 64u) {
+        const uint32_t c = c0 + (uint32_t)lane;
+        bool hit = false;
+        uint2 e = make_uint2(0u, 0u);
+        if (c < count) {
+            const float at = R.cand_d2[c];
+            if (at > 0.f) {
+                e = R.cand[c];
+                hit = (R.bq[e.x].ub & 0xFFFF0000u) == __float_as_uint(at);
+            }
+        }
+        unsigned long long m = __ballot(hit);
+        while (m) {
+            const int src = __ffsll((long long)m) - 1;
+            m &= m - 1ull;
+            const uint32_t qx = __shfl(e.x, src), row = __shfl(e.y, src);
+            const float4* r4 = reinterpret_cast<const float4*>(R.X + (long long)row * R.n);
+            const float4* q4 = reinterpret_cast<const float4*>(R.Q + (long long)qx * R.n);
+            float part = 0.f;
+            for (int v = lane; v < nv; v += 64) {
+                const float4 a = r4[v], bq = q4[v];
+                const float dx = bq.x - a.x, dy = bq.y - a.y, dz = bq.z - a.z, dw = bq.w - a.w;
+                part += (dx * dx + dy * dy) + (dz * dz + dw * dw);
+            }
+            for (int off = 32; off > 0; off >>= 1) part += __shfl_xor(part, off);
+            if (lane == 0) atomicMin(&R.bq[qx].bsf_key, pack_key_b(part, row));
+        }
+    }
+}
+
 hipError_t launch_rescore(const RescoreArgs& r, hipStream_t st)
 {
+    if (r.lb_on) {
+        k_heads<<<kHeadBlocks, 256, 0, st>>>(r);
+        const hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
     k_query_ub<<<(r.M + 255) / 256, 256, 0, st>>>(r);
     {
         const hipError_t e = hipGetLastError();

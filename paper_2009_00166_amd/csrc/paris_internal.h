@@ -188,6 +188,8 @@ struct RescoreArgs {
     int ub_on;             // skip candidates whose screened lower bound exceeds the query's ub
     float c_screen;        // the screen's relative margin (for the candidates' upper bounds)
     double seed_rel;
+    int lb_on;             // cand_d2 holds screen accumulators: head pass + lower-bound pre-check
+    int P;                 // segment length of the screen's projection (1: the series itself)
 };
 
 struct ScreenShape {
