@@ -158,6 +158,8 @@ def test_long_series_screened_on_segment_means(n, oracle_native):
     assert np.array_equal(I.cpu().numpy(), ri)
     assert np.array_equal(D.cpu().numpy(), np.sqrt(rd))
     assert st["lb_survivors"] < 0.2 * N * len(Q)      # the projected screen prunes most pairs
+    assert st["refined"] <= st["lb_survivors"]
+    print(f"n={n}: screen survivors {st['lb_survivors']}, rows re-scored {st['refined']}", flush=True)
     idx.close()
 
 
