@@ -157,8 +157,9 @@ paris_status paris_query_exact(paris_index *idx, const float *query_dev, int64_t
  * call is asynchronous unless stats is requested. A NaN/Inf query yields index -1 and distance
  * NaN. stats for the batched pipeline: lb_survivors = screen survivors, refined = survivors
  * whose rows the float32 re-score read (the others were skipped: their screened lower bound
- * exceeded a certified upper bound on the query's nearest distance from the other survivors),
- * resolved = queries answered on the per-query fallback path.
+ * exceeded a certified upper bound on the query's nearest distance from the other survivors,
+ * or the re-score's running threshold after the head pass had scored the survivors with the
+ * largest screen accumulators), resolved = queries answered on the per-query fallback path.
  */
 paris_status paris_query_batch(paris_index *idx, const float *queries_dev, int64_t n_queries,
                                int64_t *nn_index_dev, double *nn_dist_dev, paris_stats *stats,
