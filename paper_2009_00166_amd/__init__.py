@@ -25,10 +25,18 @@ def _torch():
     return torch
 
 
-def _stream_ptr(stream=None):
+def _current_stream(device_index=None) -> int:
+    """Raw handle of torch's current stream on a device (default: the current device). The raw
+    accessor avoids building a Stream object, which costs microseconds per call."""
     torch = _torch()
-    s = stream if stream is not None else torch.cuda.current_stream()
-    return ctypes.c_void_p(s.cuda_stream)
+    raw = getattr(torch._C, "_cuda_getCurrentRawStream", None)
+    if raw is None:
+        return torch.cuda.current_stream(device_index).cuda_stream
+    return raw(torch.cuda.current_device() if device_index is None else device_index)
+
+
+def _stream_ptr(stream=None):
+    return ctypes.c_void_p(stream.cuda_stream if stream is not None else _current_stream())
 
 
 def _dev_ptr(t, dtype, ndim=None, what="tensor"):
@@ -79,6 +87,7 @@ class Index:
                               ctypes.byref(self._h)), "paris_build")
         # reused by every query() call (the per-query path is latency-bound)
         self._torch = torch
+        self._dev = series.device.index if series.device.index is not None else torch.cuda.current_device()
         self._query_fn = lib.paris_query_exact
         self._idx = ctypes.c_int64(-1)
         self._dist = ctypes.c_double(0.0)
@@ -95,9 +104,9 @@ class Index:
         if q.shape[0] != self.length:
             raise ValueError("query length differs from the collection's")
         st = ParisStats() if with_stats else None
-        s = stream if stream is not None else torch.cuda.current_stream()
+        s = stream.cuda_stream if stream is not None else _current_stream(self._dev)
         rc = self._query_fn(self._h, q.data_ptr(), self._idx_ref, self._dist_ref,
-                            ctypes.byref(st) if with_stats else None, s.cuda_stream)
+                            ctypes.byref(st) if with_stats else None, s)
         if rc != PARIS_OK:
             check(rc, "paris_query_exact")
         if with_stats:

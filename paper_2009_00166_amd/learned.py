@@ -23,9 +23,8 @@ def _torch():
 
 
 def _stream_ptr(stream=None):
-    torch = _torch()
-    s = stream if stream is not None else torch.cuda.current_stream()
-    return ctypes.c_void_p(s.cuda_stream)
+    from . import _current_stream
+    return ctypes.c_void_p(stream.cuda_stream if stream is not None else _current_stream())
 
 
 def _dev(t, dtype, what):
