@@ -972,9 +972,11 @@ __device__ __forceinline__ float group16_sum_b(float v)
 }
 
 // Upper bound on every query's nearest squared distance from its screen survivors. A kept pair
-// with accumulator A has d^2 <= U_q - 2 A + 2 c (qn + xn) <= U_q - 2 A_max + 2 c (qn + xn_max)
-// for the query's largest survivor accumulator A_max (gathered by the screen) and the largest
-// series norm xn_max; evaluated in float64, rounded up, stored in place of A_max (+inf: none).
+// with accumulator A has d^2 <= U_q - 2 A + 2 c (qn + xn); for the survivor holding the query's
+// largest accumulator A_max (gathered by the screen) that is at most
+// U_q - 2 A_max + 2 c (qn + xn_max), xn_max the largest series norm, and the nearest squared
+// distance is at most this survivor's. Evaluated in float64, rounded up, stored in place of
+// A_max (+inf: none).
 __global__ void k_query_ub(RescoreArgs R)
 {
     const int q = blockIdx.x * blockDim.x + threadIdx.x;
