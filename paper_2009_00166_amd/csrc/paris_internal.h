@@ -14,6 +14,7 @@ constexpr int kCoarse = 32;        // 5-bit prefix alphabet of the coarse lower-
 constexpr int kMaxLength = 2048;   // longest series the summarise kernel stages in LDS
 constexpr int kSeedChunk = 512;    // sorted positions per seed block: its smallest bound is refined
 constexpr int kSeedBatchChunks = 32;  // seed chunks per block of the batched seed
+constexpr int kSeedGroup = 4;         // batched seed: chunks whose positions are loaded together
 constexpr int kTimingEvery = 8;       // timing mode 3: the scan of every 8th query is timed
 constexpr int kResolveList = 256;  // in-band candidates resolved block-cooperatively
 constexpr int kRefineBlocks = 512; // default refine grid (16 lane groups of 16 lanes per block)

@@ -164,6 +164,7 @@ __global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* 
     __shared__ double red_lb[256];
     __shared__ int red_r[256];
     __shared__ unsigned long long red_key[4];
+    __shared__ unsigned long long red_key4[kSeedGroup][4];
     __shared__ int32_t s_leaves[kTopLeaves];
     __shared__ unsigned long long s_keys[(kMaxLeaves / 256) * kTopLeaves];
     __shared__ unsigned long long s_best[kSeedBatchChunks];
@@ -417,19 +418,59 @@ __global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* 
         return;
     }
     // batched: the best key of every chunk of this block staged in LDS, then their real
-    // distances one row per wave at a time, one atomicMin per wave
+    // distances one row per wave at a time, one atomicMin per wave. The chunks are taken
+    // kSeedGroup at a time, every lane's sorted positions of the group loaded at once (the
+    // per-chunk loop would wait for one chunk's loads at a time).
     const int v0 = (int)blockIdx.x * kSeedBatchChunks;
     const int v1 = (v0 + kSeedBatchChunks < B.chunks) ? v0 + kSeedBatchChunks : B.chunks;
+    constexpr int PPT = kSeedChunk / 256;   // positions per thread and chunk
     int nb = 0;
-    for (int v = v0; v < v1; ++v) {
-        long long c0, c1;
-        chunk_range(v, c0, c1);
-        if (c0 >= c1) continue;  // uniform
-        const unsigned long long best = chunk_best(c0, c1);
-        if (tid == 0) s_best[nb] = best;
-        ++nb;
+    for (int vg = v0; vg < v1; vg += kSeedGroup) {
+        uint32_t rows[kSeedGroup][PPT];
+        uint4 words[kSeedGroup][PPT];
+        bool nonempty[kSeedGroup];
+#pragma unroll
+        for (int u = 0; u < kSeedGroup; ++u) {
+            long long c0 = 0, c1 = 0;
+            if (vg + u < v1) chunk_range(vg + u, c0, c1);
+            nonempty[u] = c0 < c1;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                const long long p = c0 + tid + 256 * k;
+                const bool ok = p < c1;
+                // 0xFFFFFFFF marks no position (never a series index: n_series <= 2^32 - 2)
+                rows[u][k] = ok ? A.perm[p] : 0xFFFFFFFFu;
+                words[u][k] = ok ? reinterpret_cast<const uint4*>(A.saxs)[p] : make_uint4(0u, 0u, 0u, 0u);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < kSeedGroup; ++u) {
+            unsigned long long best = ~0ull;
+#pragma unroll
+            for (int k = 0; k < PPT; ++k) {
+                if (rows[u][k] == 0xFFFFFFFFu) continue;
+                const unsigned long long key = pack_key(fine_lb(words[u][k], t8), rows[u][k]);
+                best = key < best ? key : best;
+            }
+            for (int off = 32; off > 0; off >>= 1) {
+                const unsigned long long o = __shfl_xor(best, off);
+                best = o < best ? o : best;
+            }
+            if (lane == 0) red_key4[u][tid >> 6] = best;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < kSeedGroup; ++u) {
+            if (!nonempty[u]) continue;   // uniform
+            if (tid == 0) {
+                unsigned long long best = red_key4[u][0];
+                for (int k = 1; k < 4; ++k) best = red_key4[u][k] < best ? red_key4[u][k] : best;
+                s_best[nb] = best;
+            }
+            ++nb;
+        }
+        __syncthreads();   // red_key4 is rewritten by the next group
     }
-    __syncthreads();
     unsigned long long mine = ~0ull;
     for (int k = tid >> 6; k < nb; k += 4) {
         const uint32_t row = (uint32_t)(s_best[k] & 0xFFFFFFFFu);
