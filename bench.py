@@ -84,6 +84,39 @@ def cpu_baseline(X, Q, gpu_idx, n_queries: int, threads: int):
             "seconds": dt, "answers_agree_with_gpu": agrees}
 
 
+def bsf_sharing_ablation(index, X, n: int, count: int = 200):
+    """Hard queries (dataset series + N(0, 0.5) noise) through the plain path with the shared
+    best-so-far of ParIS+ and with one private copy per distance worker, nb-ParIS+'s design
+    (Section 3.3): answers, refined rows and queries/s of both (not part of the headline)."""
+    import numpy as np
+    import torch
+    import synth
+    Q, _, _ = synth.noisy_queries(X, count, seed=4, sigma=0.5)
+    Qd = torch.from_numpy(Q).to("cuda:0")
+    rows = [Qd[m] for m in range(count)]
+
+    def run():
+        index.query(rows[0])
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        got = [index.query(r)[0] for r in rows]
+        torch.cuda.synchronize()
+        qps = count / (time.perf_counter() - t0)
+        st = [index.query(r, with_stats=True)[2] for r in rows]
+        mean = lambda k: float(np.mean([x[k] for x in st]))
+        return {"queries_per_s": qps, "mean_lb_survivors": mean("lb_survivors"),
+                "mean_refined": mean("refined"), "mean_abandoned": mean("abandoned")}, got
+
+    shared, a = run()
+    index.set_bsf_sharing(False)
+    try:
+        private, b = run()
+    finally:
+        index.set_bsf_sharing(True)
+    return {"queries": f"{count} hard queries (dataset series + N(0,0.5) noise)", "shared": shared,
+            "private": private, "answers_identical": bool(a == b)}
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -96,6 +129,8 @@ def main() -> int:
     ap.add_argument("--fresh-queries", action="store_true",
                     help="plain path: queries are new random walks (the paper's query workload) "
                          "instead of dataset series plus noise")
+    ap.add_argument("--no-nb-ablation", dest="nb_ablation", action="store_false",
+                    help="skip the pass with private best-so-far copies (nb-ParIS+)")
     ap.add_argument("--cpu-queries", type=int, default=16)
     ap.add_argument("--cpu-threads", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -202,6 +237,7 @@ def main() -> int:
     # counters of one pass (not timed)
     stats = [index.query(rows[m], with_stats=True)[2] for m in range(min(M, 200))]
     mean = lambda k: float(np.mean([s[k] for s in stats]))
+    nb = bsf_sharing_ablation(index, X, n) if args.nb_ablation else None
 
     total_q = M * args.steps
     args._plain_qps = total_q / elapsed
@@ -246,6 +282,7 @@ def main() -> int:
         "mean_counters": {k: mean(k) for k in ("lb_survivors", "refined", "abandoned", "bsf_updates",
                                                "resolved")},
         "answers_match_source_frac": None if src is None else float(np.mean(answers == src)),
+        "bsf_sharing_ablation": nb,
     }
     if not args.no_batched:
         rec["batched"] = batched_section(index, X, args)

@@ -257,6 +257,21 @@ paris_status paris_lb_scan(paris_index *idx, const float *query_dev, float thres
                            void *hip_stream);
 
 /*
+ * Best-so-far sharing during refinement (Section 3.3: ParIS+ keeps one best-so-far that every
+ * distance worker reads and lowers; nb-ParIS+ gives each worker its own copy, initialised with
+ * the approximate answer, and takes the minimum over the copies at the end).
+ *   shared  1 (the default set by paris_build): every lane group of the refine kernel re-reads
+ *           the shared best-so-far as other groups lower it. 0: each lane group (one survivor
+ *           at a time, the GPU's distance worker) prunes only against the approximate search's
+ *           best-so-far and the smallest distance it has itself completed; the answer is still
+ *           the minimum over all groups, so results are identical, only the number of rows
+ *           refined (paris_stats.refined) changes. An ablation of the paper's design
+ *           choice; affects paris_query_exact (and the per-query fallback of batches).
+ * Returns PARIS_EINVAL for any other value, PARIS_ESTATE for a bad handle. Host only.
+ */
+paris_status paris_set_bsf_sharing(paris_index *idx, int32_t shared);
+
+/*
  * Per-phase device timing of paris_query_exact, with HIP events on the call's stream:
  * [0] query summaries + approximate-search seed (+ the seed network), [1] lower-bound scan,
  * [2] refinement + float64 resolve. paris_set_timing(idx, 1) times all three phases with events

@@ -378,3 +378,61 @@ def exact_search(q: np.ndarray, X: np.ndarray, sym8: np.ndarray | None = None,
             bsf, bsf_i = acc, i
             st.bsf_updates += 1
     return bsf_i, bsf, st
+
+
+def exact_search_nb(q: np.ndarray, X: np.ndarray, workers: int, sym8: np.ndarray | None = None,
+                    mode: str = "root16", seed_cap: int = 16384, n_leaves: int = 4096):
+    """Serial twin of nb-ParIS+ exact search (Section 3.3, the non-balanced variant): returns
+    ``(index, squared distance, refined rows per worker)``.
+
+    1. BSF <- approximate search, as in ``exact_search``.
+    2. The collection is split into ``workers`` contiguous blocks of positions. Each worker
+       keeps its own BSF copy, starting from the approximate answer, and walks its block in
+       position order: a series whose lower bound exceeds the worker's copy is pruned; otherwise
+       its squared distance is computed (early abandoning against the copy), and the copy is
+       lowered when the distance is smaller (ties to the lower index).
+    3. The answer is the smallest of the copies (ties to the lowest index).
+
+    The same slack as ``exact_search`` keeps the pruning test safe against rounding of the
+    PAA values.
+    """
+    X = np.asarray(X, dtype=np.float32)
+    N, n = X.shape
+    L = n // W
+    qf = np.asarray(q, dtype=np.float32)
+    qs = query_summary(qf)
+    if sym8 is None:
+        sym8 = isax(paa(X), 8)
+    seed, seed_i = np.inf, -1
+    if N > 0:
+        perm, keys_sorted = sorted_order(sym8)
+        a, b = seed_window(qs, keys_sorted, L, mode, seed_cap, n_leaves)
+        members = seed_candidates(qs, perm[a:b], sym8, L)
+        d2 = ed_sq(qf, X[members]) if len(members) else np.zeros(0)
+        for m, d in zip(members, d2):
+            if d < seed or (d == seed and m < seed_i):
+                seed, seed_i = float(d), int(m)
+    lb = lower_bound_sq(qs.paa[None, :], sym8, L)
+    qd = qf.astype(np.float64)
+    copies = []
+    refined = []
+    edges = [w * N // workers for w in range(workers + 1)]
+    for w in range(workers):
+        bsf, bsf_i, r = seed, seed_i, 0
+        for i in range(edges[w], edges[w + 1]):
+            if lb[i] > bsf * (1.0 + 1e-9) + 1e-12:
+                continue
+            r += 1
+            x = X[i].astype(np.float64)
+            acc = 0.0
+            for j in range(n):
+                d = qd[j] - x[j]
+                acc = acc + d * d
+                if acc > bsf:
+                    break
+            if acc < bsf or (acc == bsf and i < bsf_i):
+                bsf, bsf_i = acc, i
+        copies.append((bsf, bsf_i))
+        refined.append(r)
+    best, best_i = min(copies) if copies else (np.inf, -1)
+    return best_i, best, refined

@@ -245,6 +245,11 @@ class Index:
               "paris_block_bound_bits")
         return out
 
+    def set_bsf_sharing(self, shared: bool = True) -> None:
+        """Shared best-so-far during refinement (ParIS+, the default) or one private copy per
+        distance worker (nb-ParIS+, Section 3.3); answers are identical either way."""
+        check(load_library().paris_set_bsf_sharing(self._h, 1 if shared else 0), "paris_set_bsf_sharing")
+
     def set_timing(self, enable: bool = True, scan_only: bool = False, sampled: bool = False) -> None:
         """Enable HIP-event timing of query() and zero the totals: all three phases (events
         between them), or the scan kernel alone (events bound to its dispatch; sampled: the scan

@@ -70,6 +70,7 @@ SIGNATURES = [
     ("paris_screen_dots", ctypes.c_int, [_P, _P, _I32, _P, _P]),
     ("paris_batch_screen_tiles", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64), _I32]),
     ("paris_block_bound_bits", ctypes.c_int, [_P, _P, _P, _I32, _I32, _P, _P]),
+    ("paris_set_bsf_sharing", ctypes.c_int, [_P, _I32]),
     ("paris_set_timing", ctypes.c_int, [_P, _I32]),
     ("paris_get_timing", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     ("paris_get_batch_timing", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),

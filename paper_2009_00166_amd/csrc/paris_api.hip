@@ -163,6 +163,7 @@ struct paris_index {
     ScanShape scan;
     int refine_blocks;
     int refine_lanes;
+    int bsf_private;        // paris_set_bsf_sharing(h, 0): per-group best-so-far copies
     bool timing;
     int timing_mode;        // paris_set_timing: 1 all three phases, 2 the scan only, 3 the scan of every 8th call
     long long timing_calls; // paris_query_exact calls since timing was set (mode 3 sampling)
@@ -231,6 +232,7 @@ QueryArgs args_for(const paris_index* h)
     a.learned_cpl = 0;
     a.refine_blocks = h->refine_blocks;
     a.refine_lanes = h->refine_lanes;
+    a.bsf_private = h->bsf_private;
     return a;
 }
 
@@ -1033,6 +1035,7 @@ paris_status paris_build(const float* series_dev, int64_t n_series, int32_t leng
         const int v = std::atoi(rl);
         if (v == 4 || v == 8 || v == 16) h->refine_lanes = v;
     }
+    h->bsf_private = 0;
     h->timing = false;
     h->timing_mode = 0;
     for (int set = 0; set < 2; ++set) {
@@ -1264,6 +1267,14 @@ paris_status paris_lb_scan(paris_index* h, const float* query_dev, float thresho
     if (qerr & kErrNonFinite) return PARIS_EINVAL;
     *count = n;
     return n > capacity ? PARIS_EOVERFLOW : PARIS_OK;
+}
+
+paris_status paris_set_bsf_sharing(paris_index* h, int32_t shared)
+{
+    if (!handle_ok(h)) return PARIS_ESTATE;
+    if (shared != 0 && shared != 1) return PARIS_EINVAL;
+    h->bsf_private = shared ? 0 : 1;
+    return PARIS_OK;
 }
 
 paris_status paris_set_timing(paris_index* h, int32_t enable)

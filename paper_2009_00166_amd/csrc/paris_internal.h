@@ -107,6 +107,7 @@ struct QueryArgs {
     int learned_cpl;        // > 0: learned seed over kTopLeaves leaves of up to this many chunks
     int refine_blocks;      // refine grid (0: kRefineBlocks)
     int refine_lanes;       // lanes per refined row: 4, 8 (default) or 16
+    int bsf_private;        // 1: every lane group prunes with its own best-so-far copy only
 };
 
 // ---- batched path ----

@@ -872,9 +872,14 @@ __global__ __launch_bounds__(256) void k_refine_resolve(QueryArgs A, const float
     // prunes less, never wrongly); the shared best-so-far is re-read with every kKeyEvery-th
     // row's first chunk (one address read by every group: reading it per row makes a hot spot)
     // and once per chunk of longer rows.
+    // With bsf_private set (the non-sharing design of the paper's nb-ParIS+, Section 3.3), a
+    // group never re-reads the shared best-so-far: it prunes against the seed's best-so-far
+    // and the smallest distance it has completed itself. The atomicMin below still runs, as
+    // the final minimum over the groups' copies; pruning with a larger threshold is never wrong.
+    const bool priv = A.bsf_private != 0;
     constexpr int CV = 4 * F;            // float4 per lane per chunk
     unsigned long long key0 = 0;
-    if (l == 0) key0 = load_key(&A.qs->bsf_key);
+    if (l == 0) key0 = load_key(priv ? &A.qs->seed_key : &A.qs->bsf_key);
     key0 = __shfl(key0, lead);
     float thr = prune_threshold(fminf(key_dist(key0), local_best), A.mg.prune_rel);
     uint2 e_next = grp < count ? A.surv[grp] : make_uint2(0u, 0u);
@@ -884,8 +889,8 @@ __global__ __launch_bounds__(256) void k_refine_resolve(QueryArgs A, const float
         const float lb = __uint_as_float(e.y);
         if (lb > thr) continue;  // uniform in the group
         const float4* r4 = reinterpret_cast<const float4*>(A.X + (long long)e.x * A.n);
-        const bool fresh = (refined % kKeyEvery) == 0;
-        unsigned long long key = 0;
+        const bool fresh = !priv && (refined % kKeyEvery) == 0;
+        unsigned long long key = key0;
         if (fresh && l == 0) key = load_key(&A.qs->bsf_key);
         float4 xa[CV];
 #pragma unroll
@@ -906,7 +911,7 @@ __global__ __launch_bounds__(256) void k_refine_resolve(QueryArgs A, const float
             const bool more = v1 < nv;
             float4 xn[CV];
             if (more) {
-                if (l == 0) key = load_key(&A.qs->bsf_key);
+                if (l == 0 && !priv) key = load_key(&A.qs->bsf_key);
 #pragma unroll
                 for (int k = 0; k < CV; ++k) {
                     const int v = v1 + (k / F) * 16 + (k % F) * G + l;
@@ -933,6 +938,10 @@ __global__ __launch_bounds__(256) void k_refine_resolve(QueryArgs A, const float
             thr = prune_threshold(fminf(key_dist(key), local_best), A.mg.prune_rel);
         }
         if (ab) { ++abandoned; continue; }
+        if (priv) {   // acc is the group's sum, the same in every lane of the group
+            local_best = fminf(local_best, acc);
+            thr = prune_threshold(fminf(key_dist(key0), local_best), A.mg.prune_rel);
+        }
         if (l == 0) {
             const unsigned long long mine = pack_key(acc, e.x);
             const unsigned long long old = atomicMin(&A.qs->bsf_key, mine);

@@ -97,6 +97,8 @@ def test_invalid_handles_rejected():
     assert lib.paris_query_exact(bogus, ctypes.c_void_p(0x1000), ctypes.byref(i), ctypes.byref(d), None,
                                  None) == B.PARIS_ESTATE
     assert lib.paris_query_batch(None, None, 1, None, None, None, None) == B.PARIS_ESTATE
+    assert lib.paris_set_bsf_sharing(None, 1) == B.PARIS_ESTATE
+    assert lib.paris_set_bsf_sharing(bogus, 0) == B.PARIS_ESTATE
     lay = B.ParisLayout()
     assert lib.paris_get_layout(bogus, ctypes.byref(lay)) == B.PARIS_ESTATE
 

@@ -185,6 +185,42 @@ def test_exact_uneven_difficulty_and_fresh_walks(small, oracle_native):
         _check_answer(i, d, ri[m], rd[m])
 
 
+def test_private_bsf_copies_give_same_answers(small, oracle_native):
+    """nb-ParIS+'s design (Section 3.3): every distance worker (a lane group of the refine
+    kernel) prunes with its own best-so-far copy. Answers equal the oracle's and the shared
+    mode's; hard queries refine at least as many rows in total; also without a seed (the copies
+    then start at +inf)."""
+    import paper_2009_00166_amd as paris
+    idx, X = small["index"], small["X"]
+    Q1, _, _ = synth.noisy_queries(X, 20, seed=5, sigma=0.5)
+    Q = np.concatenate([Q1, synth.fresh_walk_queries(10, 256, seed=6), small["Q"][:10]])
+    ri, rd, _ = oracle_native.nn_many(Q, X, threads=16)
+    Qd = torch.from_numpy(Q).cuda()
+    no_seed = paris.build(small["Xd"], seed_cap=0)
+    refined = {}
+    try:
+        for shared in (True, False):
+            idx.set_bsf_sharing(shared)
+            total = 0
+            for m in range(Q.shape[0]):
+                i, d, st = idx.query(Qd[m], with_stats=True)
+                _check_answer(i, d, ri[m], rd[m])
+                total += st["refined"] if m < 30 else 0
+            refined[shared] = total
+        no_seed.set_bsf_sharing(False)
+        for m in range(0, Q.shape[0], 7):
+            i, d = no_seed.query(Qd[m])
+            _check_answer(i, d, ri[m], rd[m])
+    finally:
+        idx.set_bsf_sharing(True)
+        no_seed.close()
+    assert refined[False] >= refined[True]
+    print(f"[parity] refined rows over 30 hard queries: shared {refined[True]}, private "
+          f"{refined[False]}", flush=True)
+    from paper_2009_00166_amd import _binding as B
+    assert paris.load_library().paris_set_bsf_sharing(idx._h, 2) == B.PARIS_EINVAL
+
+
 def test_seed_disabled_and_equal_count_give_same_answers(small):
     import paper_2009_00166_amd as paris
     no_seed = paris.build(small["Xd"], seed_cap=0)
