@@ -260,13 +260,15 @@ paris_status paris_lb_scan(paris_index *idx, const float *query_dev, float thres
  * Best-so-far sharing during refinement (Section 3.3: ParIS+ keeps one best-so-far that every
  * distance worker reads and lowers; nb-ParIS+ gives each worker its own copy, initialised with
  * the approximate answer, and takes the minimum over the copies at the end).
- *   shared  1 (the default set by paris_build): every lane group of the refine kernel re-reads
- *           the shared best-so-far as other groups lower it. 0: each lane group (one survivor
- *           at a time, the GPU's distance worker) prunes only against the approximate search's
- *           best-so-far and the smallest distance it has itself completed; the answer is still
- *           the minimum over all groups, so results are identical, only the number of rows
- *           refined (paris_stats.refined) changes. An ablation of the paper's design
- *           choice; affects paris_query_exact (and the per-query fallback of batches).
+ *   shared  1: every lane group of the refine kernel re-reads the shared best-so-far as other
+ *           groups lower it (ParIS+'s design). 0 (the default set by paris_build): each lane
+ *           group (one survivor at a time, the GPU's distance worker) prunes only against the
+ *           approximate search's best-so-far and the smallest distance it has itself completed;
+ *           the answer is still the minimum over all groups. Results are identical either way;
+ *           only the number of rows refined (paris_stats.refined) and the time change: private
+ *           copies refine a few percent more rows but skip the re-reads of one hot address,
+ *           and on hard queries run faster. Affects paris_query_exact (and the per-query
+ *           fallback of batches).
  * Returns PARIS_EINVAL for any other value, PARIS_ESTATE for a bad handle. Host only.
  */
 paris_status paris_set_bsf_sharing(paris_index *idx, int32_t shared);

@@ -246,8 +246,8 @@ class Index:
         return out
 
     def set_bsf_sharing(self, shared: bool = True) -> None:
-        """Shared best-so-far during refinement (ParIS+, the default) or one private copy per
-        distance worker (nb-ParIS+, Section 3.3); answers are identical either way."""
+        """Shared best-so-far during refinement (ParIS+) or one private copy per distance
+        worker (nb-ParIS+, Section 3.3; the default, faster here); answers are identical."""
         check(load_library().paris_set_bsf_sharing(self._h, 1 if shared else 0), "paris_set_bsf_sharing")
 
     def set_timing(self, enable: bool = True, scan_only: bool = False, sampled: bool = False) -> None:

@@ -163,7 +163,7 @@ struct paris_index {
     ScanShape scan;
     int refine_blocks;
     int refine_lanes;
-    int bsf_private;        // paris_set_bsf_sharing(h, 0): per-group best-so-far copies
+    int bsf_private;        // 1 (default): per-group best-so-far copies; 0: one shared best-so-far
     bool timing;
     int timing_mode;        // paris_set_timing: 1 all three phases, 2 the scan only, 3 the scan of every 8th call
     long long timing_calls; // paris_query_exact calls since timing was set (mode 3 sampling)
@@ -1035,7 +1035,7 @@ paris_status paris_build(const float* series_dev, int64_t n_series, int32_t leng
         const int v = std::atoi(rl);
         if (v == 4 || v == 8 || v == 16) h->refine_lanes = v;
     }
-    h->bsf_private = 0;
+    h->bsf_private = 1;   // measured faster on the GPU; paris_set_bsf_sharing(h, 1) for ParIS+'s
     h->timing = false;
     h->timing_mode = 0;
     for (int set = 0; set < 2; ++set) {

@@ -872,10 +872,12 @@ __global__ __launch_bounds__(256) void k_refine_resolve(QueryArgs A, const float
     // prunes less, never wrongly); the shared best-so-far is re-read with every kKeyEvery-th
     // row's first chunk (one address read by every group: reading it per row makes a hot spot)
     // and once per chunk of longer rows.
-    // With bsf_private set (the non-sharing design of the paper's nb-ParIS+, Section 3.3), a
-    // group never re-reads the shared best-so-far: it prunes against the seed's best-so-far
-    // and the smallest distance it has completed itself. The atomicMin below still runs, as
-    // the final minimum over the groups' copies; pruning with a larger threshold is never wrong.
+    // With bsf_private set (the non-sharing design of the paper's nb-ParIS+, Section 3.3; the
+    // default, since the re-reads of one hot address cost more than the few extra rows refined
+    // without them), a group never re-reads the shared best-so-far: it prunes against the
+    // seed's best-so-far and the smallest distance it has completed itself. The atomicMin below
+    // still runs, as the final minimum over the groups' copies; pruning with a larger threshold
+    // is never wrong.
     const bool priv = A.bsf_private != 0;
     constexpr int CV = 4 * F;            // float4 per lane per chunk
     unsigned long long key0 = 0;

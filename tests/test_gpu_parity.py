@@ -186,10 +186,11 @@ def test_exact_uneven_difficulty_and_fresh_walks(small, oracle_native):
 
 
 def test_private_bsf_copies_give_same_answers(small, oracle_native):
-    """nb-ParIS+'s design (Section 3.3): every distance worker (a lane group of the refine
-    kernel) prunes with its own best-so-far copy. Answers equal the oracle's and the shared
-    mode's; hard queries refine at least as many rows in total; also without a seed (the copies
-    then start at +inf)."""
+    """nb-ParIS+'s design (Section 3.3, the library's default): every distance worker (a lane
+    group of the refine kernel) prunes with its own best-so-far copy; ParIS+'s shared
+    best-so-far on request. Answers equal the oracle's in both modes; hard queries refine at
+    least as many rows in total with private copies; also without a seed (the copies then
+    start at +inf)."""
     import paper_2009_00166_amd as paris
     idx, X = small["index"], small["X"]
     Q1, _, _ = synth.noisy_queries(X, 20, seed=5, sigma=0.5)
@@ -212,7 +213,7 @@ def test_private_bsf_copies_give_same_answers(small, oracle_native):
             i, d = no_seed.query(Qd[m])
             _check_answer(i, d, ri[m], rd[m])
     finally:
-        idx.set_bsf_sharing(True)
+        idx.set_bsf_sharing(False)      # the default
         no_seed.close()
     assert refined[False] >= refined[True]
     print(f"[parity] refined rows over 30 hard queries: shared {refined[True]}, private "
