@@ -188,8 +188,8 @@ def test_exact_uneven_difficulty_and_fresh_walks(small, oracle_native):
 def test_private_bsf_copies_give_same_answers(small, oracle_native):
     """nb-ParIS+'s design (Section 3.3, the library's default): every distance worker (a lane
     group of the refine kernel) prunes with its own best-so-far copy; ParIS+'s shared
-    best-so-far on request. Answers equal the oracle's in both modes; hard queries refine at
-    least as many rows in total with private copies; also without a seed (the copies then
+    best-so-far on request. Answers equal the oracle's in both modes; hard queries refine
+    about as many rows or more with private copies; also without a seed (the copies then
     start at +inf)."""
     import paper_2009_00166_amd as paris
     idx, X = small["index"], small["X"]
@@ -215,7 +215,9 @@ def test_private_bsf_copies_give_same_answers(small, oracle_native):
     finally:
         idx.set_bsf_sharing(False)      # the default
         no_seed.close()
-    assert refined[False] >= refined[True]
+    # Not a theorem on the GPU (when the shared best-so-far falls depends on scheduling), so
+    # only a loose check: private copies do not prune much better than the shared value.
+    assert refined[False] >= 0.95 * refined[True]
     print(f"[parity] refined rows over 30 hard queries: shared {refined[True]}, private "
           f"{refined[False]}", flush=True)
     from paper_2009_00166_amd import _binding as B

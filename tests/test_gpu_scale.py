@@ -115,3 +115,24 @@ def test_full_batch_at_scale(full, oracle_native):
         assert d_ret <= d_src, m
     print(f"[scale] full batch: {st['lb_survivors']} screen survivors, {st['refined']} re-scored, "
           f"{st['resolved']} fallbacks", flush=True)
+
+
+def test_shared_and_private_best_so_far_at_scale(full, oracle_native):
+    """Both best-so-far modes of the refine kernel (private copies per lane group, the default,
+    and ParIS+'s shared value) at 10M x 256 on hard and new-walk queries: identical answers,
+    equal to the brute-force oracle's."""
+    X, index = full["X"], full["index"]
+    Qh, _, _ = synth.noisy_queries(X, 8, seed=5, sigma=0.5)
+    Q = np.ascontiguousarray(np.concatenate([Qh, synth.fresh_walk_queries(4, LEN, seed=6)]))
+    ri, rd, _ = oracle_native.nn_many(Q, X, threads=16)
+    Qd = torch.from_numpy(Q).cuda()
+    try:
+        for shared in (True, False):
+            index.set_bsf_sharing(shared)
+            for m in range(Q.shape[0]):
+                i, d = index.query(Qd[m])
+                ref = math.sqrt(rd[m])
+                assert i == int(ri[m]), (shared, m, i, int(ri[m]))
+                assert abs(d - ref) <= 1e-5 * ref
+    finally:
+        index.set_bsf_sharing(False)
