@@ -135,7 +135,7 @@ def main() -> int:
                     help="plain path: queries are new random walks (the paper's query workload) "
                          "instead of dataset series plus noise")
     ap.add_argument("--no-nb-ablation", dest="nb_ablation", action="store_false",
-                    help="skip the pass with private best-so-far copies (nb-ParIS+)")
+                    help="skip the best-so-far sharing ablation (shared vs private copies, hard queries)")
     ap.add_argument("--cpu-queries", type=int, default=16)
     ap.add_argument("--cpu-threads", type=int, default=16)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -388,7 +388,8 @@ def batched_section(index, X, args):
                    "batch": B, "n_series": N, "length": n},
         "vs_plain": qps / args._plain_qps if args._plain_qps else None,
         "roofline": {"bound": "mfma", "kernel": "k_screen32", "achieved": achieved, "peak": 2500.0,
-                     "unit": "TFLOP/s", "frac": achieved / 2500.0, "traffic": measured_traffic("k_screen"),
+                     "unit": "TFLOP/s", "frac": achieved / 2500.0, "traffic": (measured_traffic("k_screen")     # counters cover 10M x 256, 4096-query batches
+                                                 if (N, n, B) == (10_000_000, 256, 4096) else None),
                      "flops_per_launch": flops, "avg_launch_ms": stage[2],
                      "note": "flops = 2 x 256 per (query, series) pair of the query tiles the block "
                              "bound kept (tiles_kept_frac of a screen of every pair)"},
