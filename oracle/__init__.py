@@ -17,5 +17,6 @@ from .breakpoints import breakpoints, breakpoints_at_cardinality  # noqa: F401
 from .reference import (  # noqa: F401
     paa, isax, root_key, k64, lower_bound_sq, ed_sq, nn_bruteforce, sorted_order,
     root_offsets, equal_count_bounds, seed_window, exact_search, exact_search_nb, ExactStats, query_summary,
+    knn_bruteforce, exact_search_knn,
     lb_table, lb_coarse_table, seed_candidates, block_lower_bound_sq,
 )

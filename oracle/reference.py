@@ -436,3 +436,70 @@ def exact_search_nb(q: np.ndarray, X: np.ndarray, workers: int, sym8: np.ndarray
         refined.append(r)
     best, best_i = min(copies) if copies else (np.inf, -1)
     return best_i, best, refined
+
+
+def knn_bruteforce(q: np.ndarray, X: np.ndarray, k: int):
+    """k-NN by definition (the k-NN classification experiment of Section 5 uses the k nearest
+    series): the k pairs (squared distance, index) with the smallest squared distance, in
+    ascending (distance, index) order (reading: ties go to the lower index, as for 1-NN).
+    Returns ``(indices int64[min(k, N)], squared distances float64[min(k, N)])``."""
+    d2 = ed_sq(q, X)
+    order = np.lexsort((np.arange(len(d2)), d2))[:k]
+    return order.astype(np.int64), d2[order]
+
+
+def exact_search_knn(q: np.ndarray, X: np.ndarray, k: int, sym8: np.ndarray | None = None,
+                     mode: str = "root16", seed_cap: int = 16384, n_leaves: int = 4096):
+    """Serial twin of exact search generalised to k answers (the paper defines exact search for
+    one answer; this generalisation is checked against the definition, ``knn_bruteforce``).
+
+    The best-so-far becomes the k-th smallest distance found so far (+inf while fewer than k
+    are known): the approximate search's candidates seed the list; a series whose lower bound
+    exceeds the k-th best is pruned; the others are processed in ascending (LB², index), their
+    distance abandoned once it exceeds the k-th best, and kept when it enters the list.
+    Returns ``(indices, squared distances, refined count)`` like ``knn_bruteforce``.
+    """
+    X = np.asarray(X, dtype=np.float32)
+    N, n = X.shape
+    L = n // W
+    qf = np.asarray(q, dtype=np.float32)
+    qs = query_summary(qf)
+    if sym8 is None:
+        sym8 = isax(paa(X), 8)
+    best = []                                   # sorted list of (d2, index), at most k long
+
+    def kth() -> float:
+        return best[-1][0] if len(best) >= k else np.inf
+
+    def offer(d: float, i: int) -> None:
+        if len(best) < k or (d, i) < best[-1]:
+            best.append((d, i))
+            best.sort()
+            del best[k:]
+
+    if N > 0:
+        perm, keys_sorted = sorted_order(sym8)
+        a, b = seed_window(qs, keys_sorted, L, mode, seed_cap, n_leaves)
+        members = seed_candidates(qs, perm[a:b], sym8, L)
+        for m, d in zip(members, ed_sq(qf, X[members]) if len(members) else []):
+            offer(float(d), int(m))
+    seeded = {i for _, i in best}
+    lb = lower_bound_sq(qs.paa[None, :], sym8, L)
+    cand = sorted(range(N), key=lambda i: (lb[i], i))
+    qd = qf.astype(np.float64)
+    refined = 0
+    for i in cand:
+        if i in seeded or lb[i] > kth() * (1.0 + 1e-9) + 1e-12:
+            continue
+        refined += 1
+        x = X[i].astype(np.float64)
+        acc, limit = 0.0, kth()
+        for j in range(n):
+            d = qd[j] - x[j]
+            acc = acc + d * d
+            if acc > limit:
+                break
+        else:
+            offer(acc, i)
+    idx = np.array([i for _, i in best], dtype=np.int64)
+    return idx, np.array([d for d, _ in best], dtype=np.float64), refined
