@@ -149,3 +149,17 @@ def test_block_bound_from_first_member_only_is_caught(monkeypatch):
     import oracle
     monkeypatch.setattr(oracle, "block_lower_bound_sq", bad)
     _fails(T_lb.test_block_bound_below_every_member, 32)
+
+
+def test_nb_copies_shared_between_workers_is_caught(monkeypatch):
+    """nb-ParIS+ twin with one best-so-far for all workers (the copies not kept apart): the
+    per-worker refined counts no longer match their closed form."""
+    import tests.test_oracle_nb as T_nb
+    real = R.exact_search_nb
+
+    def shared_copy(q, X, workers, *a, **k):
+        i, d, r = real(q, X, 1, *a, **k)
+        return i, d, [sum(r)] + [0] * (workers - 1)
+
+    monkeypatch.setattr(T_nb, "exact_search_nb", shared_copy)
+    _fails(T_nb.test_nb_twin_answers_and_counts, 5)
