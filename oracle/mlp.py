@@ -31,7 +31,7 @@ from __future__ import annotations
 
 import numpy as np
 
-from .reference import W, ed_sq, equal_count_bounds, query_summary, seed_candidates
+from .reference import approximate_seed, equal_count_bounds, query_summary
 
 IN, HID = 16, 256
 TOP_LEAVES = 8
@@ -184,25 +184,13 @@ def leaf_of_index(perm: np.ndarray, n_leaves: int, idx) -> np.ndarray:
     return ((p + 1) * n_leaves + N - 1) // N - 1
 
 
-def learned_seed(q: np.ndarray, X: np.ndarray, sym8: np.ndarray, perm: np.ndarray,
-                 n_leaves: int, leaves) -> tuple:
-    """Seed over the given leaves: in every leaf, runs of 512 sorted positions are refined at
-    their smallest-bound member (as the plain seed does in its one leaf); the seed is the smallest
-    squared distance over all refined members (ties: lowest index).
-    Returns (index, squared distance, refined members)."""
-    qs = query_summary(np.asarray(q, np.float32))
-    L = X.shape[1] // W
+def learned_seed(q: np.ndarray, X: np.ndarray, perm: np.ndarray, n_leaves: int, leaves) -> tuple:
+    """Seed over the given leaves: the approximate search of Section 3.3 (the smallest real
+    distance over every series of the leaf) taken over all series of the listed equal-count
+    leaves together; ties go to the lowest index.
+    Returns (index, squared distance, members examined)."""
     bnd = equal_count_bounds(X.shape[0], n_leaves)
-    cands = []
-    for ell in leaves:
-        members = np.asarray(perm[bnd[ell]:bnd[ell + 1]], np.int64)
-        if len(members):
-            cands.append(seed_candidates(qs, members, sym8, L))
-    cands = np.concatenate(cands) if cands else np.zeros(0, np.int64)
-    best, bi = np.inf, -1
-    if len(cands):
-        d2 = ed_sq(q, X[cands])
-        for i, d in zip(cands, d2):
-            if d < best or (d == best and i < bi):
-                best, bi = float(d), int(i)
-    return bi, best, cands
+    parts = [np.asarray(perm[bnd[ell]:bnd[ell + 1]], np.int64) for ell in leaves]
+    members = np.concatenate(parts) if parts else np.zeros(0, np.int64)
+    bi, best = approximate_seed(q, X, members)
+    return bi, best, members

@@ -275,25 +275,33 @@ def seed_window(qs: QuerySummary, keys_sorted: np.ndarray, L: int, mode: str = "
     return a, a + seed_cap
 
 
-SEED_CHUNK = 512
+def approximate_seed(q: np.ndarray, X: np.ndarray, members: np.ndarray):
+    """The approximate answer that opens exact search (Section 3.3, first paragraph; the first
+    step of both ExactSearch algorithms, Section 3.3.2 and 3.3.3): the real distance from the
+    query to every series of the reached leaf is computed and the smallest becomes the first
+    best-so-far. ``members`` are the series of that leaf (here the window ``seed_window`` gives,
+    through the sorted order). Ties go to the lowest series index.
 
-
-def seed_candidates(qs: QuerySummary, members: np.ndarray, sym8: np.ndarray, L: int,
-                    chunk: int = SEED_CHUNK) -> np.ndarray:
-    """Members of the approximate-search window whose real distance is computed.
-
-    Reading: the paper computes the distance to every series of the leaf it reaches; leaves
-    here can hold tens of thousands of series, so the window is cut into runs of ``chunk``
-    consecutive sorted positions and in each run only the member with the smallest lower bound
-    (ties: lowest series index) is refined. The minimum real distance over these is the seed.
+    Returns ``(index, squared distance)``; ``(-1, +inf)`` for an empty leaf.
     """
-    out = []
-    for a in range(0, len(members), chunk):
-        run = members[a:a + chunk]
-        lb = lower_bound_sq(qs.paa[None, :], sym8[run], L)
-        j = int(np.lexsort((run, lb))[0])
-        out.append(int(run[j]))
-    return np.array(out, dtype=np.int64)
+    members = np.asarray(members, dtype=np.int64)
+    if members.shape[0] == 0:
+        return -1, float("inf")
+    d2 = ed_sq(q, X[members])
+    j = int(np.lexsort((members, d2))[0])
+    return int(members[j]), float(d2[j])
+
+
+def approximate_seed_k(q: np.ndarray, X: np.ndarray, members: np.ndarray, k: int):
+    """The approximate search generalised to k answers: the ``min(k, len(members))`` members of
+    the reached leaf with the smallest (squared distance, index), in that order.
+    Returns ``(indices int64[], squared distances float64[])``."""
+    members = np.asarray(members, dtype=np.int64)
+    if members.shape[0] == 0:
+        return np.zeros(0, np.int64), np.zeros(0, np.float64)
+    d2 = ed_sq(q, X[members])
+    order = np.lexsort((members, d2))[:k]
+    return members[order], d2[order]
 
 
 # --------------------------------------------------------------------------------------------
@@ -315,9 +323,9 @@ def exact_search(q: np.ndarray, X: np.ndarray, sym8: np.ndarray | None = None,
                  use_seed: bool = True):
     """Serial twin of ParIS+ exact search; returns ``(index, squared distance, ExactStats)``.
 
-    1. BSF <- approximate search (``seed_window``, then ``seed_candidates``; min squared
-       distance over the candidates, ties to the lowest index), or +inf when ``use_seed`` is
-       False.
+    1. BSF <- approximate search (``seed_window``, then ``approximate_seed``: the smallest
+       squared distance over every member of the window, ties to the lowest index), or +inf when
+       ``use_seed`` is False.
     2. LBC step: candidates = {i : LB^2_i <= BSF^2}. The paper keeps i when minDist < BSF;
        reading: prune only on ">", so a series tied with the BSF at a lower index survives.
     3. Candidates are processed in ascending (LB^2, i) (the paper sorts by file position for
@@ -343,11 +351,7 @@ def exact_search(q: np.ndarray, X: np.ndarray, sym8: np.ndarray | None = None,
     if use_seed and N > 0:
         perm, keys_sorted = sorted_order(sym8)
         a, b = seed_window(qs, keys_sorted, L, mode, seed_cap, n_leaves)
-        members = seed_candidates(qs, perm[a:b], sym8, L)
-        d2 = ed_sq(qf, X[members]) if len(members) else np.zeros(0)
-        for m, d in zip(members, d2):
-            if d < bsf or (d == bsf and m < bsf_i):
-                bsf, bsf_i = float(d), int(m)
+        bsf_i, bsf = approximate_seed(qf, X, perm[a:b])
         st.seed_index, st.seed_d2 = bsf_i, bsf
     lb = lower_bound_sq(qs.paa[None, :], sym8, L)
 
@@ -407,11 +411,7 @@ def exact_search_nb(q: np.ndarray, X: np.ndarray, workers: int, sym8: np.ndarray
     if N > 0:
         perm, keys_sorted = sorted_order(sym8)
         a, b = seed_window(qs, keys_sorted, L, mode, seed_cap, n_leaves)
-        members = seed_candidates(qs, perm[a:b], sym8, L)
-        d2 = ed_sq(qf, X[members]) if len(members) else np.zeros(0)
-        for m, d in zip(members, d2):
-            if d < seed or (d == seed and m < seed_i):
-                seed, seed_i = float(d), int(m)
+        seed_i, seed = approximate_seed(qf, X, perm[a:b])
     lb = lower_bound_sq(qs.paa[None, :], sym8, L)
     qd = qf.astype(np.float64)
     copies = []
@@ -439,7 +439,7 @@ def exact_search_nb(q: np.ndarray, X: np.ndarray, workers: int, sym8: np.ndarray
 
 
 def knn_bruteforce(q: np.ndarray, X: np.ndarray, k: int):
-    """k-NN by definition (the k-NN classification experiment of Section 5 uses the k nearest
+    """k-NN by definition (the k-NN classification experiment of Section 4 uses the k nearest
     series): the k pairs (squared distance, index) with the smallest squared distance, in
     ascending (distance, index) order (reading: ties go to the lower index, as for 1-NN).
     Returns ``(indices int64[min(k, N)], squared distances float64[min(k, N)])``."""
@@ -454,7 +454,8 @@ def exact_search_knn(q: np.ndarray, X: np.ndarray, k: int, sym8: np.ndarray | No
     one answer; this generalisation is checked against the definition, ``knn_bruteforce``).
 
     The best-so-far becomes the k-th smallest distance found so far (+inf while fewer than k
-    are known): the approximate search's candidates seed the list; a series whose lower bound
+    are known): every member of the approximate search's window is offered to the list first
+    (their distances are all computed, as the approximate search computes them); a series whose lower bound
     exceeds the k-th best is pruned; the others are processed in ascending (LB², index), their
     distance abandoned once it exceeds the k-th best, and kept when it enters the list.
     Returns ``(indices, squared distances, refined count)`` like ``knn_bruteforce``.
@@ -480,10 +481,12 @@ def exact_search_knn(q: np.ndarray, X: np.ndarray, k: int, sym8: np.ndarray | No
     if N > 0:
         perm, keys_sorted = sorted_order(sym8)
         a, b = seed_window(qs, keys_sorted, L, mode, seed_cap, n_leaves)
-        members = seed_candidates(qs, perm[a:b], sym8, L)
+        members = perm[a:b]
         for m, d in zip(members, ed_sq(qf, X[members]) if len(members) else []):
             offer(float(d), int(m))
-    seeded = {i for _, i in best}
+        seeded = {int(m) for m in members}
+    else:
+        seeded = set()
     lb = lower_bound_sq(qs.paa[None, :], sym8, L)
     cand = sorted(range(N), key=lambda i: (lb[i], i))
     qd = qf.astype(np.float64)

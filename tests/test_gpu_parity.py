@@ -240,22 +240,26 @@ def test_seed_disabled_and_equal_count_give_same_answers(small):
 
 
 def test_seed_is_a_true_distance_in_its_window(small):
+    """Whatever members of the window the kernel refines (it samples the smallest-bound member of
+    every 512 sorted positions), a valid seed is the true distance of a member of the window the
+    oracle's approximate search reaches, never below the oracle's seed (the smallest distance over
+    every member of that window, Section 3.3), and leaves the answer unchanged."""
     idx = small["index"]
-    perm, _ = sorted_order(small["sym"])
-    from oracle import ed_sq, seed_candidates
+    perm, ks = sorted_order(small["sym"])
+    off = root_offsets(ks)
+    from oracle import approximate_seed, ed_sq
     for m in range(0, 100, 11):
         q = small["Q"][m]
         i, d, st = idx.query(small["Qd"][m], with_stats=True)
-        members = perm[st["seed_lo"]:st["seed_hi"]]
+        a, b = seed_window(query_summary(q), ks, 16, "root16", seed_cap=16384, off=off)
+        assert (st["seed_lo"], st["seed_hi"]) == (a, b)
+        members = perm[a:b]
         assert st["seed_index"] in set(members.tolist())
         own = math.sqrt(float(ed_sq(q, small["X"][st["seed_index"]])))
         assert abs(st["seed_dist"] - own) <= 1e-5 * own + 1e-6       # a true distance
-        window_min = math.sqrt(float(np.min(ed_sq(q, small["X"][members]))))
-        assert st["seed_dist"] >= window_min * (1 - 1e-5) and st["seed_dist"] >= d * (1 - 1e-5)
-        # the oracle's reading of the seed (smallest bound per 512-run) reaches the same distance
-        cand = seed_candidates(query_summary(q), members, small["sym"], 16)
-        ref = math.sqrt(float(np.min(ed_sq(q, small["X"][cand]))))
-        assert abs(st["seed_dist"] - ref) <= 1e-4 * ref + 1e-6
+        _, ref_d2 = approximate_seed(q, small["X"], members)
+        assert st["seed_dist"] >= math.sqrt(ref_d2) * (1 - 1e-5) and st["seed_dist"] >= d * (1 - 1e-5)
+        _check_answer(i, d, small["ref_i"][m], small["ref_d2"][m])
 
 
 def test_ties_duplicates_and_degenerate_sizes(oracle_native):

@@ -1,6 +1,6 @@
 """GPU parity at the paper's own scale and query workload: 100,000,000 random walks of length
 256 (102.4 GB of float32, inside the 50-250 GB range of the paper's query experiments, Section
-5), queried with new random walks as the paper's query sets are (Section 5, datasets), plus a
+4), queried with new random walks as the paper's query sets are (Section 4, datasets), plus a
 few dataset-series-plus-noise queries. The per-query path (paris_query_exact) and one batch
 through paris_query_batch are checked against the brute-force C oracle; at this size the iSAX
 array (1.6 GB) no longer fits the chip's last-level cache, so the scan streams from HBM."""

@@ -1,5 +1,5 @@
 """Pins for the oracle's exact k-NN (the k nearest series, used by the paper's k-NN
-classification experiment, Section 5): the definition against scipy's distance matrix and a
+classification experiment, Section 4): the definition against scipy's distance matrix and a
 library sort; k = 1 against the 1-NN definition and the 1-NN twin; the serial k-NN twin (the
 best-so-far is the k-th best) against the definition, with ties, k >= N and both leaf modes."""
 import numpy as np

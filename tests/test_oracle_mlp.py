@@ -188,11 +188,11 @@ def test_learned_seed_over_the_plain_leaf_is_the_plain_seed():
         a, b = seed_window(qs, keys, 64 // 16, mode="equal_count", n_leaves=nl)
         ell = int(np.searchsorted(bnd, a, side="right") - 1)
         assert (bnd[ell], bnd[ell + 1]) == (a, b)
-        i, d2, _ = M.learned_seed(q, X, sym8, perm, nl, [ell])
+        i, d2, _ = M.learned_seed(q, X, perm, nl, [ell])
         _, _, st = exact_search(q, X, sym8, mode="equal_count", n_leaves=nl)
         assert (i, d2) == (st.seed_index, st.seed_d2)
         # more leaves can only lower the seed, and it stays a true distance >= the 1-NN distance
-        i8, d8, _ = M.learned_seed(q, X, sym8, perm, nl, [ell] + [(ell + k) % nl for k in range(1, 8)])
+        i8, d8, _ = M.learned_seed(q, X, perm, nl, [ell] + [(ell + k) % nl for k in range(1, 8)])
         assert d8 <= d2
         true = ((q.astype(np.float64) - X[i8].astype(np.float64)) ** 2).sum()
         assert d8 == pytest.approx(true, rel=1e-12)

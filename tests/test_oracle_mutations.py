@@ -163,3 +163,62 @@ def test_nb_copies_shared_between_workers_is_caught(monkeypatch):
 
     monkeypatch.setattr(T_nb, "exact_search_nb", shared_copy)
     _fails(T_nb.test_nb_twin_answers_and_counts, 5)
+
+
+# ---- approximate search and the k-NN twin ------------------------------------------------------
+def _mutated(fn, old, new):
+    """A copy of oracle function ``fn`` with one source fragment replaced (the planted slip)."""
+    import inspect
+    import textwrap
+    src = textwrap.dedent(inspect.getsource(fn))
+    assert old in src, old
+    ns = dict(vars(R))
+    exec(compile(src.replace(old, new), "<mutant>", "exec"), ns)
+    return ns[fn.__name__]
+
+
+def test_seed_sampled_per_run_is_caught(monkeypatch):
+    """Refining only the smallest-bound member of every 512 sorted positions is a kernel design;
+    as the oracle's seed it must fail the brute-force pin of the approximate search."""
+    real = R.approximate_seed
+
+    def sampled(q, X, members, run=512):
+        members = np.asarray(members, np.int64)
+        if len(members) == 0:
+            return -1, float("inf")
+        qp = R.query_summary(np.asarray(q, np.float32)).paa
+        S = R.isax(R.paa(np.asarray(X[members], np.float32)))
+        picks = []
+        for a in range(0, len(members), run):
+            lb = R.lower_bound_sq(qp[None, :], S[a:a + run], X.shape[1] // 16)
+            picks.append(int(members[a + int(np.lexsort((members[a:a + run], lb))[0])]))
+        return real(q, X, np.array(picks))
+    monkeypatch.setattr(R, "approximate_seed", sampled)
+    import oracle
+    monkeypatch.setattr(oracle, "approximate_seed", sampled)
+    _fails(T_search.test_approximate_seed_is_the_window_minimum_by_brute_force)
+
+
+def test_seed_ties_to_highest_index_are_caught(monkeypatch):
+    bad = _mutated(R.approximate_seed, "np.lexsort((members, d2))", "np.lexsort((-members, d2))")
+    import oracle
+    monkeypatch.setattr(oracle, "approximate_seed", bad)
+    _fails(T_search.test_approximate_seed_hand_worked)
+
+
+def test_knn_threshold_at_the_best_instead_of_the_kth_is_caught(monkeypatch):
+    import oracle
+    import tests.test_oracle_knn as T_knn
+    bad = _mutated(R.exact_search_knn, "return best[-1][0] if len(best) >= k else np.inf",
+                   "return best[0][0] if best else np.inf")
+    monkeypatch.setattr(oracle, "exact_search_knn", bad)
+    monkeypatch.setattr(T_knn, "exact_search_knn", bad)
+    _fails(T_knn.test_twin_equals_definition, 10, "equal_count")
+    _fails(T_search.test_knn_twin_refined_count_closed_form, 4)
+
+
+def test_knn_twin_without_pruning_is_caught(monkeypatch):
+    import oracle
+    bad = _mutated(R.exact_search_knn, "lb[i] > kth() * (1.0 + 1e-9) + 1e-12", "False")
+    monkeypatch.setattr(oracle, "exact_search_knn", bad)
+    _fails(T_search.test_knn_twin_refined_count_closed_form, 4)

@@ -126,3 +126,87 @@ def test_c_oracle_short_segments(oracle_native):
     p_c, s_c = oracle_native.summarise(X)
     assert np.array_equal(paa(X).view(np.uint64), p_c.view(np.uint64))
     assert np.array_equal(isax(paa(X)), s_c)
+
+
+# ---- the approximate search (Section 3.3): the smallest real distance over the reached leaf ----
+def test_approximate_seed_hand_worked():
+    """q = 0 and constant rows c: ED^2 = 16 c^2. Members 4, 1, 3, 0 hold 2.5, -2, 2, 3, so the
+    squared distances are 100, 64, 64, 144: the minimum 64 is tied between series 1 and 3 and
+    goes to the lower index 1. Series 2 (0.5, distance^2 4) is closer but not a member."""
+    from oracle import approximate_seed, approximate_seed_k
+    vals = [3.0, -2.0, 0.5, 2.0, 2.5]
+    X = np.stack([np.full(16, v, np.float32) for v in vals])
+    q = np.zeros(16, np.float32)
+    members = np.array([4, 1, 3, 0])
+    assert approximate_seed(q, X, members) == (1, 64.0)
+    assert approximate_seed(q, X, members[::-1].copy()) == (1, 64.0)
+    idx, d2 = approximate_seed_k(q, X, members, 3)
+    assert list(idx) == [1, 3, 4] and list(d2) == [64.0, 64.0, 100.0]
+    assert approximate_seed(q, X, np.array([], np.int64)) == (-1, float("inf"))
+
+
+def test_approximate_seed_is_the_window_minimum_by_brute_force():
+    """Against scipy's distance matrix over the whole window (every member, not a sample)."""
+    from scipy.spatial.distance import cdist
+    from oracle import approximate_seed
+    X = _collection(6000, 64, seed=8)
+    S = isax(paa(X))
+    perm, ks = sorted_order(S)
+    off = root_offsets(ks)
+    Q, _, _ = synth.noisy_queries(X, 12, seed=9, sigma=(0.2, 0.8))
+    windows = [seed_window(query_summary(q), ks, 4, "root16", seed_cap=1500, off=off) for q in Q]
+    windows += [seed_window(query_summary(q), ks, 4, "equal_count", n_leaves=4) for q in Q]
+    for q, (a, b) in zip(list(Q) + list(Q), windows):
+        members = perm[a:b]
+        d = cdist(q[None, :].astype(np.float64), X[members].astype(np.float64), "sqeuclidean")[0]
+        j = np.lexsort((members, d))[0]
+        i, d2 = approximate_seed(q, X, members)
+        assert i == members[j] and d2 == pytest.approx(d[j], rel=1e-12)
+        # the seed bounds the exact answer from above
+        assert d2 >= nn_bruteforce(q, X)[1]
+
+
+def _knn_refined_closed_form(q, X, S, k, a, b, perm):
+    """Refined rows of the k-NN twin, from its definition: candidates outside the window are
+    taken in ascending (bound, index); the k-th best before candidate t is the k-th smallest of
+    the window's distances and the FULL distances of every earlier candidate (a pruned or
+    abandoned candidate is farther than the k-th best, so adding it never changes that order
+    statistic); candidate t is refined iff its bound does not exceed that value."""
+    import heapq
+    from oracle import ed_sq
+    n = X.shape[1]
+    lb = lower_bound_sq(query_summary(q).paa[None, :], S, n // 16)
+    d_all = ed_sq(q, X)
+    window = set(int(m) for m in perm[a:b])
+    heap = [-float(d_all[m]) for m in window]          # max-heap of the k smallest
+    heapq.heapify(heap)
+    while len(heap) > k:
+        heapq.heappop(heap)
+    refined = 0
+    for i in np.lexsort((np.arange(X.shape[0]), lb)):
+        i = int(i)
+        if i in window:
+            continue
+        kth = -heap[0] if len(heap) >= k else np.inf
+        if not (lb[i] > kth * (1.0 + 1e-9) + 1e-12):
+            refined += 1
+        heapq.heappush(heap, -float(d_all[i]))
+        if len(heap) > k:
+            heapq.heappop(heap)
+    return refined
+
+
+@pytest.mark.parametrize("k", [1, 4, 16])
+def test_knn_twin_refined_count_closed_form(k):
+    from oracle import exact_search_knn
+    X = _collection(1200, 64, seed=10)
+    S = isax(paa(X))
+    perm, ks = sorted_order(S)
+    off = root_offsets(ks)
+    Q, _, _ = synth.noisy_queries(X, 4, seed=11, sigma=(0.1, 0.7))
+    Q = np.concatenate([Q, synth.fresh_walk_queries(2, 64, seed=12)])
+    for q in Q:
+        a, b = seed_window(query_summary(q), ks, 4, "root16", seed_cap=32, off=off)
+        _, _, refined = exact_search_knn(q, X, k, S, seed_cap=32)
+        assert refined == _knn_refined_closed_form(q, X, S, k, a, b, perm)
+        assert refined < X.shape[0] - (b - a)      # the bound prunes something
