@@ -46,7 +46,9 @@ void make_plan(long long N, Plan* p)
     p->t8 = take(kSeg * kSym * 4);
     p->t5 = take(kSeg * kCoarse * 4);
     p->surv = take((size_t)N * 8);
-    p->done = take((size_t)N * 8);
+    // every survivor completes at most once, plus the head survivor computed first (it is also
+    // met again in the list): N + 1 entries
+    p->done = take((size_t)(N + 1) * 8);
     p->total = off;
     p->keys_alt = p->surv;  // 8N bytes
     p->perm_alt = p->done;  // 4N bytes
@@ -224,7 +226,7 @@ QueryArgs args_for(const paris_index* h)
     a.surv = reinterpret_cast<uint2*>(ws + h->plan.surv);
     a.surv_cap = (uint32_t)h->N;
     a.done = reinterpret_cast<uint2*>(ws + h->plan.done);
-    a.done_cap = (uint32_t)h->N;
+    a.done_cap = (uint32_t)h->N + 1u;
     a.mg = h->mg;
     a.host_res = nullptr;
     a.leaf_keys = nullptr;
