@@ -141,6 +141,29 @@ paris_status paris_query_exact(paris_index *idx, const float *query_dev, int64_t
                                double *nn_dist, paris_stats *stats, void *hip_stream);
 
 /*
+ * Allocation-free variant of paris_query_exact, for callers that cannot allocate device memory
+ * while they run: code under HIP graph capture, tight serving loops, harnesses that forbid
+ * allocation. Same arguments, outputs, answer and synchrony as paris_query_exact. The per-query
+ * scratch (query state, lower-bound tables, survivor list, completed-candidate list) is taken
+ * from one library-held device array of at most 20 MiB per GPU (a static device array of the
+ * library's code object, held by each GPU it runs on until the process ends) instead of the
+ * index workspace; the call allocates and frees nothing.
+ *   Limits: at most PARIS_NOALLOC_MAX_SURVIVORS series may survive the lower-bound scan and at
+ *   most PARIS_NOALLOC_MAX_COMPLETED completed distances may fall in the float64 resolve band
+ *   (only exact or near ties reach it). A query beyond either returns PARIS_EOVERFLOW with the
+ *   outputs untouched (paris_query_exact, whose lists hold n_series entries, answers it). An
+ *   index of at most PARIS_NOALLOC_MAX_SURVIVORS series can never exceed the first limit.
+ *   The index's device must be the current device (else PARIS_EINVAL).
+ *   The array is shared by every index on that GPU and keeps the last call's contents (each call
+ *   first resets the state it needs): calls that overlap on one GPU (other streams, other host
+ *   threads) race and must be serialised by the caller. Timing (paris_set_timing) is ignored.
+ */
+#define PARIS_NOALLOC_MAX_SURVIVORS (1u << 21)
+#define PARIS_NOALLOC_MAX_COMPLETED (1u << 18)
+paris_status paris_query_exact_noalloc(paris_index *idx, const float *query_dev, int64_t *nn_index,
+                                       double *nn_dist, paris_stats *stats, void *hip_stream);
+
+/*
  * Exact 1-NN of n_queries queries.
  *   queries_dev   float32 [n_queries][length] on the device, finite.
  *   nn_index_dev  int64 [n_queries] device out;  nn_dist_dev  float64 [n_queries] device out.

@@ -113,6 +113,23 @@ class Index:
             return int(self._idx.value), float(self._dist.value), st.as_dict()
         return int(self._idx.value), float(self._dist.value)
 
+    def query_noalloc(self, q, stream=None, with_stats: bool = False):
+        """As ``query``, through paris_query_exact_noalloc: the per-query scratch comes from the
+        library's static device array (no allocation; at most 2^21 lower-bound survivors, else
+        ParisError with PARIS_EOVERFLOW)."""
+        torch = self._torch
+        _dev_ptr(q, torch.float32, 1, "query")
+        if q.shape[0] != self.length:
+            raise ValueError("query length differs from the collection's")
+        st = ParisStats() if with_stats else None
+        s = stream.cuda_stream if stream is not None else _current_stream(self._dev)
+        check(load_library().paris_query_exact_noalloc(self._h, q.data_ptr(), self._idx_ref, self._dist_ref,
+                                                       ctypes.byref(st) if with_stats else None, s),
+              "paris_query_exact_noalloc")
+        if with_stats:
+            return int(self._idx.value), float(self._dist.value), st.as_dict()
+        return int(self._idx.value), float(self._dist.value)
+
     def query_batch(self, Q, stream=None, with_stats: bool = False, out=None):
         """Exact 1-NN of every row of Q (float32 [M, length] on the device).
 

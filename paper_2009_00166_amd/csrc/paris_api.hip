@@ -305,11 +305,36 @@ paris_status collect_pending(paris_index* h)
     return PARIS_OK;
 }
 
+// Per-query scratch taken from somewhere other than the index workspace (the allocation-free
+// entry point): query state, lower-bound tables, survivor and completed-candidate lists.
+struct QueryScratch {
+    QState* qs;
+    float* t8;
+    float* t5;
+    uint2* surv;
+    uint32_t surv_cap;
+    uint2* done;
+    uint32_t done_cap;
+};
+
 paris_status run_query(paris_index* h, const float* q, hipStream_t st, long long* out_idx,
-                       double* out_dist, long long qi, bool timed, QResult* host_res = nullptr)
+                       double* out_dist, long long qi, bool timed, QResult* host_res = nullptr,
+                       const QueryScratch* scratch_in = nullptr)
 {
     QueryArgs a = args_for(h);
     a.host_res = host_res;
+    if (scratch_in) {
+        a.qs = scratch_in->qs;
+        a.t8 = scratch_in->t8;
+        a.t5 = scratch_in->t5;
+        a.surv = scratch_in->surv;
+        a.surv_cap = scratch_in->surv_cap;
+        a.done = scratch_in->done;
+        a.done_cap = scratch_in->done_cap;
+        // the array keeps whatever the previous call on this device left: start from a clean
+        // state (a kernel, not a memset, so the sequence stays capturable)
+        HIP_TRY(launch_reset(a, st));
+    }
     int set = 0;
     const bool all = h->timing_mode == 1;
     if (timed) {
@@ -1117,18 +1142,15 @@ paris_status paris_get_layout(const paris_index* h, paris_layout* o)
     return PARIS_OK;
 }
 
-paris_status paris_query_exact(paris_index* h, const float* query_dev, int64_t* nn_index, double* nn_dist,
-                               paris_stats* stats, void* hip_stream)
+}  // extern "C"
+
+namespace {
+
+// Waits for the result of the query just launched on st (it lands in the index's mapped host
+// buffer) and copies it out.
+paris_status finish_query(paris_index* h, hipStream_t st, int64_t* nn_index, double* nn_dist, paris_stats* stats)
 {
-    if (!handle_ok(h)) return PARIS_ESTATE;
-    if (!query_dev || !nn_index || !nn_dist || reinterpret_cast<uintptr_t>(query_dev) % 16 != 0)
-        return PARIS_EINVAL;
-    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
     volatile long long* flag = &h->host_res->idx;
-    *flag = -2;  // overwritten by the resolve, last of the result's fields
-    const bool timed = h->timing && (h->timing_mode != 3 || (h->timing_calls++ % kTimingEvery) == 0);
-    paris_status s = run_query(h, query_dev, st, nullptr, nullptr, 0, timed, h->host_res_dev);
-    if (s != PARIS_OK) return s;
     // The result lands in mapped host memory: wait for it there (a stream synchronisation costs
     // a few microseconds more). Every 1024 polls the stream is asked whether it failed or
     // drained without producing the result.
@@ -1151,6 +1173,94 @@ paris_status paris_query_exact(paris_index* h, const float* query_dev, int64_t* 
     *nn_dist = std::sqrt(r.d2);
     if (stats) fill_stats(r, stats);
     return PARIS_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+paris_status paris_query_exact(paris_index* h, const float* query_dev, int64_t* nn_index, double* nn_dist,
+                               paris_stats* stats, void* hip_stream)
+{
+    if (!handle_ok(h)) return PARIS_ESTATE;
+    if (!query_dev || !nn_index || !nn_dist || reinterpret_cast<uintptr_t>(query_dev) % 16 != 0)
+        return PARIS_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    *reinterpret_cast<volatile long long*>(&h->host_res->idx) = -2;  // the resolve writes it last
+    const bool timed = h->timing && (h->timing_mode != 3 || (h->timing_calls++ % kTimingEvery) == 0);
+    paris_status s = run_query(h, query_dev, st, nullptr, nullptr, 0, timed, h->host_res_dev);
+    if (s != PARIS_OK) return s;
+    return finish_query(h, st, nn_index, nn_dist, stats);
+}
+
+}  // extern "C"
+
+// ---- allocation-free per-query entry point ----------------------------------------------
+// The per-query scratch of paris_query_exact_noalloc lives in one file-scope device array per
+// GPU (the code object's copy on that device), never allocated or freed by any call.
+namespace {
+constexpr size_t na_align(size_t v) { return (v + 255) & ~(size_t)255; }
+constexpr size_t kNaSurvCap = (size_t)PARIS_NOALLOC_MAX_SURVIVORS;
+constexpr size_t kNaDoneCap = (size_t)PARIS_NOALLOC_MAX_COMPLETED;
+constexpr size_t kNaQs = 0;
+constexpr size_t kNaT8 = na_align(kNaQs + sizeof(QState));
+constexpr size_t kNaT5 = na_align(kNaT8 + (size_t)kSeg * kSym * 4);
+constexpr size_t kNaSurv = na_align(kNaT5 + (size_t)kSeg * kCoarse * 4);
+constexpr size_t kNaDone = na_align(kNaSurv + kNaSurvCap * 8);
+constexpr size_t kNaBytes = na_align(kNaDone + kNaDoneCap * 8);
+static_assert(kNaBytes <= ((size_t)20 << 20), "the allocation-free scratch stays below 20 MiB");
+}  // namespace
+
+static __device__ __align__(256) uint8_t scratch[kNaBytes];
+
+namespace {
+constexpr int kNaMaxDevices = 64;
+std::mutex g_na_mu;
+uint8_t* g_na_ptr[kNaMaxDevices] = {};   // device address of `scratch` on each GPU
+
+// Device address of this GPU's copy of the scratch array (looked up once per device, with that
+// device current; the array's host-side name is not a device address).
+paris_status noalloc_scratch(int dev, uint8_t** out)
+{
+    if (dev < 0 || dev >= kNaMaxDevices) return PARIS_ENODEV;
+    std::lock_guard<std::mutex> g(g_na_mu);
+    if (!g_na_ptr[dev]) {
+        void* p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return PARIS_EHIP;
+        g_na_ptr[dev] = static_cast<uint8_t*>(p);
+    }
+    *out = g_na_ptr[dev];
+    return PARIS_OK;
+}
+}  // namespace
+
+extern "C" {
+
+paris_status paris_query_exact_noalloc(paris_index* h, const float* query_dev, int64_t* nn_index,
+                                       double* nn_dist, paris_stats* stats, void* hip_stream)
+{
+    if (!handle_ok(h)) return PARIS_ESTATE;
+    if (!query_dev || !nn_index || !nn_dist || reinterpret_cast<uintptr_t>(query_dev) % 16 != 0)
+        return PARIS_EINVAL;
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess) return PARIS_EHIP;
+    if (dev != h->device) return PARIS_EINVAL;   // the index's device must be current
+    uint8_t* base = nullptr;
+    paris_status ps = noalloc_scratch(dev, &base);
+    if (ps != PARIS_OK) return ps;
+    QueryScratch sc;
+    sc.qs = reinterpret_cast<QState*>(base + kNaQs);
+    sc.t8 = reinterpret_cast<float*>(base + kNaT8);
+    sc.t5 = reinterpret_cast<float*>(base + kNaT5);
+    sc.surv = reinterpret_cast<uint2*>(base + kNaSurv);
+    sc.surv_cap = (uint32_t)kNaSurvCap;
+    sc.done = reinterpret_cast<uint2*>(base + kNaDone);
+    sc.done_cap = (uint32_t)kNaDoneCap;
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    *reinterpret_cast<volatile long long*>(&h->host_res->idx) = -2;
+    paris_status s = run_query(h, query_dev, st, nullptr, nullptr, 0, false, h->host_res_dev, &sc);
+    if (s != PARIS_OK) return s;
+    return finish_query(h, st, nn_index, nn_dist, stats);
 }
 
 paris_status paris_query_batch(paris_index* h, const float* queries_dev, int64_t n_queries, int64_t* nn_index_dev,
