@@ -19,7 +19,7 @@ def build(force: bool = True) -> str:
     """Compile the C oracle with gcc (-O2, no floating-point contraction)."""
     if force or not os.path.exists(LIB):
         tmp = LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c99",
+        subprocess.check_call(["gcc", "-O2", "-ffp-contract=off", "-fno-fast-math", "-std=c11",
                                "-fPIC", "-shared", "-o", tmp, SRC, "-lpthread", "-lm"])
         os.replace(tmp, LIB)
     return LIB
@@ -39,6 +39,10 @@ def lib():
         L.orc_nn_many.argtypes = [P, i64, P, i64, i32, i32, P, P]
         L.orc_nn_many.restype = ctypes.c_int
         L.orc_lb2.argtypes = [P, P, i64, i32, i32, P, P]
+        L.orc_nn_many_blocked.argtypes = [P, i64, P, i64, i32, i32, P, P]
+        L.orc_nn_many_blocked.restype = ctypes.c_int
+        L.orc_exact_search.argtypes = [P, P, i64, i32, P, i32, P, i64, P, P, P, P, P]
+        L.orc_exact_search.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -85,6 +89,61 @@ def nn_many(Q: np.ndarray, X: np.ndarray, threads: int = 1):
     d2 = np.empty(M, np.float64)
     used = lib().orc_nn_many(_p(Q), M, _p(X), X.shape[0], X.shape[1], threads, _p(idx), _p(d2))
     return idx, d2, max(1, used)
+
+
+def nn_many_blocked(Q: np.ndarray, X: np.ndarray, threads: int = 1):
+    """As ``nn_many`` (bit-identical results), eight queries per pass over the collection."""
+    Q = np.ascontiguousarray(Q, dtype=np.float32)
+    if not (X.dtype == np.float32 and X.flags.c_contiguous):
+        raise ValueError("X must be C-contiguous float32")
+    M = Q.shape[0]
+    idx = np.empty(M, np.int64)
+    d2 = np.empty(M, np.float64)
+    used = lib().orc_nn_many_blocked(_p(Q), M, _p(X), X.shape[0], X.shape[1], threads, _p(idx), _p(d2))
+    return idx, d2, max(1, used)
+
+
+class SearchIndex:
+    """What the serial exact-search twin needs besides the raw series: the iSAX words and the
+    leaf order the approximate search walks (computed by the numpy oracle, once)."""
+
+    def __init__(self, X: np.ndarray, sym: np.ndarray | None = None, mode: str = "root16",
+                 seed_cap: int = 16384, n_leaves: int = 4096):
+        from .reference import root_offsets, sorted_order
+        if not (X.dtype == np.float32 and X.flags.c_contiguous):
+            raise ValueError("X must be C-contiguous float32")
+        self.X = X
+        self.sym = np.ascontiguousarray(summarise(X)[1] if sym is None else sym, dtype=np.uint8)
+        self.perm, self.keys = sorted_order(self.sym)
+        self.off = root_offsets(self.keys) if mode == "root16" else None
+        self.mode, self.seed_cap, self.n_leaves = mode, seed_cap, n_leaves
+
+    def members(self, q: np.ndarray) -> np.ndarray:
+        from .reference import query_summary, seed_window
+        qs = query_summary(np.asarray(q, np.float32))
+        a, b = seed_window(qs, self.keys, self.X.shape[1] // 16, self.mode, self.seed_cap,
+                           self.n_leaves, off=self.off)
+        return np.ascontiguousarray(self.perm[a:b], dtype=np.int64), qs.paa
+
+
+def exact_search(q: np.ndarray, ix: "SearchIndex", members=None):
+    """Serial exact-search twin in C (one thread); returns (index, squared distance, counters)
+    with counters seed_index, lb_survivors, refined, abandoned, bsf_updates. ``members`` (the
+    approximate search's leaf and the query PAA) may be passed precomputed."""
+    q = np.ascontiguousarray(q, dtype=np.float32)
+    mem, qpaa = ix.members(q) if members is None else members
+    qpaa = np.ascontiguousarray(qpaa, dtype=np.float64)
+    beta = np.ascontiguousarray(breakpoints())
+    oi = ctypes.c_int64(-1)
+    od = ctypes.c_double(0.0)
+    cnt = np.zeros(5, np.int64)
+    N, n = ix.X.shape
+    rc = lib().orc_exact_search(_p(q), _p(ix.X), N, n, _p(ix.sym), 16, _p(mem), mem.shape[0], _p(qpaa),
+                                _p(beta), ctypes.byref(oi), ctypes.byref(od), _p(cnt))
+    if rc != 0:
+        raise MemoryError("orc_exact_search")
+    keys = ("seed_index", "lb_survivors", "refined", "abandoned", "bsf_updates")
+    return int(oi.value), float(od.value), dict(zip(keys, (int(v) for v in cnt)))
 
 
 def lb2(qpaa: np.ndarray, sym: np.ndarray, L: int) -> np.ndarray:

@@ -210,3 +210,41 @@ def test_knn_twin_refined_count_closed_form(k):
         _, _, refined = exact_search_knn(q, X, k, S, seed_cap=32)
         assert refined == _knn_refined_closed_form(q, X, S, k, a, b, perm)
         assert refined < X.shape[0] - (b - a)      # the bound prunes something
+
+
+# ---- the C oracle's eight-queries-per-pass brute force and its serial exact-search twin ------
+@pytest.mark.parametrize("M", [1, 3, 8, 9, 17])
+def test_c_brute_force_blocked_is_bit_identical(oracle_native, M):
+    X = _collection(1500, 128, seed=31)
+    X[900] = X[33]                       # an exact tie: the lower index must win in both
+    Q, _, _ = synth.noisy_queries(X, M, seed=M, sigma=(0.05, 0.6))
+    Q[0] = X[33]
+    a_i, a_d, _ = oracle_native.nn_many(Q, X, threads=2)
+    b_i, b_d, _ = oracle_native.nn_many_blocked(Q, X, threads=2)
+    assert np.array_equal(a_i, b_i) and np.array_equal(a_d.view(np.uint64), b_d.view(np.uint64))
+    assert b_i[0] == 33 and b_d[0] == 0.0
+
+
+@pytest.mark.parametrize("mode", ["root16", "equal_count"])
+def test_c_exact_search_twin_equals_numpy_twin_and_brute_force(oracle_native, mode):
+    """The serial C twin takes the same steps as the numpy twin: same answer, seed and counters
+    (survivors, refined, abandoned, updates), and the brute-force answer."""
+    X = _collection(3000, 256, seed=32)
+    X[2500] = X[40]
+    S = isax(paa(X))
+    Q, _, _ = synth.noisy_queries(X, 10, seed=5, sigma=(0.05, 0.6))
+    Q = np.concatenate([Q, synth.fresh_walk_queries(3, 256, seed=6), X[40:41]])
+    ix = oracle_native.SearchIndex(X, S, mode=mode, seed_cap=256, n_leaves=16)
+    for q in Q:
+        i, d2, st = oracle_native.exact_search(q, ix)
+        j, e2, ref = exact_search(q, X, S, mode=mode, seed_cap=256, n_leaves=16)
+        assert (i, d2) == (j, e2) == nn_bruteforce(q, X)[:2]
+        assert st == {"seed_index": ref.seed_index, "lb_survivors": ref.lb_survivors,
+                      "refined": ref.refined, "abandoned": ref.abandoned,
+                      "bsf_updates": ref.bsf_updates}
+    # the tie at distance 0 goes to the lower index, and an empty leaf means no seed
+    assert oracle_native.exact_search(X[40], ix)[:2] == (40, 0.0)
+    none = (np.zeros(0, np.int64), paa(Q[0]))
+    i, d2, st = oracle_native.exact_search(Q[0], ix, members=none)
+    assert (i, d2) == nn_bruteforce(Q[0], X)[:2] and st["seed_index"] == -1
+    assert st["lb_survivors"] == 3000
