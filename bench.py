@@ -5,13 +5,20 @@ prepare -> approximate-search seed -> lower-bound scan -> early-abandoning refin
 resolve, one query at a time with its result back on the host), over an index built once before
 the timed region (the build time is reported beside). Inputs are resident in HBM before timing.
 
+Beside the headline the default run records: the scan cold (caches swept before every query);
+the best-so-far sharing ablation on hard queries (with the refine kernel's bytes per second);
+batches of 4096 through the batched pipeline (paris_query_batch) with a brute-force check of 64
+of their answers; the CPU oracle (brute force over all host threads, and on one thread the
+median latency of brute force and of the serial exact-search twin over 20 queries); the learned
+seed on 50,000,000 x 256 with 4096 equal-count leaves; and the mixed-length workload
+(100M x 128 + 20M x 512 + 5M x 1024 in one call per batch of 2048).
+
 Prints one JSON line. Options: --gpus N (only 1 is supported: the benchmark measures one GPU),
 --steps K, --warmup W, --queries Q, --series N, --length n, --fresh-queries (new random walks
-as queries, the paper's workload), --no-cpu-baseline, --no-batched,
---batch B, --batch-steps K (the batched section: batches of B queries through paris_query_batch),
---cold-queries C (the lower-bound scan timed with caches flushed before each of C queries),
---no-learned, --train-queries T, --epochs E, --eval-queries V (the learned-seed section: a seed
-network trained on T exact labels, evaluated on V hard queries and in the batched pipeline).
+as queries, the paper's workload), --no-cpu-baseline, --cpu-single S, --oracle-check C,
+--no-batched, --batch B, --batch-steps K, --cold-queries C, --no-nb-ablation, --no-learned,
+--learned-series N (0: the main collection), --train-queries T, --epochs E, --eval-queries V,
+--learned-only, --multi (only the mixed-length workload), --no-multi, --multi-scale F.
 """
 from __future__ import annotations
 
@@ -67,8 +74,23 @@ def measured_traffic(kernel: str):
     return float(vals["traffic_bytes_per_launch"])
 
 
-def cpu_baseline(X, Q, gpu_idx, n_queries: int, threads: int):
-    """The C oracle (brute force, float64) on a bounded sample of the same workload."""
+def cpu_model() -> str:
+    try:
+        for ln in open("/proc/cpuinfo"):
+            if ln.startswith("model name"):
+                return ln.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(X, Q, gpu_idx, n_queries: int, threads: int, single: int):
+    """The C oracle on bounded samples of the same workload: brute force (float64, the
+    definition) over all host threads, then on one thread the median latency of brute force and
+    of the serial exact-search twin (ExactSearch with its lower-bound and distance workers,
+    Section 3.3.3, run by one thread: approximate-search seed, float64 lower bound of every
+    series, sorted candidates, early-abandoning distances), over ``single`` queries each."""
+    import statistics
     import numpy as np
     from oracle import native
     native.build(force=False)
@@ -77,11 +99,44 @@ def cpu_baseline(X, Q, gpu_idx, n_queries: int, threads: int):
     ri, rd, used = native.nn_many(sample, X, threads=threads)
     dt = time.perf_counter() - t0
     agrees = bool(np.array_equal(ri, np.asarray(gpu_idx[:n_queries])))
+    log(f"cpu oracle: {n_queries} brute-force queries in {dt:.1f}s on {used} threads")
+    bf_ms, tw_ms, tw_ok = [], [], True
+    for m in range(single):
+        t1 = time.perf_counter()
+        i, _, _ = native.nn_many(Q[m:m + 1], X, threads=1)
+        bf_ms.append((time.perf_counter() - t1) * 1e3)
+        tw_ok &= int(i[0]) == int(gpu_idx[m])
+    log(f"cpu oracle: {single} single-thread brute-force queries, median {statistics.median(bf_ms):.0f} ms")
+    t2 = time.perf_counter()
+    ix = native.SearchIndex(X)
+    prep_s = time.perf_counter() - t2
+    counters = []
+    for m in range(single):
+        mem = ix.members(Q[m])     # leaf lookup (numpy), outside the timed call
+        t1 = time.perf_counter()
+        i, _, st = native.exact_search(Q[m], ix, members=mem)
+        tw_ms.append((time.perf_counter() - t1) * 1e3)
+        tw_ok &= i == int(gpu_idx[m])
+        counters.append(st)
+    log(f"cpu oracle: {single} single-thread exact-search twin queries, median {statistics.median(tw_ms):.0f} ms")
+    mean = lambda k: float(np.mean([c[k] for c in counters]))
     return {"value": n_queries / dt, "unit": "queries/s", "cores": int(used), "kind": "oracle",
             "sample": f"first {n_queries} of the {Q.shape[0]} queries against the full "
                       f"{X.shape[0]}x{X.shape[1]} collection, brute-force float64 C oracle "
                       f"(-O2, no FMA), queries split over {used} threads",
-            "seconds": dt, "answers_agree_with_gpu": agrees}
+            "seconds": dt, "answers_agree_with_gpu": agrees,
+            "host": {"cpu_count": os.cpu_count(), "model": cpu_model(), "threads_used": int(used)},
+            "single_thread": {
+                "queries": single,
+                "brute_force_median_ms": statistics.median(bf_ms),
+                "exact_search_twin_median_ms": statistics.median(tw_ms),
+                "twin_mean_lb_survivors": mean("lb_survivors"), "twin_mean_refined": mean("refined"),
+                "twin_index_prep_s": prep_s,
+                "answers_agree_with_gpu": bool(tw_ok),
+                "note": "one thread each; brute force = the definition (every distance in float64); "
+                        "twin = serial C ExactSearch (seed over the approximate search's leaf, float64 "
+                        "lower bound of every series, candidates sorted by bound, early abandoning); "
+                        "its words and leaf order are prepared once by the numpy oracle (twin_index_prep_s)"}}
 
 
 def bsf_sharing_ablation(index, X, n: int, count: int = 200):
@@ -104,8 +159,26 @@ def bsf_sharing_ablation(index, X, n: int, count: int = 200):
         qps = count / (time.perf_counter() - t0)
         st = [index.query(r, with_stats=True)[2] for r in rows]
         mean = lambda k: float(np.mean([x[k] for x in st]))
+        # one more pass with events between the phases: the refine + resolve kernel's time
+        index.set_timing(True)
+        for r in rows:
+            index.query(r)
+        ms, k = index.timing()
+        index.set_timing(False)
+        ref_ms = ms[2] / max(k, 1)
+        row_bytes = 4 * n            # a refined row is read in 1 KiB pieces: the whole row at n <= 256
+        read = mean("refined") * row_bytes
         return {"queries_per_s": qps, "mean_lb_survivors": mean("lb_survivors"),
-                "mean_refined": mean("refined"), "mean_abandoned": mean("abandoned")}, got
+                "mean_refined": mean("refined"), "mean_abandoned": mean("abandoned"),
+                "mean_bsf_updates": mean("bsf_updates"),
+                "mean_raw_bytes_read": read,
+                "refine_roofline": {"bound": "hbm", "kernel": "k_refine_resolve",
+                                    "bytes_per_launch": read, "avg_launch_ms": ref_ms,
+                                    "achieved": read / (ref_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBPS,
+                                    "unit": "GB/s", "frac": read / (ref_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                                    "note": "bytes = refined rows x 4n (rows are loaded whole for n <= 256, "
+                                            "abandoned or not); time from events recorded around the "
+                                            "refine + resolve launch (includes its dispatch gap)"}}, got
 
     # alternate the modes twice and keep each one's faster pass, so neither gains from going last
     res = {True: [], False: []}
@@ -138,6 +211,10 @@ def main() -> int:
                     help="skip the best-so-far sharing ablation (shared vs private copies, hard queries)")
     ap.add_argument("--cpu-queries", type=int, default=16)
     ap.add_argument("--cpu-threads", type=int, default=16)
+    ap.add_argument("--cpu-single", type=int, default=20,
+                    help="queries timed on one thread (brute force and the serial exact-search twin)")
+    ap.add_argument("--oracle-check", type=int, default=64,
+                    help="batched answers checked against the brute-force oracle per batch record")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch", type=int, default=4096)
@@ -147,11 +224,13 @@ def main() -> int:
     ap.add_argument("--train-queries", type=int, default=200_000)
     ap.add_argument("--epochs", type=int, default=20)
     ap.add_argument("--eval-queries", type=int, default=1000)
-    ap.add_argument("--learned-series", type=int, default=0,
+    ap.add_argument("--learned-series", type=int, default=50_000_000,
                     help="collection size of the learned-seed section (0: the main collection)")
     ap.add_argument("--learned-only", action="store_true", help="run only the learned-seed section")
     ap.add_argument("--multi", action="store_true",
-                    help="the mixed-length workload instead: 100M x 128 + 20M x 512 + 5M x 1024")
+                    help="only the mixed-length workload: 100M x 128 + 20M x 512 + 5M x 1024")
+    ap.add_argument("--no-multi", action="store_true",
+                    help="skip the mixed-length sub-record of the default run")
     ap.add_argument("--multi-scale", type=float, default=1.0,
                     help="fraction of the mixed-length collections' sizes (1.0 = full)")
     args = ap.parse_args()
@@ -271,6 +350,9 @@ def main() -> int:
                    "seed_cap": 16384},
         "roofline": {"bound": "hbm", "kernel": "k_lbscan", "achieved": achieved,
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
+                     "cache_resident": bool(lb_bytes < 256e6),
+                     "achieved_cold": cold["achieved_GBps"] if cold else None,
+                     "frac_cold": cold["frac"] if cold else None,
                      # the committed counter summary covers the 10M x 256 launch only
                      "traffic": measured_traffic("k_lbscan") if (N, n) == (10_000_000, 256) else None,
                      "bytes_per_launch": lb_bytes, "avg_launch_ms": lb_ms,
@@ -278,7 +360,10 @@ def main() -> int:
                              "events bound to the scan kernel's dispatch (every 8th query of the timed "
                              "region); phases_ms_per_query.lbscan adds the dispatch gap before the "
                              f"kernel; the {lb_bytes / 1e6:g} MB array "
-                             + ("fits" if lb_bytes < 256e6 else "exceeds") + " the 256 MB Infinity Cache"},
+                             + ("fits the 256 MB Infinity Cache, so the timed-region figure is cache-resident "
+                                "(achieved_cold / frac_cold: the same kernel after a 1 GiB read-only sweep "
+                                "before every query, i.e. streamed from HBM)" if lb_bytes < 256e6
+                                else "exceeds the 256 MB Infinity Cache (streamed from HBM)")},
         "lbscan_cold": cold,
         "phases_ms_per_query": dict(zip(["prepare_seed", "lbscan", "refine_resolve"],
                                         [p / max(phased, 1) for p in phase_ms])),
@@ -291,18 +376,33 @@ def main() -> int:
     }
     if not args.no_batched:
         rec["batched"] = batched_section(index, X, args)
+    if not args.no_cpu_baseline:
+        log("timing the CPU oracle on a sample")
+        rec["cpu_baseline"] = cpu_baseline(X, Q, answers, min(args.cpu_queries, M), args.cpu_threads,
+                                           min(args.cpu_single, M))
     if not args.no_learned:
         if args.learned_series and args.learned_series != N:
             index.close()   # frees the library state; the workspace goes with the object
+            del index, Xd, rows, Qd
+            torch.cuda.empty_cache()
             XL = synth.random_walks(args.learned_series, n, seed=0, threads=16)
-            rec["learned"] = learned_section(torch.from_numpy(XL).to(dev), XL, args)
+            log(f"generated the {args.learned_series} x {n} learned-seed collection")
+            XLd = torch.from_numpy(XL).to(dev)
+            rec["learned"] = learned_section(XLd, XL, args)
+            del XL, XLd
+            torch.cuda.empty_cache()
         else:
             rec["learned"] = learned_section(Xd, X, args)
-    if not args.no_cpu_baseline:
-        log("timing the CPU oracle on a sample")
-        rec["cpu_baseline"] = cpu_baseline(X, Q, answers, min(args.cpu_queries, M), args.cpu_threads)
+            index.close()
+    else:
+        index.close()
+    if not args.no_multi and not args.fresh_queries and (N, n) == (10_000_000, 256):
+        # the mixed-length workload as a sub-record of the default run
+        index = None
+        Xd = rows = Qd = None
+        torch.cuda.empty_cache()
+        rec["mixed_lengths"] = multi_section(args)
     print(json.dumps(rec), flush=True)
-    index.close()
     return 0
 
 
@@ -346,7 +446,7 @@ def batched_section(index, X, args):
     t0 = time.perf_counter()
     ws_bytes = index.attach_batch(max_batch=B)
     attach_s = time.perf_counter() - t0
-    Qb, src, _ = synth.noisy_queries(X, B, seed=1, sigma=(0.01, 0.5))
+    Qb, src, sig = synth.noisy_queries(X, B, seed=1, sigma=(0.01, 0.5))
     Qd = torch.from_numpy(Qb).cuda()
     I = torch.empty(B, dtype=torch.int64, device="cuda")
     D = torch.empty(B, dtype=torch.float64, device="cuda")
@@ -400,7 +500,30 @@ def batched_section(index, X, args):
         "fallback_queries": st["resolved"],
         "workspace_bytes": ws_bytes,
         "answers_match_source_frac": float(np.mean(answers == src)),
+        "oracle_check": oracle_check(X, Qb, answers, D.cpu().numpy(), sig, args),
     }
+
+
+def oracle_check(X, Q, I, D, sig, args, seed=0):
+    """Brute-force check of a batch's answers on ``args.oracle_check`` of its queries (a quarter
+    of them the noisiest, the rest at random): indices equal and distances bit-identical."""
+    import numpy as np
+    from oracle import native
+    k = min(args.oracle_check, Q.shape[0])
+    if k == 0 or args.no_cpu_baseline:
+        return None
+    native.build(force=False)
+    order = np.argsort(-np.asarray(sig), kind="stable")
+    hard = k // 4
+    pick = np.sort(np.concatenate([order[:hard], np.random.default_rng(seed).choice(order[hard:], k - hard,
+                                                                                    replace=False)]))
+    t0 = time.perf_counter()
+    ri, rd, used = native.nn_many_blocked(Q[pick], X, threads=args.cpu_threads)
+    dt = time.perf_counter() - t0
+    log(f"oracle check: {k} queries of {X.shape[0]} x {X.shape[1]} in {dt:.1f}s")
+    return {"queries": k, "indices_equal": bool(np.array_equal(ri, np.asarray(I)[pick])),
+            "distances_bit_identical": bool(np.array_equal(np.sqrt(rd), np.asarray(D)[pick])),
+            "selection": f"{hard} noisiest + {k - hard} at random", "seconds": dt}
 
 
 def learned_section(Xd, X, args):
@@ -459,17 +582,17 @@ def learned_section(Xd, X, args):
     a0, plain = per_query(False)
     a1, learned = per_query(True)
     log(f"hard queries: plain {plain['queries_per_s']:.0f} q/s, learned {learned['queries_per_s']:.0f} q/s")
-    oracle_check = None
+    per_query_check = None
     if not args.no_cpu_baseline:
         from oracle import native
         native.build(force=False)
-        k = min(8, len(rows))
-        ri, _, _ = native.nn_many(Qe[:k], X, threads=args.cpu_threads)
-        oracle_check = {"queries": k, "learned_answers_equal_oracle": bool(np.array_equal(ri, np.array(a1[:k]))),
+        k = min(32, len(rows))
+        ri, _, _ = native.nn_many_blocked(Qe[:k], X, threads=args.cpu_threads)
+        per_query_check = {"queries": k, "learned_answers_equal_oracle": bool(np.array_equal(ri, np.array(a1[:k]))),
                         "plain_answers_equal_oracle": bool(np.array_equal(ri, np.array(a0[:k])))}
 
     B = args.batch
-    Qb, _, _ = synth.noisy_queries(X, B, seed=1, sigma=(0.01, 0.5))
+    Qb, _, sigb = synth.noisy_queries(X, B, seed=1, sigma=(0.01, 0.5))
     Qbd = torch.from_numpy(Qb).cuda()
     I = torch.empty(B, dtype=torch.int64, device="cuda")
     D = torch.empty(B, dtype=torch.float64, device="cuda")
@@ -486,8 +609,10 @@ def learned_section(Xd, X, args):
         _, _, st = idx.query_batch(Qbd, out=(I, D), with_stats=True)
         res[enabled] = {"queries_per_s": B * args.batch_steps / el, "ms_per_batch": el / args.batch_steps * 1e3,
                         "screen_survivors_per_query": st["lb_survivors"] / B, "fallback_queries": st["resolved"],
-                        "answers": I.cpu().numpy()}
-    same_batch = bool(np.array_equal(res[False].pop("answers"), res[True].pop("answers")))
+                        "answers": I.cpu().numpy(), "dists": D.cpu().numpy()}
+    same_batch = bool(np.array_equal(res[False].pop("answers"), res[True]["answers"]))
+    res[False].pop("dists")
+    learned_check = oracle_check(X, Qb, res[True].pop("answers"), res[True].pop("dists"), sigb, args, seed=5)
     idx.set_seed_model(None, False)
     net.close()
     idx.close()
@@ -500,8 +625,9 @@ def learned_section(Xd, X, args):
         "loss_last_epoch": hist[-1],
         "hard_queries": {"count": len(rows), "plain_seed": plain, "learned_seed": learned,
                          "answers_identical": bool(np.array_equal(np.array(a0), np.array(a1))),
-                         "oracle_sample": oracle_check},
+                         "oracle_sample": per_query_check},
         "batched": {"plain_seed": res[False], "learned_seed": res[True], "answers_identical": same_batch,
+                    "oracle_check": learned_check,
                     "learned_vs_plain_per_query_path": (res[True]["queries_per_s"] / args._plain_qps
                                                         if args._plain_qps else None)},
     }
@@ -536,11 +662,12 @@ def multi_section(args):
     rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence(7)))
     which = rng.integers(0, 3, size=B)
     counts = [int((which == c).sum()) for c in range(3)]
-    Qs, srcs = [], []
+    Qs, srcs, sigs = [], [], []
     for c, (X, _) in enumerate(Xs):
-        Q, src, _ = synth.noisy_queries(X, counts[c], seed=10 + c, sigma=(0.05, 0.5))
+        Q, src, sig = synth.noisy_queries(X, counts[c], seed=10 + c, sigma=(0.05, 0.5))
         Qs.append(torch.from_numpy(Q).cuda())
         srcs.append(src)
+        sigs.append(sig)
     paris.query_batch_multi(idxs, Qs)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
@@ -600,6 +727,9 @@ def multi_section(args):
         rec["cpu_baseline"] = {"value": len(sample) / dt, "unit": "queries/s", "cores": int(used), "kind": "oracle",
                                "sample": f"4 queries of the 100M x 128 collection, brute-force float64 C oracle",
                                "answers_agree_with_gpu": bool(np.array_equal(ri, outs[0][0][:4].cpu().numpy()))}
+        rec["oracle_check"] = [oracle_check(Xs[c][0], Qs[c].cpu().numpy(), outs[c][0].cpu().numpy(),
+                                            outs[c][1].cpu().numpy(), sigs[c], args, seed=20 + c)
+                               for c in range(3)]
     for ix in idxs:
         ix.close()
     return rec

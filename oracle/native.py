@@ -113,7 +113,16 @@ class SearchIndex:
         if not (X.dtype == np.float32 and X.flags.c_contiguous):
             raise ValueError("X must be C-contiguous float32")
         self.X = X
-        self.sym = np.ascontiguousarray(summarise(X)[1] if sym is None else sym, dtype=np.uint8)
+        if sym is None:   # the numpy oracle's words, row blocks on a thread pool
+            from concurrent.futures import ThreadPoolExecutor
+            from .reference import isax, paa
+            sym = np.empty((X.shape[0], 16), np.uint8)
+
+            def block(a):
+                sym[a:a + 65536] = isax(paa(X[a:a + 65536]))
+            with ThreadPoolExecutor(max_workers=min(16, os.cpu_count() or 1)) as ex:
+                list(ex.map(block, range(0, X.shape[0], 65536)))
+        self.sym = np.ascontiguousarray(sym, dtype=np.uint8)
         self.perm, self.keys = sorted_order(self.sym)
         self.off = root_offsets(self.keys) if mode == "root16" else None
         self.mode, self.seed_cap, self.n_leaves = mode, seed_cap, n_leaves

@@ -91,21 +91,32 @@ def test_batched_pipeline_at_scale(full, oracle_native):
     print(f"[scale] batched: {st['lb_survivors']} screen survivors, {st['resolved']} fallbacks", flush=True)
 
 
+def _oracle_sample(sig, count, hardest, seed):
+    """Indices of the queries checked by brute force: the ``hardest`` with the largest noise and
+    ``count - hardest`` others at random, ascending."""
+    order = np.argsort(-np.asarray(sig), kind="stable")
+    top = order[:hardest]
+    rest = np.random.default_rng(seed).choice(order[hardest:], count - hardest, replace=False)
+    return np.sort(np.concatenate([top, rest]))
+
+
 def test_full_batch_at_scale(full, oracle_native):
     """One whole batch of 4096 uneven-difficulty queries at 10M x 256, the batch size and tuned
-    launch shape the benchmark times: the brute-force oracle's answers on a sample of 32 of its
-    queries; for every query, the returned distance is bit-identical to the oracle's float64
-    distance to the returned series and no larger than the distance to the series the query was
-    made from."""
+    launch shape the benchmark times: the brute-force oracle's answers on 256 of its queries
+    (the 64 with the largest noise, the hardest to prune, and 192 drawn at random); for every
+    query, the returned distance is bit-identical to the oracle's float64 distance to the
+    returned series and no larger than the distance to the series the query was made from."""
     X, index = full["X"], full["index"]
     index.attach_batch(max_batch=4096)
     M = 4096
-    Q, src, _ = synth.noisy_queries(X, M, seed=3, sigma=(0.01, 0.5))
+    Q, src, sig = synth.noisy_queries(X, M, seed=3, sigma=(0.01, 0.5))
     I, D, st = index.query_batch(torch.from_numpy(Q).cuda(), with_stats=True)
     torch.cuda.synchronize()
     I, D = I.cpu().numpy(), D.cpu().numpy()
-    pick = np.sort(np.random.default_rng(3).choice(M, 32, replace=False))
-    ri, rd, _ = oracle_native.nn_many(Q[pick], X, threads=16)
+    pick = _oracle_sample(sig, 256, 64, seed=3)
+    t0 = time.time()
+    ri, rd, _ = oracle_native.nn_many_blocked(Q[pick], X, threads=16)
+    print(f"[scale] oracle: {len(pick)} of the batch's queries in {time.time() - t0:.1f}s", flush=True)
     assert np.array_equal(I[pick], ri)
     assert np.array_equal(D[pick], np.sqrt(rd))
     assert np.all((I >= 0) & (I < N_FULL))

@@ -31,11 +31,11 @@ def paper_full(oracle_native):
     index = paris.build(Xd)
     torch.cuda.synchronize()
     print(f"[scale100] built index at {time.time() - t0:.1f}s", flush=True)
-    Qf = synth.fresh_walk_queries(12, LEN, seed=7)
-    Qn, _, _ = synth.noisy_queries(X, 4, seed=8, sigma=(0.05, 0.5))
+    Qf = synth.fresh_walk_queries(48, LEN, seed=7)
+    Qn, _, _ = synth.noisy_queries(X, 16, seed=8, sigma=(0.05, 0.5))
     Q = np.ascontiguousarray(np.concatenate([Qf, Qn]))
     t1 = time.time()
-    ri, rd, used = oracle_native.nn_many(Q, X, threads=16)
+    ri, rd, used = oracle_native.nn_many_blocked(Q, X, threads=16)
     print(f"[scale100] oracle brute force {Q.shape[0]} queries in {time.time() - t1:.1f}s on {used} "
           "threads", flush=True)
     yield dict(X=X, Xd=Xd, index=index, Q=Q, ri=ri, rd=rd)
