@@ -7,6 +7,7 @@ the timed region (the build time is reported beside). Inputs are resident in HBM
 
 Beside the headline the default run records: the scan cold (caches swept before every query);
 the best-so-far sharing ablation on hard queries (with the refine kernel's bytes per second);
+exact k-NN (k = 10 and 64) on 200 of the queries;
 batches of 4096 through the batched pipeline (paris_query_batch) with a brute-force check of 64
 of their answers; the CPU oracle (brute force over all host threads, and on one thread the
 median latency of brute force and of the serial exact-search twin over 20 queries); the learned
@@ -16,7 +17,7 @@ seed on 50,000,000 x 256 with 4096 equal-count leaves; and the mixed-length work
 Prints one JSON line. Options: --gpus N (only 1 is supported: the benchmark measures one GPU),
 --steps K, --warmup W, --queries Q, --series N, --length n, --fresh-queries (new random walks
 as queries, the paper's workload), --no-cpu-baseline, --cpu-single S, --oracle-check C,
---no-batched, --batch B, --batch-steps K, --cold-queries C, --no-nb-ablation, --no-learned,
+--no-knn, --no-batched, --batch B, --batch-steps K, --cold-queries C, --no-nb-ablation, --no-learned,
 --learned-series N (0: the main collection), --train-queries T, --epochs E, --eval-queries V,
 --learned-only, --multi (only the mixed-length workload), --no-multi, --multi-scale F.
 """
@@ -100,6 +101,14 @@ def cpu_baseline(X, Q, gpu_idx, n_queries: int, threads: int, single: int):
     dt = time.perf_counter() - t0
     agrees = bool(np.array_equal(ri, np.asarray(gpu_idx[:n_queries])))
     log(f"cpu oracle: {n_queries} brute-force queries in {dt:.1f}s on {used} threads")
+    base = {"value": n_queries / dt, "unit": "queries/s", "cores": int(used), "kind": "oracle",
+            "sample": f"first {n_queries} of the {Q.shape[0]} queries against the full "
+                      f"{X.shape[0]}x{X.shape[1]} collection, brute-force float64 C oracle "
+                      f"(-O2, no FMA), queries split over {used} threads",
+            "seconds": dt, "answers_agree_with_gpu": agrees,
+            "host": {"cpu_count": os.cpu_count(), "model": cpu_model(), "threads_used": int(used)}}
+    if single <= 0:
+        return base
     bf_ms, tw_ms, tw_ok = [], [], True
     for m in range(single):
         t1 = time.perf_counter()
@@ -120,13 +129,7 @@ def cpu_baseline(X, Q, gpu_idx, n_queries: int, threads: int, single: int):
         counters.append(st)
     log(f"cpu oracle: {single} single-thread exact-search twin queries, median {statistics.median(tw_ms):.0f} ms")
     mean = lambda k: float(np.mean([c[k] for c in counters]))
-    return {"value": n_queries / dt, "unit": "queries/s", "cores": int(used), "kind": "oracle",
-            "sample": f"first {n_queries} of the {Q.shape[0]} queries against the full "
-                      f"{X.shape[0]}x{X.shape[1]} collection, brute-force float64 C oracle "
-                      f"(-O2, no FMA), queries split over {used} threads",
-            "seconds": dt, "answers_agree_with_gpu": agrees,
-            "host": {"cpu_count": os.cpu_count(), "model": cpu_model(), "threads_used": int(used)},
-            "single_thread": {
+    return {**base, "single_thread": {
                 "queries": single,
                 "brute_force_median_ms": statistics.median(bf_ms),
                 "exact_search_twin_median_ms": statistics.median(tw_ms),
@@ -195,6 +198,43 @@ def bsf_sharing_ablation(index, X, n: int, count: int = 200):
             "passes": "two per mode, alternated; the faster of each mode's passes"}
 
 
+def knn_section(index, X, Q, args, count: int = 200):
+    """Exact k-NN (k = 10 and 64) through paris_query_knn on the first queries of the plain
+    workload: queries/s, counters, and the answers of a few queries against the k-NN by
+    definition (the C oracle's float64 distances ordered by (distance, index))."""
+    import numpy as np
+    import torch
+    Qd = torch.from_numpy(np.ascontiguousarray(Q[:count])).to("cuda:0")
+    rows = [Qd[m] for m in range(Qd.shape[0])]
+    out = {"queries": f"first {len(rows)} queries of the plain workload"}
+    for k in (10, 64):
+        for r in rows[:10]:
+            index.query_knn(r, k)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        got = [index.query_knn(r, k) for r in rows]
+        dt = time.perf_counter() - t0
+        st = [index.query_knn(r, k, with_stats=True)[2] for r in rows[:50]]
+        mean = lambda key: float(np.mean([x[key] for x in st]))
+        rec = {"queries_per_s": len(rows) / dt, "mean_lb_survivors": mean("lb_survivors"),
+               "mean_refined": mean("refined"), "mean_resolved": mean("resolved")}
+        if not args.no_cpu_baseline:
+            from concurrent.futures import ThreadPoolExecutor
+            from oracle import native
+            native.build(force=False)
+            kk = 4
+            with ThreadPoolExecutor(max_workers=kk) as ex:
+                d2s = list(ex.map(lambda q: native.ed2(q, X), Q[:kk]))
+            ok = True
+            for m in range(kk):
+                order = np.lexsort((np.arange(X.shape[0]), d2s[m]))[:k]
+                ok &= bool(np.array_equal(got[m][0], order) and np.array_equal(got[m][1], np.sqrt(d2s[m][order])))
+            rec["oracle_check"] = {"queries": kk, "answers_equal_oracle": ok}
+        out[f"k{k}"] = rec
+        log(f"k-NN k={k}: {rec['queries_per_s']:.0f} queries/s")
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -216,6 +256,7 @@ def main() -> int:
     ap.add_argument("--oracle-check", type=int, default=64,
                     help="batched answers checked against the brute-force oracle per batch record")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-knn", action="store_true", help="skip the exact k-NN sub-record")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--batch-steps", type=int, default=3)
@@ -322,6 +363,7 @@ def main() -> int:
     stats = [index.query(rows[m], with_stats=True)[2] for m in range(min(M, 200))]
     mean = lambda k: float(np.mean([s[k] for s in stats]))
     nb = bsf_sharing_ablation(index, X, n) if args.nb_ablation else None
+    knn = knn_section(index, X, Q, args) if not args.no_knn else None
 
     total_q = M * args.steps
     args._plain_qps = total_q / elapsed
@@ -373,6 +415,7 @@ def main() -> int:
                                                "resolved")},
         "answers_match_source_frac": None if src is None else float(np.mean(answers == src)),
         "bsf_sharing_ablation": nb,
+        "knn": knn,
     }
     if not args.no_batched:
         rec["batched"] = batched_section(index, X, args)

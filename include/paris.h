@@ -141,6 +141,32 @@ paris_status paris_query_exact(paris_index *idx, const float *query_dev, int64_t
                                double *nn_dist, paris_stats *stats, void *hip_stream);
 
 /*
+ * Exact k-NN of one query: the k series nearest to the query (the k-NN classification
+ * experiment of Section 4 uses the k nearest series), in ascending (distance, index) order;
+ * among equal float64 squared distances the lower index comes first.
+ *   k           1 .. 64 (else PARIS_EINVAL).
+ *   nn_index    host out [k]: indices of the answers; nn_dist host out [k]: their Euclidean
+ *               distances (float64 squared distance in the oracle's operation order, correctly
+ *               rounded sqrt).
+ *   n_found     host out: min(k, n_series) answers written.
+ *   stats       optional host out: lb_survivors, refined, abandoned; bsf_updates = times a
+ *               completed distance entered the k best; resolved = candidates re-scored in float64.
+ * The method is the exact search with the k-th best distance in the role of the best-so-far
+ * (Section 3.3.3): the approximate search's window, 16384 sorted positions centred on the query's
+ * leaf key (or the learned seed's leaves), gives the first k-th best (8k of its members, the
+ * smallest-bound ones of every 512 positions in equal numbers, get their distance; the environment
+ * variable PARIS_KNN_SEED = 1 .. 16 sets the 8), the lower-bound scan
+ * keeps the series whose bound does not exceed it, the refinement abandons a distance once its
+ * partial sum passes it while completed distances replace the largest of the k best, and the last
+ * block re-scores in float64 every completed candidate within the rounding band of the final k-th
+ * distance. PARIS_EOVERFLOW if more than 2048 candidates fall in that band (only with massive
+ * exact ties). k = 1 runs paris_query_exact. Synchronous; one call in flight per handle; uses the
+ * learned seed when one is set.
+ */
+paris_status paris_query_knn(paris_index *idx, const float *query_dev, int32_t k, int64_t *nn_index,
+                             double *nn_dist, int32_t *n_found, paris_stats *stats, void *hip_stream);
+
+/*
  * Allocation-free variant of paris_query_exact, for callers that cannot allocate device memory
  * while they run: code under HIP graph capture, tight serving loops, harnesses that forbid
  * allocation. Same arguments, outputs, answer and synchrony as paris_query_exact. The per-query

@@ -113,6 +113,28 @@ class Index:
             return int(self._idx.value), float(self._dist.value), st.as_dict()
         return int(self._idx.value), float(self._dist.value)
 
+    def query_knn(self, q, k: int, stream=None, with_stats: bool = False):
+        """Exact k-NN of one query (float32 [length] on the device), k in 1 .. 64: (indices,
+        distances[, stats]) as numpy arrays of min(k, n_series) entries in ascending (distance,
+        index) order."""
+        import numpy as np
+        torch = self._torch
+        _dev_ptr(q, torch.float32, 1, "query")
+        if q.shape[0] != self.length:
+            raise ValueError("query length differs from the collection's")
+        idx = np.zeros(max(int(k), 1), np.int64)
+        dist = np.zeros(max(int(k), 1), np.float64)
+        found = ctypes.c_int32(0)
+        st = ParisStats() if with_stats else None
+        s = stream.cuda_stream if stream is not None else _current_stream(self._dev)
+        check(load_library().paris_query_knn(self._h, q.data_ptr(), int(k), idx.ctypes.data_as(ctypes.c_void_p),
+                                             dist.ctypes.data_as(ctypes.c_void_p), ctypes.byref(found),
+                                             ctypes.byref(st) if with_stats else None, s), "paris_query_knn")
+        f = found.value
+        if with_stats:
+            return idx[:f].copy(), dist[:f].copy(), st.as_dict()
+        return idx[:f].copy(), dist[:f].copy()
+
     def query_noalloc(self, q, stream=None, with_stats: bool = False):
         """As ``query``, through paris_query_exact_noalloc: the per-query scratch comes from the
         library's static device array (no allocation; at most 2^21 lower-bound survivors, else

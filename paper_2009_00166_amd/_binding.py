@@ -61,6 +61,8 @@ SIGNATURES = [
     ("paris_get_layout", ctypes.c_int, [_P, ctypes.POINTER(ParisLayout)]),
     ("paris_query_exact", ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_int64),
                                          ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ParisStats), _P]),
+    ("paris_query_knn", ctypes.c_int, [_P, _P, _I32, _P, _P, ctypes.POINTER(ctypes.c_int32),
+                                       ctypes.POINTER(ParisStats), _P]),
     ("paris_query_exact_noalloc", ctypes.c_int, [_P, _P, ctypes.POINTER(ctypes.c_int64),
                                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ParisStats), _P]),
     ("paris_query_batch", ctypes.c_int, [_P, _P, _I64, _P, _P, ctypes.POINTER(ParisStats), _P]),

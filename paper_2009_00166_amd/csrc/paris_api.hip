@@ -21,6 +21,9 @@ using namespace paris;
 namespace {
 
 constexpr uint32_t kMagic = 0x50415249u;  // "PARI"
+// mapped host buffer of an index: the query result, then the k-NN answers 256 bytes on
+constexpr size_t kHostResBytes = 256 + kKnnMax * sizeof(KnnHit);
+static_assert(sizeof(QResult) <= 256, "the k-NN answers follow the result at 256 bytes");
 constexpr size_t kAlign = 256;
 
 size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
@@ -28,7 +31,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 // Workspace layout. The radix-sort scratch (alternate keys / positions / histograms) is only
 // needed during the build and aliases the survivor and completed-candidate buffers.
 struct Plan {
-    size_t hdr, sax, saxs, keys, perm, roff, qs, t8, t5, surv, done, total;
+    size_t hdr, sax, saxs, keys, perm, roff, qs, t8, t5, knn, surv, done, total;
     size_t keys_alt, perm_alt, hist;
 };
 
@@ -45,6 +48,7 @@ void make_plan(long long N, Plan* p)
     p->qs = take(sizeof(QState));
     p->t8 = take(kSeg * kSym * 4);
     p->t5 = take(kSeg * kCoarse * 4);
+    p->knn = take(kKnnMax * 8);
     p->surv = take((size_t)N * 8);
     // every survivor completes at most once, plus the head survivor computed first (it is also
     // met again in the list): N + 1 entries
@@ -161,6 +165,8 @@ struct paris_index {
     QState* host_qs;   // pinned read-back buffer
     QResult* host_res;       // pinned, device-mapped: the query result lands here directly
     QResult* host_res_dev;   // its device address
+    KnnHit* host_knn;        // the k-NN answers, in the same mapped allocation (256 bytes on)
+    KnnHit* host_knn_dev;
     Margins mg;
     ScanShape scan;
     int refine_blocks;
@@ -229,6 +235,10 @@ QueryArgs args_for(const paris_index* h)
     a.done_cap = (uint32_t)h->N + 1u;
     a.mg = h->mg;
     a.host_res = nullptr;
+    a.knn_k = 0;
+    a.knn_r = 0;
+    a.knn_slots = reinterpret_cast<unsigned long long*>(ws + h->plan.knn);
+    a.knn_out = nullptr;
     a.leaf_keys = nullptr;
     a.leaf_key_count = 0;
     a.learned_cpl = 0;
@@ -1098,13 +1108,15 @@ paris_status paris_build(const float* series_dev, int64_t n_series, int32_t leng
     h->model = nullptr;
     h->learned = false;
     if (hipHostMalloc(reinterpret_cast<void**>(&h->host_qs), sizeof(QState), hipHostMallocDefault) != hipSuccess ||
-        hipHostMalloc(reinterpret_cast<void**>(&h->host_res), sizeof(QResult), hipHostMallocMapped) != hipSuccess ||
+        hipHostMalloc(reinterpret_cast<void**>(&h->host_res), kHostResBytes, hipHostMallocMapped) != hipSuccess ||
         hipHostGetDevicePointer(reinterpret_cast<void**>(&h->host_res_dev), h->host_res, 0) != hipSuccess) {
         if (h->host_qs) (void)hipHostFree(h->host_qs);
         if (h->host_res) (void)hipHostFree(h->host_res);
         delete h;
         return PARIS_EHIP;
     }
+    h->host_knn = reinterpret_cast<KnnHit*>(reinterpret_cast<uint8_t*>(h->host_res) + 256);
+    h->host_knn_dev = reinterpret_cast<KnnHit*>(reinterpret_cast<uint8_t*>(h->host_res_dev) + 256);
     const QueryArgs a = args_for(h);
     paris_status ts = PARIS_OK;
     if (launch_reset(a, st) != hipSuccess) ts = PARIS_EHIP;
@@ -1194,6 +1206,68 @@ paris_status paris_query_exact(paris_index* h, const float* query_dev, int64_t* 
 }
 
 }  // extern "C"
+
+// ---- exact k-NN --------------------------------------------------------------------------
+namespace {
+// seed distances per answer (PARIS_KNN_SEED overrides, 1 .. 16)
+int knn_seed_per_answer()
+{
+    if (const char* e = std::getenv("PARIS_KNN_SEED")) {
+        const int v = std::atoi(e);
+        if (v >= 1 && v <= 16) return v;
+    }
+    return 8;   // measured at 10M x 256 over 1, 2, 4, 8 and 16 (k = 10 and 64)
+}
+}  // namespace
+
+extern "C" paris_status paris_query_knn(paris_index* h, const float* query_dev, int32_t k, int64_t* nn_index,
+                             double* nn_dist, int32_t* n_found, paris_stats* stats, void* hip_stream)
+{
+    if (!handle_ok(h)) return PARIS_ESTATE;
+    if (!query_dev || !nn_index || !nn_dist || !n_found || k < 1 || k > kKnnMax ||
+        reinterpret_cast<uintptr_t>(query_dev) % 16 != 0)
+        return PARIS_EINVAL;
+    hipStream_t st = reinterpret_cast<hipStream_t>(hip_stream);
+    if (k == 1) {   // the 1-NN search itself
+        paris_status s1 = paris_query_exact(h, query_dev, nn_index, nn_dist, stats, hip_stream);
+        if (s1 == PARIS_OK) *n_found = 1;
+        return s1;
+    }
+    QueryArgs a = args_for(h);
+    a.host_res = h->host_res_dev;
+    a.knn_k = k;
+    a.knn_out = h->host_knn_dev;
+    const paris_mlp* m = h->learned ? h->model : nullptr;
+    if (m) {
+        a.leaf_keys = m->partq;
+        a.leaf_key_count = (m->n_out + 255) / 256 * kTopLeaves;
+        a.learned_cpl = learned_chunks(h);
+    }
+    // seed distances per answer: the smallest-bound members of every chunk of the approximate
+    // search's window(s), kKnnSeedPerAnswer * k of them spread over its chunks
+    a.knn_r = knn_seed_per_answer();
+    *reinterpret_cast<volatile long long*>(&h->host_res->idx) = -2;
+    HIP_TRY(launch_knn_reset(a, st));
+    if (m) {
+        MlpQueryScratch sc{m->partq};
+        HIP_TRY(launch_mlp_query(net_of(m), query_dev, h->n, sc, st));
+    }
+    HIP_TRY(launch_prepare_seed(a, query_dev, st));
+    HIP_TRY(launch_lbscan(a, -1.f, h->scan, st));
+    HIP_TRY(launch_refine_resolve(a, query_dev, nullptr, nullptr, 0, st));
+    int64_t top_i = -1;
+    double top_d = 0.0;
+    paris_status s = finish_query(h, st, &top_i, &top_d, stats);
+    if (s != PARIS_OK) return s;
+    const QResult r = *h->host_res;
+    const int found = (int)(r.n_resolved < (uint32_t)k ? r.n_resolved : (uint32_t)k);
+    for (int j = 0; j < found; ++j) {
+        nn_index[j] = h->host_knn[j].idx;
+        nn_dist[j] = std::sqrt(h->host_knn[j].d2);
+    }
+    *n_found = found;
+    return PARIS_OK;
+}
 
 // ---- allocation-free per-query entry point ----------------------------------------------
 // The per-query scratch of paris_query_exact_noalloc lives in one file-scope device array per

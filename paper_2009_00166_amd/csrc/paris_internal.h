@@ -34,6 +34,16 @@ enum ErrBits : uint32_t {
     kErrDoneOverflow = 4u,   // more completed candidates than capacity
 };
 
+constexpr int kKnnMax = 64;          // largest k of the exact k-NN
+constexpr int kKnnResolve = 2048;    // k-NN: completed candidates re-scored in float64 at most
+constexpr int kKnnWindow = 16384;    // k-NN: sorted positions of the approximate search's window
+
+// One answer of the exact k-NN: series index and float64 squared distance.
+struct KnnHit {
+    long long idx;
+    double d2;
+};
+
 // Result of one query, written by the last kernel of the query.
 struct QResult {
     long long idx;            // -1 if none (non-finite query)
@@ -108,6 +118,13 @@ struct QueryArgs {
     int refine_blocks;      // refine grid (0: kRefineBlocks)
     int refine_lanes;       // lanes per refined row: 4, 8 (default) or 16
     int bsf_private;        // 1: every lane group prunes with its own best-so-far copy only
+    // exact k-NN (knn_k > 0): the best-so-far key of QState is the k-th best key found so far,
+    // the k best keys live in knn_slots, and the seed refines knn_r * knn_k smallest-bound
+    // members of the approximate search's window (spread evenly over its chunks)
+    int knn_k;
+    int knn_r;
+    unsigned long long* knn_slots;  // [kKnnMax] (float32 bits of ED^2, index) keys
+    KnnHit* knn_out;                // [kKnnMax] answers of the last block (mapped host memory)
 };
 
 // ---- batched path ----
@@ -322,5 +339,7 @@ hipError_t launch_lbscan(const QueryArgs& a, float threshold_sq, ScanShape shape
 hipError_t launch_refine_resolve(const QueryArgs& a, const float* q, long long* out_idx, double* out_dist,
                                  long long qi, hipStream_t st);
 int seed_grid(const QueryArgs& a);
+// exact k-NN: the k best slots set to (+inf, no index) and the state's k-th key to +inf
+hipError_t launch_knn_reset(const QueryArgs& a, hipStream_t st);
 
 }  // namespace paris

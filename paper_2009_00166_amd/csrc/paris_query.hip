@@ -105,6 +105,71 @@ hipError_t launch_reset(const QueryArgs& a, hipStream_t st)
 }
 
 // ------------------------------------------------------------------------------------------
+// exact k-NN: the k best (distance, index) keys found so far, in k slots of global memory.
+// The slots hold distinct series (kBsfInit, whose index is never a series', marks an empty
+// slot). A key enters by replacing the slot that holds the largest key with a compare-and-swap;
+// the swap fails, and the insertion starts over, when another insertion changed that slot first.
+// Slots only ever decrease, so the slot read as the largest still is the largest when its swap
+// succeeds: the slots always hold the k smallest keys offered so far. After a successful swap the
+// slots' new largest key is folded into `kth` (atomicMin): kth bounds the k-th best distance from
+// above (a stale, larger value is only looser). A series already in the slots is not offered
+// twice (the seed computed it with another summation order).
+// ------------------------------------------------------------------------------------------
+// The insertion is made by a lane group of G lanes (every lane of the group calls it with the
+// same key): each lane reads every G-th slot, the group reduces the largest key and the
+// duplicate flag, the group's first lane swaps.
+template <int G>
+__device__ bool knn_insert_group(unsigned long long* slots, int k, unsigned long long c, unsigned long long* kth,
+                                 int l, int lead)
+{
+    const uint32_t ci = (uint32_t)(c & 0xFFFFFFFFu);
+    for (;;) {
+        unsigned long long mx = 0ull;
+        int ms = -1, dup = 0;
+        for (int s = l; s < k; s += G) {
+            const unsigned long long v = load_key(slots + s);
+            dup |= (uint32_t)(v & 0xFFFFFFFFu) == ci ? 1 : 0;
+            if (ms < 0 || v > mx) { mx = v; ms = s; }
+        }
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) {
+            const unsigned long long om = __shfl_xor(mx, off, G);
+            const int os = __shfl_xor(ms, off, G);
+            dup |= __shfl_xor(dup, off, G);
+            if (os >= 0 && (ms < 0 || om > mx || (om == mx && os < ms))) { mx = om; ms = os; }
+        }
+        if (dup || ms < 0 || c >= mx) return false;
+        int ok = 0;
+        if (l == 0) ok = atomicCAS(slots + ms, mx, c) == mx ? 1 : 0;
+        ok = __shfl(ok, lead);
+        if (!ok) continue;
+        unsigned long long m2 = 0ull;
+        for (int s = l; s < k; s += G) {
+            const unsigned long long v = load_key(slots + s);
+            m2 = v > m2 ? v : m2;
+        }
+#pragma unroll
+        for (int off = G / 2; off > 0; off >>= 1) {
+            const unsigned long long o = __shfl_xor(m2, off, G);
+            m2 = o > m2 ? o : m2;
+        }
+        if (l == 0) atomicMin(kth, m2);
+        return true;
+    }
+}
+
+__global__ void k_knn_reset(unsigned long long* slots)
+{
+    if (threadIdx.x < kKnnMax) slots[threadIdx.x] = kBsfInit;
+}
+
+hipError_t launch_knn_reset(const QueryArgs& a, hipStream_t st)
+{
+    k_knn_reset<<<1, kKnnMax, 0, st>>>(a.knn_slots);
+    return hipGetLastError();
+}
+
+// ------------------------------------------------------------------------------------------
 // prepare + seed. Every block computes the query summaries (same arithmetic as the build), the
 // table T8[s][c] = L * delta(q_s, region c)^2 (float64, rounded toward zero to float32) in LDS,
 // and the approximate-search window (sorted positions). Block 0 also publishes T8, the coarse
@@ -273,7 +338,17 @@ __global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* 
         wl = ell * N / nl;
         wh = (ell + 1) * N / nl;
     };
-    if (learned) {
+    if (A.knn_k > 0 && !learned && (A.leaf_mode != 0 || A.seed_cap > 0)) {
+        // exact k-NN: kKnnWindow consecutive sorted positions centred on the lower bound of the
+        // query's leaf key in the whole order (a small root subtree would hold fewer than k)
+        const long long N = A.N;
+        const long long c = block_lower_bound(A.keys, 0, N, kq, &s_cnt);
+        long long a = c - kKnnWindow / 2;
+        if (a > N - kKnnWindow) a = N - kKnnWindow;
+        if (a < 0) a = 0;
+        lo = a;
+        hi = (a + kKnnWindow < N) ? a + kKnnWindow : N;
+    } else if (learned) {
         if (batch) {
             lv = B.leaves + (long long)blockIdx.y * kTopLeaves;
         } else {
@@ -371,15 +446,16 @@ __global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* 
         c0 = wl + ch;
         c1 = (c0 + kSeedChunk < wh) ? c0 + kSeedChunk : wh;
     };
-    // the chunk member with the smallest fine bound, as a (bound, row) key (whole block)
-    auto chunk_best = [&](long long c0, long long c1) -> unsigned long long {
+    // the chunk member with the smallest fine bound, as a (bound, row) key, among the keys at
+    // least `floor` (whole block; keys are distinct)
+    auto chunk_best = [&](long long c0, long long c1, unsigned long long floor) -> unsigned long long {
         unsigned long long best = ~0ull;
         for (long long p = c0 + tid; p < c1; p += 256) {
             const uint32_t row = A.perm[p];
             const uint4 w = reinterpret_cast<const uint4*>(A.saxs)[p];   // leaf-order copy: contiguous
             const float lb = fine_lb(w, t8);
             const unsigned long long k = pack_key(lb, row);
-            best = k < best ? k : best;
+            best = (k < best && k >= floor) ? k : best;
         }
         for (int off = 32; off > 0; off >>= 1) {
             const unsigned long long o = __shfl_xor(best, off);
@@ -409,7 +485,33 @@ __global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* 
         long long c0, c1;
         chunk_range((int)blockIdx.x, c0, c1);
         if (c0 >= c1) return;  // uniform
-        const unsigned long long best = chunk_best(c0, c1);
+        if (A.knn_k > 0) {
+            // exact k-NN: the chunk's r smallest-bound members, each round the smallest key above
+            // the previous round's, their distances offered to the k best slots. r spreads the
+            // knn_r * k seed distances over the window's chunks (knn_r: seeds per answer); the
+            // learned seed's chunk count comes from the host.
+            long long nch = learned ? (long long)gridDim.x : (hi - lo + kSeedChunk - 1) / kSeedChunk;
+            if (nch < 1) nch = 1;
+            long long r = ((long long)A.knn_r * A.knn_k + nch - 1) / nch;
+            if (r > kSeedBatchChunks) r = kSeedBatchChunks;
+            unsigned long long floor = 0ull;
+            int nsel = 0;
+            for (int t = 0; t < (int)r; ++t) {
+                const unsigned long long best = chunk_best(c0, c1, floor);
+                if (best == ~0ull) break;  // uniform: the chunk has no more members
+                floor = best + 1ull;
+                if (tid == 0) s_best[t] = best;
+                ++nsel;
+            }
+            __syncthreads();
+            for (int t = tid >> 6; t < nsel; t += 4) {   // one wave per selected member
+                const uint32_t row = (uint32_t)(s_best[t] & 0xFFFFFFFFu);
+                const float acc = wave_dist(row);
+                knn_insert_group<64>(A.knn_slots, A.knn_k, pack_key(acc, row), bsf, lane, 0);
+            }
+            return;
+        }
+        const unsigned long long best = chunk_best(c0, c1, 0ull);
         if (tid < 64) {
             const uint32_t row = (uint32_t)(best & 0xFFFFFFFFu);
             const float acc = wave_dist(row);
@@ -483,6 +585,7 @@ __global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* 
 int seed_grid(const QueryArgs& a)
 {
     if (a.learned_cpl > 0) return kTopLeaves * a.learned_cpl;
+    if (a.knn_k > 0 && (a.leaf_mode != 0 || a.seed_cap > 0)) return kKnnWindow / kSeedChunk;
     long long win = 0;
     if (a.leaf_mode == 0) win = a.seed_cap;
     else win = (a.N + a.n_leaves - 1) / a.n_leaves;
@@ -804,6 +907,94 @@ __device__ void resolve_block(const QueryArgs& A, const float* __restrict__ q, l
     }
 }
 
+// exact k-NN resolve (the last block): every completed candidate within the band of the final
+// k-th float32 distance is re-scored in float64 with the oracle's operation order (one thread
+// per candidate, ascending j); a candidate's rank in ascending (squared distance, index) among
+// them places it in the answer list when it is below k.
+__device__ void resolve_knn_block(const QueryArgs& A, const float* __restrict__ q)
+{
+    __shared__ uint32_t c_idx[kKnnResolve];
+    __shared__ double c_d[kKnnResolve];
+    __shared__ uint32_t ncand;
+    __shared__ int s_top;
+    const int tid = threadIdx.x, n = A.n, k = A.knn_k;
+    QState* qs = A.qs;
+    const unsigned long long key = load_key(&qs->bsf_key);
+    const double band = (double)key_dist(key) * (1.0 + A.mg.band_rel) + 1e-25;
+    const uint32_t ndone = __hip_atomic_load(&qs->n_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint32_t count = min(ndone, A.done_cap);
+    if (tid == 0) { ncand = 0; s_top = -1; }
+    __syncthreads();
+    for (uint32_t e = tid; e < count; e += 256) {
+        const uint2 v = A.done[e];
+        if ((double)__uint_as_float(v.y) <= band) {
+            const uint32_t p = atomicAdd(&ncand, 1u);
+            if (p < (uint32_t)kKnnResolve) c_idx[p] = v.x;
+        }
+    }
+    __syncthreads();
+    const uint32_t nc = ncand;
+    const bool over = nc > (uint32_t)kKnnResolve;
+    const uint32_t m = over ? 0u : nc;
+    for (uint32_t c = tid; c < m; c += 256) {
+        const float* x = A.X + (long long)c_idx[c] * n;
+        double acc = 0.0;
+        for (int j = 0; j < n; ++j) {
+            const double d = (double)q[j] - (double)x[j];
+            const double t = d * d;
+            acc = acc + t;
+        }
+        c_d[c] = acc;
+    }
+    __syncthreads();
+    bool wrote = false;
+    for (uint32_t c = tid; c < m; c += 256) {
+        const double dc = c_d[c];
+        const uint32_t ic = c_idx[c];
+        uint32_t r = 0;
+        for (uint32_t o = 0; o < m; ++o) {
+            const double d2 = c_d[o];
+            r += (d2 < dc || (d2 == dc && c_idx[o] < ic)) ? 1u : 0u;
+        }
+        if (r < (uint32_t)k) {
+            if (A.knn_out) {
+                A.knn_out[r].idx = ic;
+                A.knn_out[r].d2 = dc;
+                wrote = true;
+            }
+            if (r == 0) s_top = (int)c;
+        }
+    }
+    if (wrote) __threadfence_system();   // the answers reach host memory before the flag below
+    __syncthreads();
+    if (tid == 0) {
+        uint32_t err = qs->err;
+        if (qs->n_surv > A.surv_cap) err |= kErrSurvOverflow;
+        if (ndone > A.done_cap || over) err |= kErrDoneOverflow;
+        const bool found = s_top >= 0 && (err & kErrNonFinite) == 0u;
+        QResult& r = qs->res;
+        r.idx = found ? (long long)c_idx[s_top] : -1;
+        r.d2 = found ? c_d[s_top] : __builtin_nan("");
+        r.seed_key = qs->seed_key;
+        r.win_lo = qs->win_lo;
+        r.win_hi = qs->win_hi;
+        r.n_surv = qs->n_surv;
+        r.n_refined = qs->n_refined;
+        r.n_abandon = qs->n_abandon;
+        r.n_bsf_upd = qs->n_bsf_upd;
+        r.n_resolved = m;
+        r.err = err;
+        if (A.host_res) {
+            QResult hr = r;
+            hr.idx = -2;
+            *A.host_res = hr;
+            __threadfence_system();
+            *reinterpret_cast<volatile long long*>(&A.host_res->idx) = r.idx;
+        }
+        reset_state(qs);
+    }
+}
+
 // all-reduce over groups of G lanes (butterfly: bit-identical result on all G lanes)
 template <int G>
 __device__ __forceinline__ float group_sum(float v)
@@ -813,7 +1004,9 @@ __device__ __forceinline__ float group_sum(float v)
     return v;
 }
 
-template <int G>
+// KNN: exact k-NN mode (the best-so-far key is the k-th best, completions go to the k best
+// slots, no head pass, no private copies, the k-NN resolve)
+template <int G, bool KNN>
 __global__ __launch_bounds__(256) void k_refine_resolve(QueryArgs A, const float* __restrict__ q,
                                                         long long* out_idx, double* out_dist, long long qi)
 {
@@ -843,7 +1036,7 @@ __global__ __launch_bounds__(256) void k_refine_resolve(QueryArgs A, const float
     // with the smallest bound (usually the answer), so its own threshold starts there instead of
     // waiting for other groups' atomicMin; group 0 also publishes it.
     float local_best = __builtin_inff();
-    if (count > ngrp) {
+    if (!KNN && count > ngrp) {
         const unsigned long long hk = A.qs->head_key;
         if (hk != ~0ull) {
             const uint32_t hrow = (uint32_t)(hk & 0xFFFFFFFFu);
@@ -878,7 +1071,7 @@ __global__ __launch_bounds__(256) void k_refine_resolve(QueryArgs A, const float
     // seed's best-so-far and the smallest distance it has completed itself. The atomicMin below
     // still runs, as the final minimum over the groups' copies; pruning with a larger threshold
     // is never wrong.
-    const bool priv = A.bsf_private != 0;
+    const bool priv = !KNN && A.bsf_private != 0;
     constexpr int CV = 4 * F;            // float4 per lane per chunk
     unsigned long long key0 = 0;
     if (l == 0) key0 = load_key(priv ? &A.qs->seed_key : &A.qs->bsf_key);
@@ -944,7 +1137,22 @@ __global__ __launch_bounds__(256) void k_refine_resolve(QueryArgs A, const float
             local_best = fminf(local_best, acc);
             thr = prune_threshold(fminf(key_dist(key0), local_best), A.mg.prune_rel);
         }
-        if (l == 0) {
+        if (KNN) {
+            // recorded when within the band of the current k-th best (a superset of the final
+            // band), then offered to the k best slots by the whole group
+            const unsigned long long mine = pack_key(acc, e.x);
+            unsigned long long now = 0ull;
+            if (l == 0) now = load_key(&A.qs->bsf_key);
+            now = __shfl(now, lead);
+            if (l == 0 && (double)acc <= (double)key_dist(now) * (1.0 + A.mg.band_rel) + 1e-25) {
+                const uint32_t pos = atomicAdd(&A.qs->n_done, 1u);
+                if (pos < A.done_cap) A.done[pos] = make_uint2(e.x, __float_as_uint(acc));
+                wrote = true;
+            }
+            if (mine < now && knn_insert_group<G>(A.knn_slots, A.knn_k, mine, &A.qs->bsf_key, l, lead) &&
+                l == 0)
+                atomicAdd(&A.qs->n_bsf_upd, 1u);
+        } else if (l == 0) {
             const unsigned long long mine = pack_key(acc, e.x);
             const unsigned long long old = atomicMin(&A.qs->bsf_key, mine);
             if (mine < old) atomicAdd(&A.qs->n_bsf_upd, 1u);
@@ -978,19 +1186,22 @@ __global__ __launch_bounds__(256) void k_refine_resolve(QueryArgs A, const float
     __syncthreads();
     if (!s_last) return;
     __threadfence();
-    resolve_block(A, q, out_idx, out_dist, qi);
+    if constexpr (KNN) resolve_knn_block(A, q);
+    else resolve_block(A, q, out_idx, out_dist, qi);
 }
 
 hipError_t launch_refine_resolve(const QueryArgs& a, const float* q, long long* out_idx, double* out_dist,
                                  long long qi, hipStream_t st)
 {
     const int grid = a.refine_blocks > 0 ? a.refine_blocks : kRefineBlocks;
-    if (a.refine_lanes == 4)
-        k_refine_resolve<4><<<grid, 256, 0, st>>>(a, q, out_idx, out_dist, qi);
+    if (a.knn_k > 0)
+        k_refine_resolve<8, true><<<grid, 256, 0, st>>>(a, q, out_idx, out_dist, qi);
+    else if (a.refine_lanes == 4)
+        k_refine_resolve<4, false><<<grid, 256, 0, st>>>(a, q, out_idx, out_dist, qi);
     else if (a.refine_lanes == 16)
-        k_refine_resolve<16><<<grid, 256, 0, st>>>(a, q, out_idx, out_dist, qi);
+        k_refine_resolve<16, false><<<grid, 256, 0, st>>>(a, q, out_idx, out_dist, qi);
     else
-        k_refine_resolve<8><<<grid, 256, 0, st>>>(a, q, out_idx, out_dist, qi);
+        k_refine_resolve<8, false><<<grid, 256, 0, st>>>(a, q, out_idx, out_dist, qi);
     return hipGetLastError();
 }
 

@@ -147,3 +147,26 @@ def test_shared_and_private_best_so_far_at_scale(full, oracle_native):
                 assert abs(d - ref) <= 1e-5 * ref
     finally:
         index.set_bsf_sharing(False)
+
+
+def test_knn_at_scale(full, oracle_native):
+    """Exact k-NN (k = 10 and 64) at 10M x 256 on easy, hard and new-walk queries against the
+    k-NN by definition: the C oracle's float64 distances to every series, ordered by (distance,
+    index)."""
+    from concurrent.futures import ThreadPoolExecutor
+    X, index = full["X"], full["index"]
+    Qe, _, _ = synth.noisy_queries(X, 3, seed=11, sigma=0.1)
+    Qh, _, _ = synth.noisy_queries(X, 2, seed=12, sigma=0.5)
+    Q = np.ascontiguousarray(np.concatenate([Qe, Qh, synth.fresh_walk_queries(1, LEN, seed=13)]))
+    t0 = time.time()
+    with ThreadPoolExecutor(max_workers=Q.shape[0]) as ex:
+        d2s = list(ex.map(lambda q: oracle_native.ed2(q, X), Q))
+    print(f"[scale] k-NN oracle distances for {Q.shape[0]} queries in {time.time() - t0:.1f}s", flush=True)
+    Qd = torch.from_numpy(Q).cuda()
+    for m in range(Q.shape[0]):
+        order = np.lexsort((np.arange(N_FULL), d2s[m]))[:64]
+        for k in (10, 64):
+            idx, dist, st = index.query_knn(Qd[m], k, with_stats=True)
+            assert np.array_equal(idx, order[:k]), (m, k)
+            assert np.array_equal(dist, np.sqrt(d2s[m][order[:k]])), (m, k)
+        print(f"[scale] k-NN query {m}: {st['lb_survivors']} LB survivors, {st['refined']} refined", flush=True)
