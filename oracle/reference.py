@@ -318,14 +318,31 @@ class ExactStats:
     candidates: list = field(default_factory=list)
 
 
+def seed_members(qs: QuerySummary, sym8: np.ndarray, L: int, mode: str = "root16", seed_cap: int = 16384,
+                 n_leaves: int = 4096, leaf_cap: int = 2048) -> np.ndarray:
+    """Series of the leaf the approximate search reaches (Section 3.3): the window of
+    ``seed_window`` in the ``root16`` and ``equal_count`` modes; in the ``ads`` mode the ADS+
+    tree's leaf reached by the query's descent (``ads.ads_query_leaf``), at most ``seed_cap`` of
+    its positions from its start."""
+    if mode == "ads":
+        from .ads import ads_query_leaf, ads_tree
+        tree = ads_tree(sym8, leaf_cap)
+        v = ads_query_leaf(tree, qs.sym, qs.paa, L)
+        a, b = int(tree.start[v]), int(tree.end[v])
+        return tree.perm[a:min(b, a + seed_cap)]
+    perm, keys_sorted = sorted_order(sym8)
+    a, b = seed_window(qs, keys_sorted, L, mode, seed_cap, n_leaves)
+    return perm[a:b]
+
+
 def exact_search(q: np.ndarray, X: np.ndarray, sym8: np.ndarray | None = None,
                  mode: str = "root16", seed_cap: int = 16384, n_leaves: int = 4096,
-                 use_seed: bool = True):
+                 use_seed: bool = True, leaf_cap: int = 2048):
     """Serial twin of ParIS+ exact search; returns ``(index, squared distance, ExactStats)``.
 
-    1. BSF <- approximate search (``seed_window``, then ``approximate_seed``: the smallest
-       squared distance over every member of the window, ties to the lowest index), or +inf when
-       ``use_seed`` is False.
+    1. BSF <- approximate search (``seed_members``, then ``approximate_seed``: the smallest
+       squared distance over every member of the reached leaf, ties to the lowest index), or
+       +inf when ``use_seed`` is False.
     2. LBC step: candidates = {i : LB^2_i <= BSF^2}. The paper keeps i when minDist < BSF;
        reading: prune only on ">", so a series tied with the BSF at a lower index survives.
     3. Candidates are processed in ascending (LB^2, i) (the paper sorts by file position for
@@ -349,9 +366,7 @@ def exact_search(q: np.ndarray, X: np.ndarray, sym8: np.ndarray | None = None,
     st = ExactStats()
     bsf, bsf_i = np.inf, -1
     if use_seed and N > 0:
-        perm, keys_sorted = sorted_order(sym8)
-        a, b = seed_window(qs, keys_sorted, L, mode, seed_cap, n_leaves)
-        bsf_i, bsf = approximate_seed(qf, X, perm[a:b])
+        bsf_i, bsf = approximate_seed(qf, X, seed_members(qs, sym8, L, mode, seed_cap, n_leaves, leaf_cap))
         st.seed_index, st.seed_d2 = bsf_i, bsf
     lb = lower_bound_sq(qs.paa[None, :], sym8, L)
 

@@ -222,3 +222,52 @@ def test_knn_twin_without_pruning_is_caught(monkeypatch):
     bad = _mutated(R.exact_search_knn, "lb[i] > kth() * (1.0 + 1e-9) + 1e-12", "False")
     monkeypatch.setattr(oracle, "exact_search_knn", bad)
     _fails(T_search.test_knn_twin_refined_count_closed_form, 4)
+
+
+# ---- the ADS+ tree ----------------------------------------------------------------------------
+def _ads_mutant(monkeypatch, old, new, fn_name="ads_tree"):
+    """Replace ``oracle.ads.<fn_name>`` (and the name the tree tests import) by a copy of its source
+    with one fragment changed."""
+    import inspect
+    import textwrap
+    import oracle
+    import oracle.ads as A
+    import tests.test_oracle_ads as T_ads
+    src = textwrap.dedent(inspect.getsource(getattr(A, fn_name)))
+    assert old in src, old
+    ns = dict(vars(A))
+    exec(compile(src.replace(old, new), "<mutant>", "exec"), ns)
+    bad = ns[fn_name]
+    monkeypatch.setattr(A, fn_name, bad)
+    monkeypatch.setattr(oracle, fn_name, bad)
+    monkeypatch.setattr(T_ads, fn_name, bad)
+    return T_ads
+
+
+def test_ads_least_balanced_split_is_caught(monkeypatch):
+    T = _ads_mutant(monkeypatch, "if best_gap is None or gap < best_gap:", "if best_gap is None or gap > best_gap:")
+    _fails(T.test_hand_worked_tree)
+
+
+def test_ads_ties_to_the_highest_segment_are_caught(monkeypatch):
+    T = _ads_mutant(monkeypatch, "if best_gap is None or gap < best_gap:", "if best_gap is None or gap <= best_gap:")
+    _fails(T.test_hand_worked_tree)
+
+
+def test_ads_wrong_bit_is_caught(monkeypatch):
+    import oracle.ads as A
+    import tests.test_oracle_ads as T
+    bad = lambda sym, card: (np.asarray(sym, np.int64) >> card) & 1      # counted from the wrong end
+    monkeypatch.setattr(A, "next_bit", bad)
+    _fails(T.test_hand_worked_tree)
+
+
+def test_ads_unstable_partition_is_caught(monkeypatch):
+    T = _ads_mutant(monkeypatch, "perm[a:b] = np.concatenate([zeros, ones_])",
+                    "perm[a:b] = np.concatenate([zeros[::-1], ones_])")
+    _fails(T.test_hand_worked_tree)
+
+
+def test_ads_descent_without_detour_is_caught(monkeypatch):
+    T = _ads_mutant(monkeypatch, "c = int(tree.child0[v]) + (1 - b)", "c = c", fn_name="ads_query_leaf")
+    _fails(T.test_descent_into_an_empty_child_takes_the_other)
