@@ -46,7 +46,7 @@ typedef enum paris_status {
     PARIS_ESTATE = -6      /* invalid or freed handle                                        */
 } paris_status;
 
-enum { PARIS_LEAF_ROOT16 = 0, PARIS_LEAF_EQUAL_COUNT = 1 };
+enum { PARIS_LEAF_ROOT16 = 0, PARIS_LEAF_EQUAL_COUNT = 1, PARIS_LEAF_ADS = 2 };
 
 /* Index configuration. Start from paris_default_config(). */
 typedef struct paris_config {
@@ -54,7 +54,11 @@ typedef struct paris_config {
     int32_t card_bits;  /* must be 8: 256 symbols, the maximum cardinality (Section 2.2)        */
     int32_t leaf_mode;  /* PARIS_LEAF_ROOT16: leaves are the root subtrees, i.e. runs of equal
                            first bits of the 16 symbols (Section 3, pipeline overview).
-                           PARIS_LEAF_EQUAL_COUNT: n_leaves equal slices of the key order.    */
+                           PARIS_LEAF_EQUAL_COUNT: n_leaves equal slices of the key order.
+                           PARIS_LEAF_ADS: the ADS+ tree (Section 2.2): root subtrees whose
+                           leaves split while they hold more than leaf_cap series, each split
+                           fixing one more bit of the segment that divides the leaf most evenly
+                           (ties: the lowest segment); bulk loaded on the GPU.                 */
     int32_t n_leaves;   /* EQUAL_COUNT only: 1 .. 65536 (default 4096)                          */
     int32_t seed_cap;   /* ROOT16 only: the approximate search examines at most this many
                            members of the query's subtree (default 16384), consecutive in key
@@ -62,7 +66,10 @@ typedef struct paris_config {
                            with the smallest lower bound gets its real distance computed, and
                            the smallest of those is the first best-so-far. 0 disables the seed:
                            the best-so-far starts at +inf (the answer is unchanged).           */
-    int32_t reserved[3];
+    int32_t leaf_cap;   /* PARIS_LEAF_ADS only: leaf capacity, 1 .. 2^20 (default 2048; the paper
+                           gives none). The approximate search reaches the query's leaf by the
+                           query's bits and examines at most seed_cap of its positions.        */
+    int32_t reserved[2];
 } paris_config;
 
 /* Per-query counters (paris_query_batch sums them over the batch). */
@@ -90,6 +97,17 @@ typedef struct paris_layout {
     int32_t leaf_mode, n_leaves, seed_cap;
     int32_t scan_threads, scan_blocks_per_cu, scan_unroll;  /* lower-bound scan launch shape
                                                                picked at build                */
+    /* PARIS_LEAF_ADS only (else NULL / 0): the tree's nodes, 32 bytes each: uint32 start, end
+       (range of the leaf order), int32 child0 (-1: leaf; the bit-1 child is child0 + 1), int32
+       split (segment refined by the split, -1: leaf), uint8 card[16] (bits fixed per segment).
+       Nodes 0 .. 65535 are the root subtrees (node r: root key r); every round of the build
+       splits the leaves that must split in ascending id, the i-th getting children next + 2i and
+       next + 2i + 1 (next: the node count before the round). In this mode perm_dev is the tree's
+       leaf order (a stable partition of the key order per split, bit 0 first) and keys_dev[p] is
+       the leaf key of series perm_dev[p] (no longer ascending).                                */
+    const void *tree_nodes_dev;
+    int64_t n_tree_nodes;
+    int64_t tree_max_leaf;      /* series in the largest leaf                                   */
 } paris_layout;
 
 /* Query summaries as computed on the device (inspection and tests). */

@@ -14,10 +14,10 @@ from __future__ import annotations
 
 import ctypes
 
-from ._binding import (LEAF_EQUAL_COUNT, LEAF_ROOT16, PARIS_OK, ParisConfig, ParisError,  # noqa: F401
+from ._binding import (LEAF_ADS, LEAF_EQUAL_COUNT, LEAF_ROOT16, PARIS_OK, ParisConfig, ParisError,  # noqa: F401
                        ParisLayout, ParisQueryInfo, ParisStats, check, load_library)
 
-__all__ = ["build", "Index", "ParisError", "LEAF_ROOT16", "LEAF_EQUAL_COUNT", "load_library"]
+__all__ = ["build", "Index", "ParisError", "LEAF_ROOT16", "LEAF_EQUAL_COUNT", "LEAF_ADS", "load_library"]
 
 
 def _torch():
@@ -201,6 +201,21 @@ class Index:
         torch = _torch()
         off = self.layout().roff_dev - self.workspace.data_ptr()
         return self.workspace[off:off + 4 * 65537].view(torch.int32)
+
+    def tree_nodes(self):
+        """ADS+ leaf mode: the tree's nodes as a dict of host numpy arrays (start, end, child0,
+        split, card [nodes, 16]); None in the other leaf modes."""
+        import numpy as np
+        lay = self.layout()
+        if not lay.tree_nodes_dev:
+            return None
+        off = lay.tree_nodes_dev - self.workspace.data_ptr()
+        raw = self.workspace[off:off + 32 * lay.n_tree_nodes].cpu().numpy().reshape(-1, 32)
+        u32 = raw[:, :16].copy().view(np.uint32).reshape(-1, 4)
+        return {"start": u32[:, 0].astype(np.int64), "end": u32[:, 1].astype(np.int64),
+                "child0": u32[:, 2].view(np.int32).astype(np.int64),
+                "split": u32[:, 3].view(np.int32).astype(np.int64),
+                "card": raw[:, 16:].astype(np.int64), "max_leaf": int(lay.tree_max_leaf)}
 
     def query_info(self, q, stream=None, tables: bool = False):
         torch = _torch()

@@ -10,13 +10,13 @@ LIB_PATH = os.path.join(_HERE, "libparis.so")
 
 PARIS_OK, PARIS_EINVAL, PARIS_ENOMEM, PARIS_ENODEV, PARIS_EHIP, PARIS_EOVERFLOW, PARIS_ESTATE = \
     0, -1, -2, -3, -4, -5, -6
-LEAF_ROOT16, LEAF_EQUAL_COUNT = 0, 1
+LEAF_ROOT16, LEAF_EQUAL_COUNT, LEAF_ADS = 0, 1, 2
 
 
 class ParisConfig(ctypes.Structure):
     _fields_ = [("segments", ctypes.c_int32), ("card_bits", ctypes.c_int32),
                 ("leaf_mode", ctypes.c_int32), ("n_leaves", ctypes.c_int32),
-                ("seed_cap", ctypes.c_int32), ("reserved", ctypes.c_int32 * 3)]
+                ("seed_cap", ctypes.c_int32), ("leaf_cap", ctypes.c_int32), ("reserved", ctypes.c_int32 * 2)]
 
 
 class ParisStats(ctypes.Structure):
@@ -36,7 +36,9 @@ class ParisLayout(ctypes.Structure):
                 ("n_series", ctypes.c_int64), ("length", ctypes.c_int32),
                 ("leaf_mode", ctypes.c_int32), ("n_leaves", ctypes.c_int32),
                 ("seed_cap", ctypes.c_int32), ("scan_threads", ctypes.c_int32),
-                ("scan_blocks_per_cu", ctypes.c_int32), ("scan_unroll", ctypes.c_int32)]
+                ("scan_blocks_per_cu", ctypes.c_int32), ("scan_unroll", ctypes.c_int32),
+                ("tree_nodes_dev", ctypes.c_void_p), ("n_tree_nodes", ctypes.c_int64),
+                ("tree_max_leaf", ctypes.c_int64)]
 
 
 class ParisQueryInfo(ctypes.Structure):

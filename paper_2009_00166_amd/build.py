@@ -12,7 +12,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 LIB = os.path.join(HERE, "libparis.so")
-SOURCES = ["paris_build.hip", "paris_query.hip", "paris_batch.hip", "paris_mlp.hip", "paris_api.hip"]
+SOURCES = ["paris_build.hip", "paris_tree.hip", "paris_query.hip", "paris_batch.hip", "paris_mlp.hip",
+           "paris_api.hip"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",

@@ -12,6 +12,7 @@
 #include <mutex>
 #include <new>
 #include <unordered_set>
+#include <vector>
 
 #include "paris.h"
 #include "paris_internal.h"
@@ -33,9 +34,24 @@ size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 struct Plan {
     size_t hdr, sax, saxs, keys, perm, roff, qs, t8, t5, knn, surv, done, total;
     size_t keys_alt, perm_alt, hist;
+    // ADS+ tree (leaf mode 2): nodes, and the scratch of a build round (todo ids, chunk starts,
+    // splits; chunks, their counts and destinations); 0 otherwise
+    size_t tree, tree_todo, tree_todo_chunks, tree_split, tree_chunks, tree_ones, tree_dst;
+    long long node_cap, todo_cap, chunk_cap;
 };
 
-void make_plan(long long N, Plan* p)
+// Largest number of nodes a tree over N series with leaf capacity cap is given: the root
+// subtrees, twice a generous count of splits (every split node holds more than cap series, so
+// the nodes split in one round number at most N / (cap + 1)), and room for chains of splits of
+// a group of identical words. A build that would need more stops splitting (its leaves stay
+// larger than cap; the search only reads a larger window).
+long long tree_node_cap(long long N, int cap)
+{
+    const long long per_round = N / ((long long)cap + 1) + 1;
+    return kRoots + 8 * per_round + 2 * kTreeMaxDepth * 64;
+}
+
+void make_plan(long long N, Plan* p, const paris_config* cfg)
 {
     size_t off = 0;
     auto take = [&off](size_t bytes) { const size_t at = off; off = align_up(off + bytes); return at; };
@@ -53,6 +69,20 @@ void make_plan(long long N, Plan* p)
     // every survivor completes at most once, plus the head survivor computed first (it is also
     // met again in the list): N + 1 entries
     p->done = take((size_t)(N + 1) * 8);
+    p->tree = p->tree_todo = p->tree_todo_chunks = p->tree_split = p->tree_chunks = p->tree_ones = p->tree_dst = 0;
+    p->node_cap = p->todo_cap = p->chunk_cap = 0;
+    if (cfg && cfg->leaf_mode == PARIS_LEAF_ADS) {
+        p->node_cap = tree_node_cap(N, cfg->leaf_cap);
+        p->todo_cap = N / ((long long)cfg->leaf_cap + 1) + 1;
+        p->chunk_cap = N / kTreeChunk + p->todo_cap + 1;
+        p->tree = take((size_t)p->node_cap * sizeof(AdsNode));
+        p->tree_todo = take((size_t)p->todo_cap * 4);
+        p->tree_todo_chunks = take((size_t)(p->todo_cap + 1) * 4);
+        p->tree_split = take((size_t)p->todo_cap * 4);
+        p->tree_chunks = take((size_t)p->chunk_cap * sizeof(TreeChunk));
+        p->tree_ones = take((size_t)p->chunk_cap * kSeg * 4);
+        p->tree_dst = take((size_t)p->chunk_cap * 8);
+    }
     p->total = off;
     p->keys_alt = p->surv;  // 8N bytes
     p->perm_alt = p->done;  // 4N bytes
@@ -68,7 +98,10 @@ bool config_ok(const paris_config* c)
 {
     if (!c) return false;
     if (c->segments != 16 || c->card_bits != 8) return false;
-    if (c->leaf_mode != PARIS_LEAF_ROOT16 && c->leaf_mode != PARIS_LEAF_EQUAL_COUNT) return false;
+    if (c->leaf_mode != PARIS_LEAF_ROOT16 && c->leaf_mode != PARIS_LEAF_EQUAL_COUNT &&
+        c->leaf_mode != PARIS_LEAF_ADS)
+        return false;
+    if (c->leaf_mode == PARIS_LEAF_ADS && (c->leaf_cap < 1 || c->leaf_cap > (1 << 20))) return false;
     if (c->leaf_mode == PARIS_LEAF_EQUAL_COUNT && (c->n_leaves < 1 || c->n_leaves > 65536)) return false;
     if (c->seed_cap < 0 || c->seed_cap > (1 << 24)) return false;
     return true;
@@ -207,6 +240,9 @@ struct paris_index {
     // learned seed (paris_set_seed_model): the network is borrowed, not owned
     paris_mlp* model;
     bool learned;
+    // ADS+ tree (leaf mode 2)
+    long long n_tree_nodes;
+    long long tree_max_leaf;
 };
 
 namespace {
@@ -239,6 +275,8 @@ QueryArgs args_for(const paris_index* h)
     a.knn_r = 0;
     a.knn_slots = reinterpret_cast<unsigned long long*>(ws + h->plan.knn);
     a.knn_out = nullptr;
+    a.tree = h->cfg.leaf_mode == PARIS_LEAF_ADS ? reinterpret_cast<const AdsNode*>(ws + h->plan.tree) : nullptr;
+    a.tree_window = (int)(h->tree_max_leaf < 0x7FFFFFFF ? h->tree_max_leaf : 0x7FFFFFFF);
     a.leaf_keys = nullptr;
     a.leaf_key_count = 0;
     a.learned_cpl = 0;
@@ -312,6 +350,96 @@ paris_status collect_pending(paris_index* h)
             paris_status s = collect_timing(h, set);
             if (s != PARIS_OK) return s;
         }
+    return PARIS_OK;
+}
+
+// ADS+ tree build (leaf mode 2): the root subtrees from the root offsets, then rounds that split,
+// in ascending node id, every leaf holding more than cap series with a segment below 8 bits
+// (the kernels choose the segment and partition the leaf order). The host lists each round's
+// nodes and cuts them into chunks; after the round it reads the new children back to list the
+// next round. Returns the node count and the size of the largest leaf.
+paris_status build_tree(const Plan& plan, uint8_t* ws, long long N, int cap, hipStream_t st, long long* n_nodes,
+                        long long* max_leaf_out)
+{
+    AdsNode* nodes = reinterpret_cast<AdsNode*>(ws + plan.tree);
+    const uint32_t* roff = reinterpret_cast<const uint32_t*>(ws + plan.roff);
+    HIP_TRY(launch_tree_roots(roff, nodes, st));
+    std::vector<uint32_t> hroff(kRoots + 1);
+    HIP_TRY(hipMemcpyAsync(hroff.data(), roff, (size_t)(kRoots + 1) * 4, hipMemcpyDeviceToHost, st));
+    HIP_TRY(hipStreamSynchronize(st));
+    struct Item {
+        int32_t id;
+        uint32_t start, end;
+    };
+    std::vector<Item> todo, nt;
+    long long max_leaf = 0;
+    for (int r = 0; r < kRoots; ++r) {
+        const long long sz = (long long)hroff[r + 1] - hroff[r];
+        if (sz > cap) todo.push_back({r, hroff[r], hroff[r + 1]});
+        else if (sz > max_leaf) max_leaf = sz;
+    }
+    TreeRound R;
+    R.nodes = nodes;
+    R.todo = reinterpret_cast<const int32_t*>(ws + plan.tree_todo);
+    R.todo_chunks = reinterpret_cast<const uint32_t*>(ws + plan.tree_todo_chunks);
+    R.todo_split = reinterpret_cast<int32_t*>(ws + plan.tree_split);
+    R.chunks = reinterpret_cast<const TreeChunk*>(ws + plan.tree_chunks);
+    R.chunk_ones = reinterpret_cast<uint32_t*>(ws + plan.tree_ones);
+    R.chunk_dst = reinterpret_cast<uint2*>(ws + plan.tree_dst);
+    R.sax = ws + plan.sax;
+    R.perm = reinterpret_cast<uint32_t*>(ws + plan.perm);
+    R.perm_tmp = reinterpret_cast<uint32_t*>(ws + plan.surv);   // 4N of the 8N survivor bytes
+    long long next = kRoots;
+    std::vector<int32_t> h_todo;
+    std::vector<uint32_t> h_tc;
+    std::vector<TreeChunk> h_chunks;
+    std::vector<AdsNode> kids;
+    while (!todo.empty()) {
+        const long long n = (long long)todo.size();
+        long long chunks = 0;
+        for (const Item& it : todo) chunks += ((long long)it.end - it.start + kTreeChunk - 1) / kTreeChunk;
+        if (next + 2 * n > plan.node_cap || n > plan.todo_cap || chunks > plan.chunk_cap) {
+            // out of node room: these stay leaves
+            for (const Item& it : todo)
+                if ((long long)it.end - it.start > max_leaf) max_leaf = (long long)it.end - it.start;
+            break;
+        }
+        h_todo.resize(n);
+        h_tc.resize(n + 1);
+        h_chunks.clear();
+        for (long long i = 0; i < n; ++i) {
+            h_todo[i] = todo[i].id;
+            h_tc[i] = (uint32_t)h_chunks.size();
+            for (uint32_t a = todo[i].start; a < todo[i].end; a += kTreeChunk) {
+                const uint32_t b = todo[i].end - a > (uint32_t)kTreeChunk ? a + kTreeChunk : todo[i].end;
+                h_chunks.push_back(TreeChunk{(uint32_t)i, a, b, 0u});
+            }
+        }
+        h_tc[n] = (uint32_t)h_chunks.size();
+        HIP_TRY(hipMemcpyAsync(ws + plan.tree_todo, h_todo.data(), (size_t)n * 4, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(ws + plan.tree_todo_chunks, h_tc.data(), (size_t)(n + 1) * 4, hipMemcpyHostToDevice, st));
+        HIP_TRY(hipMemcpyAsync(ws + plan.tree_chunks, h_chunks.data(), h_chunks.size() * sizeof(TreeChunk),
+                               hipMemcpyHostToDevice, st));
+        R.n_todo = (int)n;
+        R.next = (int)next;
+        HIP_TRY(launch_tree_round(R, (int)h_chunks.size(), st));
+        kids.resize(2 * n);
+        HIP_TRY(hipMemcpyAsync(kids.data(), nodes + next, (size_t)(2 * n) * sizeof(AdsNode), hipMemcpyDeviceToHost, st));
+        HIP_TRY(hipStreamSynchronize(st));
+        nt.clear();
+        for (long long j = 0; j < 2 * n; ++j) {
+            const AdsNode& k = kids[j];
+            const long long sz = (long long)k.end - k.start;
+            bool open = false;
+            for (int sg = 0; sg < kSeg; ++sg) open |= k.card[sg] < 8;
+            if (sz > cap && open) nt.push_back({(int32_t)(next + j), k.start, k.end});
+            else if (sz > max_leaf) max_leaf = sz;
+        }
+        next += 2 * n;
+        todo.swap(nt);
+    }
+    *n_nodes = next;
+    *max_leaf_out = max_leaf;
     return PARIS_OK;
 }
 
@@ -1006,6 +1134,7 @@ paris_status paris_default_config(paris_config* cfg)
     cfg->leaf_mode = PARIS_LEAF_ROOT16;
     cfg->n_leaves = 4096;
     cfg->seed_cap = 16384;
+    cfg->leaf_cap = 2048;
     return PARIS_OK;
 }
 
@@ -1013,7 +1142,7 @@ paris_status paris_workspace_size(int64_t n_series, int32_t length, const paris_
 {
     if (!bytes || !config_ok(cfg) || !shape_ok(n_series, length)) return PARIS_EINVAL;
     Plan p;
-    make_plan(n_series, &p);
+    make_plan(n_series, &p, cfg);
     *bytes = p.total;
     return PARIS_OK;
 }
@@ -1027,7 +1156,7 @@ paris_status paris_build(const float* series_dev, int64_t n_series, int32_t leng
         reinterpret_cast<uintptr_t>(workspace_dev) % kAlign != 0)
         return PARIS_EINVAL;
     Plan plan;
-    make_plan(n_series, &plan);
+    make_plan(n_series, &plan, cfg);
     if (workspace_bytes < plan.total) return PARIS_ENOMEM;
     paris_status ds = device_ok();
     if (ds != PARIS_OK) return ds;
@@ -1043,6 +1172,12 @@ paris_status paris_build(const float* series_dev, int64_t n_series, int32_t leng
                              reinterpret_cast<uint32_t*>(ws + plan.perm_alt),
                              reinterpret_cast<uint32_t*>(ws + plan.hist), n_series, st));
     HIP_TRY(launch_root_offsets(keys, n_series, reinterpret_cast<uint32_t*>(ws + plan.roff), st));
+    long long tree_nodes = 0, tree_max_leaf = 0;
+    if (cfg->leaf_mode == PARIS_LEAF_ADS) {
+        paris_status ts = build_tree(plan, ws, n_series, cfg->leaf_cap, st, &tree_nodes, &tree_max_leaf);
+        if (ts != PARIS_OK) return ts;
+        HIP_TRY(launch_tree_keys(ws + plan.sax, perm, n_series, keys, st));
+    }
     HIP_TRY(launch_gather_sax(ws + plan.sax, perm, n_series, ws + plan.saxs, st));
     uint32_t herr = 0;
     HIP_TRY(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, st));
@@ -1107,6 +1242,8 @@ paris_status paris_build(const float* series_dev, int64_t n_series, int32_t leng
     h->timed_chunks = 0;
     h->model = nullptr;
     h->learned = false;
+    h->n_tree_nodes = tree_nodes;
+    h->tree_max_leaf = tree_max_leaf;
     if (hipHostMalloc(reinterpret_cast<void**>(&h->host_qs), sizeof(QState), hipHostMallocDefault) != hipSuccess ||
         hipHostMalloc(reinterpret_cast<void**>(&h->host_res), kHostResBytes, hipHostMallocMapped) != hipSuccess ||
         hipHostGetDevicePointer(reinterpret_cast<void**>(&h->host_res_dev), h->host_res, 0) != hipSuccess) {
@@ -1151,6 +1288,10 @@ paris_status paris_get_layout(const paris_index* h, paris_layout* o)
     o->scan_threads = h->scan.threads;
     o->scan_blocks_per_cu = h->scan.per_cu;
     o->scan_unroll = h->scan.unroll;
+    const bool tree = h->cfg.leaf_mode == PARIS_LEAF_ADS;
+    o->tree_nodes_dev = tree ? static_cast<const void*>(h->ws + h->plan.tree) : nullptr;
+    o->n_tree_nodes = tree ? h->n_tree_nodes : 0;
+    o->tree_max_leaf = tree ? h->tree_max_leaf : 0;
     return PARIS_OK;
 }
 

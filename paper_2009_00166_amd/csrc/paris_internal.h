@@ -91,6 +91,49 @@ hipError_t launch_root_offsets(const unsigned long long* keys, long long N, uint
                                hipStream_t st);
 hipError_t launch_gather_sax(const uint8_t* sax, const uint32_t* perm, long long N, uint8_t* saxs, hipStream_t st);
 
+// ---- ADS+ tree (leaf mode 2) ----
+constexpr int kRoots = 65536;       // root subtrees: node r is root key r
+constexpr int kTreeChunk = 4096;    // positions per work item of a tree-building round
+constexpr int kTreeMaxDepth = 112;  // 16 segments x 7 extra bits: splits along any path
+
+// A node of the tree (32 bytes): its range of the leaf order, its children (child0 and
+// child0 + 1, the bit-0 and bit-1 children; -1 for a leaf), the segment its split refines and
+// the bits it fixes per segment.
+struct AdsNode {
+    uint32_t start, end;
+    int32_t child0;
+    int32_t split;
+    uint8_t card[kSeg];
+};
+static_assert(sizeof(AdsNode) == 32, "tree nodes are 32 bytes");
+
+struct TreeChunk {
+    uint32_t slot;          // index of its node in the round's list
+    uint32_t start, end;    // positions of the leaf order
+    uint32_t pad;
+};
+
+// One round of the tree build: the nodes that split (ascending ids), their chunks, the scratch.
+struct TreeRound {
+    AdsNode* nodes;
+    const int32_t* todo;          // [n_todo] node ids
+    const uint32_t* todo_chunks;  // [n_todo + 1] first chunk of every node
+    int32_t* todo_split;          // [n_todo] chosen segment
+    int n_todo;
+    int next;                     // id of the first child created in this round
+    const TreeChunk* chunks;
+    uint32_t* chunk_ones;         // [chunks][16] series whose next bit is 1
+    uint2* chunk_dst;             // [chunks] first destination of a zero / of a one
+    const uint8_t* sax;
+    uint32_t* perm;
+    uint32_t* perm_tmp;
+};
+
+hipError_t launch_tree_roots(const uint32_t* roff, AdsNode* nodes, hipStream_t st);
+hipError_t launch_tree_round(const TreeRound& r, int n_chunks, hipStream_t st);
+hipError_t launch_tree_keys(const uint8_t* sax, const uint32_t* perm, long long N, unsigned long long* keys,
+                            hipStream_t st);
+
 // ---- query kernels ----
 struct QueryArgs {
     const float* X;
@@ -125,6 +168,9 @@ struct QueryArgs {
     int knn_r;
     unsigned long long* knn_slots;  // [kKnnMax] (float32 bits of ED^2, index) keys
     KnnHit* knn_out;                // [kKnnMax] answers of the last block (mapped host memory)
+    // leaf mode 2 (ADS+ tree): the nodes, and the largest window the approximate search reaches
+    const AdsNode* tree;
+    int tree_window;
 };
 
 // ---- batched path ----

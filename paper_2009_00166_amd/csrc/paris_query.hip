@@ -338,7 +338,77 @@ __global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* 
         wl = ell * N / nl;
         wh = (ell + 1) * N / nl;
     };
-    if (A.knn_k > 0 && !learned && (A.leaf_mode != 0 || A.seed_cap > 0)) {
+    // the query's root subtree, or when it is empty the non-empty one with the smallest
+    // cardinality-2 lower bound (ties: the lowest root key); whole block
+    auto pick_root = [&](uint32_t R) -> uint32_t {
+        if (A.roff[R] != A.roff[R + 1]) return R;   // uniform
+        double best = __builtin_inf();
+        int br = 0x7FFFFFFF;
+        for (int r = tid * 256; r < tid * 256 + 256; ++r) {
+            if (A.roff[r + 1] == A.roff[r]) continue;
+            double acc = 0.0;
+            for (int s = 0; s < kSeg; ++s) {
+                const int bx = (r >> (15 - s)) & 1;
+                const double x = qpaa[s];
+                double d = 0.0;
+                if (bx == 1 && x < 0.0) d = 0.0 - x;       // region [0, +inf)
+                else if (bx == 0 && x > 0.0) d = x - 0.0;  // region (-inf, 0)
+                acc = acc + d * d;
+            }
+            const double lbv = (double)L * acc;
+            if (lbv < best) { best = lbv; br = r; }  // ascending r: ties keep the lowest
+        }
+        red_lb[tid] = best;
+        red_r[tid] = br;
+        __syncthreads();
+        for (int off = 128; off > 0; off >>= 1) {
+            if (tid < off) {
+                const double b2 = red_lb[tid + off];
+                const int r2 = red_r[tid + off];
+                if (b2 < red_lb[tid] || (b2 == red_lb[tid] && r2 < red_r[tid])) {
+                    red_lb[tid] = b2;
+                    red_r[tid] = r2;
+                }
+            }
+            __syncthreads();
+        }
+        return (uint32_t)red_r[0];
+    };
+    // ADS+ tree: from root subtree R down to a leaf, following the query's next bit of every
+    // split's segment; a child on the query's side that is empty sends it to its sibling. Every
+    // thread walks the same path (the node loads are shared by the wave).
+    auto tree_leaf = [&](uint32_t R, long long& wl, long long& wh) {
+        int v = (int)R;
+        for (;;) {
+            const AdsNode nd = A.tree[v];
+            if (nd.child0 < 0) {
+                wl = nd.start;
+                wh = nd.end;
+                return;
+            }
+            const int sg = nd.split;
+            const int b = (qsym[sg] >> (7 - nd.card[sg])) & 1;
+            int c = nd.child0 + b;
+            if (A.tree[c].start == A.tree[c].end) c = nd.child0 + 1 - b;
+            v = c;
+        }
+    };
+    if (A.leaf_mode == 2 && !learned) {
+        if (A.seed_cap > 0) {
+            tree_leaf(pick_root(s_root), lo, hi);
+            if (A.knn_k > 0) {
+                // exact k-NN: kKnnWindow positions of the leaf order centred on the reached leaf
+                const long long N = A.N;
+                long long a = (lo + hi) / 2 - kKnnWindow / 2;
+                if (a > N - kKnnWindow) a = N - kKnnWindow;
+                if (a < 0) a = 0;
+                lo = a;
+                hi = (a + kKnnWindow < N) ? a + kKnnWindow : N;
+            } else if (hi - lo > A.seed_cap) {
+                hi = lo + A.seed_cap;
+            }
+        }
+    } else if (A.knn_k > 0 && !learned && (A.leaf_mode != 0 || A.seed_cap > 0)) {
         // exact k-NN: kKnnWindow consecutive sorted positions centred on the lower bound of the
         // query's leaf key in the whole order (a small root subtree would hold fewer than k)
         const long long N = A.N;
@@ -368,45 +438,9 @@ __global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* 
         leaf_window(0, lo, hi);
     } else if (A.leaf_mode == 0) {
         if (A.seed_cap > 0) {
-            uint32_t R = s_root;
+            const uint32_t R = pick_root(s_root);
             lo = A.roff[R];
             hi = A.roff[R + 1];
-            if (lo == hi) {
-                // empty subtree: the non-empty one with the smallest cardinality-2 lower bound
-                double best = __builtin_inf();
-                int br = 0x7FFFFFFF;
-                for (int r = tid * 256; r < tid * 256 + 256; ++r) {
-                    if (A.roff[r + 1] == A.roff[r]) continue;
-                    double acc = 0.0;
-                    for (int s = 0; s < kSeg; ++s) {
-                        const int bx = (r >> (15 - s)) & 1;
-                        const double x = qpaa[s];
-                        double d = 0.0;
-                        if (bx == 1 && x < 0.0) d = 0.0 - x;       // region [0, +inf)
-                        else if (bx == 0 && x > 0.0) d = x - 0.0;  // region (-inf, 0)
-                        acc = acc + d * d;
-                    }
-                    const double lbv = (double)L * acc;
-                    if (lbv < best) { best = lbv; br = r; }  // ascending r: ties keep the lowest
-                }
-                red_lb[tid] = best;
-                red_r[tid] = br;
-                __syncthreads();
-                for (int off = 128; off > 0; off >>= 1) {
-                    if (tid < off) {
-                        const double b2 = red_lb[tid + off];
-                        const int r2 = red_r[tid + off];
-                        if (b2 < red_lb[tid] || (b2 == red_lb[tid] && r2 < red_r[tid])) {
-                            red_lb[tid] = b2;
-                            red_r[tid] = r2;
-                        }
-                    }
-                    __syncthreads();
-                }
-                R = (uint32_t)red_r[0];
-                lo = A.roff[R];
-                hi = A.roff[R + 1];
-            }
             if (hi - lo > A.seed_cap) {
                 const long long c = block_lower_bound(A.keys, lo, hi, kq, &s_cnt);
                 long long a = c - A.seed_cap / 2;
@@ -588,6 +622,7 @@ int seed_grid(const QueryArgs& a)
     if (a.knn_k > 0 && (a.leaf_mode != 0 || a.seed_cap > 0)) return kKnnWindow / kSeedChunk;
     long long win = 0;
     if (a.leaf_mode == 0) win = a.seed_cap;
+    else if (a.leaf_mode == 2) win = a.seed_cap < a.tree_window ? a.seed_cap : a.tree_window;
     else win = (a.N + a.n_leaves - 1) / a.n_leaves;
     long long g = (win + kSeedChunk - 1) / kSeedChunk;
     return (int)(g < 1 ? 1 : g);
