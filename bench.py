@@ -7,7 +7,8 @@ the timed region (the build time is reported beside). Inputs are resident in HBM
 
 Beside the headline the default run records: the scan cold (caches swept before every query);
 the best-so-far sharing ablation on hard queries (with the refine kernel's bytes per second);
-exact k-NN (k = 10 and 64) on 200 of the queries;
+exact k-NN (k = 10 and 64) on 200 of the queries; the ADS+ tree leaf mode and the collection in
+pinned host memory (out of core);
 batches of 4096 through the batched pipeline (paris_query_batch) with a brute-force check of 64
 of their answers; the CPU oracle (brute force over all host threads, and on one thread the
 median latency of brute force and of the serial exact-search twin over 20 queries); the learned
@@ -17,7 +18,7 @@ seed on 50,000,000 x 256 with 4096 equal-count leaves; and the mixed-length work
 Prints one JSON line. Options: --gpus N (only 1 is supported: the benchmark measures one GPU),
 --steps K, --warmup W, --queries Q, --series N, --length n, --fresh-queries (new random walks
 as queries, the paper's workload), --no-cpu-baseline, --cpu-single S, --oracle-check C,
---no-knn, --no-batched, --batch B, --batch-steps K, --cold-queries C, --no-nb-ablation, --no-learned,
+--no-knn, --no-tree, --no-batched, --batch B, --batch-steps K, --cold-queries C, --no-nb-ablation, --no-learned,
 --learned-series N (0: the main collection), --train-queries T, --epochs E, --eval-queries V,
 --learned-only, --multi (only the mixed-length workload), --no-multi, --multi-scale F.
 """
@@ -235,6 +236,89 @@ def knn_section(index, X, Q, args, count: int = 200):
     return out
 
 
+def tree_and_host_section(index, X, Q, answers, args):
+    """The ADS+ tree leaf mode (Section 2.2 node splitting, bulk loaded on the GPU) and the
+    out-of-core collection (raw series in pinned host memory, index in HBM, rows read over PCIe)
+    on the main collection: build times, tree shape, per-query queries/s on the plain workload's
+    queries and on hard ones (noise 0.5), batched queries/s, answers against the in-HBM root16
+    index."""
+    import numpy as np
+    import torch
+    import paper_2009_00166_amd as paris
+    import synth
+    N, n = X.shape
+    M = min(1000, Q.shape[0])
+    Qd = torch.from_numpy(np.ascontiguousarray(Q[:M])).to("cuda:0")
+    rows = [Qd[m] for m in range(M)]
+    Qh, _, _ = synth.noisy_queries(X, 200, seed=4, sigma=0.5)
+    Qhd = torch.from_numpy(Qh).to("cuda:0")
+    hrows = [Qhd[m] for m in range(Qh.shape[0])]
+    ref_h = [index.query(r)[0] for r in hrows]
+
+    def per_query(ix, rs):
+        for r in rs[:20]:
+            ix.query(r)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        got = [ix.query(r)[0] for r in rs]
+        return len(rs) / (time.perf_counter() - t0), got
+
+    def batched(ix):
+        B = args.batch
+        Qb, _, _ = synth.noisy_queries(X, B, seed=1, sigma=(0.01, 0.5))
+        Qbd = torch.from_numpy(Qb).cuda()
+        ix.attach_batch(max_batch=B)
+        I, D = ix.query_batch(Qbd)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.batch_steps):
+            ix.query_batch(Qbd, out=(I, D))
+        torch.cuda.synchronize()
+        return B * args.batch_steps / (time.perf_counter() - t0), I.cpu().numpy(), Qbd
+
+    out = {}
+    Xd = index.series
+    t0 = time.perf_counter()
+    tree = paris.build(Xd, leaf_mode=paris.LEAF_ADS, leaf_cap=2048)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    t = tree.tree_nodes()
+    leaves = t["child0"] < 0
+    sizes = (t["end"] - t["start"])[leaves]
+    qps, got = per_query(tree, rows)
+    hqps, hgot = per_query(tree, hrows)
+    out["ads_tree"] = {"leaf_cap": 2048, "build_ms": tb * 1e3, "nodes": int(len(t["start"])),
+                       "leaves_nonempty": int((sizes > 0).sum()), "largest_leaf": int(sizes.max()),
+                       "mean_nonempty_leaf": float(sizes[sizes > 0].mean()),
+                       "per_query_queries_per_s": qps, "hard_queries_per_s": hqps,
+                       "answers_equal_root16": bool(np.array_equal(got, answers[:M]) and hgot == ref_h)}
+    log(f"ADS+ tree: built in {tb * 1e3:.0f} ms, {len(t['start'])} nodes; {qps:.0f} q/s, hard {hqps:.0f} q/s")
+    tree.close()
+    # out of core: the same series in pinned host memory
+    coll = paris.HostCollection(N, n)
+    np.copyto(coll.array, X)
+    t0 = time.perf_counter()
+    host = paris.build(coll)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    qps, got = per_query(host, rows)
+    hqps, hgot = per_query(host, hrows)
+    bqps, bI, Qbd = batched(host)
+    ref_b, _ = index.query_batch(Qbd)
+    torch.cuda.synchronize()
+    out["host_collection"] = {
+        "where": f"{N} x {n} float32 ({X.nbytes / 1e9:.1f} GB) in pinned host memory mapped for the GPU; "
+                 "index, iSAX words and the batched path's bfloat16 copy in HBM",
+        "build_ms": tb * 1e3, "build_GBps_raw_over_pcie": X.nbytes / tb / 1e9,
+        "per_query_queries_per_s": qps, "hard_queries_per_s": hqps, "batched_queries_per_s": bqps,
+        "answers_equal_in_hbm": bool(np.array_equal(got, answers[:M]) and hgot == ref_h
+                                     and np.array_equal(bI, ref_b.cpu().numpy()))}
+    log(f"host collection: built in {tb * 1e3:.0f} ms; {qps:.0f} q/s, hard {hqps:.0f} q/s, batched {bqps:.0f} q/s")
+    host.close()
+    coll.close()
+    return out
+
+
 def main() -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -257,6 +341,8 @@ def main() -> int:
                     help="batched answers checked against the brute-force oracle per batch record")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-knn", action="store_true", help="skip the exact k-NN sub-record")
+    ap.add_argument("--no-tree", action="store_true",
+                    help="skip the ADS+ tree and host-resident collection sub-record")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--batch-steps", type=int, default=3)
@@ -419,6 +505,8 @@ def main() -> int:
     }
     if not args.no_batched:
         rec["batched"] = batched_section(index, X, args)
+    if not args.no_tree:
+        rec["tree_and_host_collection"] = tree_and_host_section(index, X, Q, answers, args)
     if not args.no_cpu_baseline:
         log("timing the CPU oracle on a sample")
         rec["cpu_baseline"] = cpu_baseline(X, Q, answers, min(args.cpu_queries, M), args.cpu_threads,

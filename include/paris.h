@@ -143,6 +143,21 @@ paris_status paris_build(const float *series_dev, int64_t n_series, int32_t leng
                          const paris_config *cfg, void *workspace_dev, size_t workspace_bytes,
                          void *hip_stream, paris_index **out);
 
+/*
+ * Out-of-core collections (the paper's setting of Section 3: the raw data stay outside the memory
+ * that holds the index, and only the series the lower bound cannot prune are read). A collection
+ * in host memory from paris_host_alloc can be passed to paris_build as series_dev (its device
+ * address): the index (iSAX words, leaf order, tree, workspaces, the batched path's bfloat16
+ * copy) lives in HBM, while the summarisation, the approximate search, the refinement, the
+ * batched re-score and the float64 resolve read the raw series over PCIe. Answers are identical.
+ *   paris_host_alloc   pinned host memory of `bytes` (256-byte aligned), mapped for the current
+ *                      device: *host_ptr for the host, *dev_ptr for the kernels. PARIS_ENOMEM if
+ *                      the allocation fails.
+ *   paris_host_free    releases it (after every index built on it is freed).
+ */
+paris_status paris_host_alloc(size_t bytes, void **host_ptr, void **dev_ptr);
+paris_status paris_host_free(void *host_ptr);
+
 /* Addresses and shape of a built index (host-only call). */
 paris_status paris_get_layout(const paris_index *idx, paris_layout *out);
 

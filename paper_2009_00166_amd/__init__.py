@@ -17,7 +17,7 @@ import ctypes
 from ._binding import (LEAF_ADS, LEAF_EQUAL_COUNT, LEAF_ROOT16, PARIS_OK, ParisConfig, ParisError,  # noqa: F401
                        ParisLayout, ParisQueryInfo, ParisStats, check, load_library)
 
-__all__ = ["build", "Index", "ParisError", "LEAF_ROOT16", "LEAF_EQUAL_COUNT", "LEAF_ADS", "load_library"]
+__all__ = ["build", "Index", "HostCollection", "ParisError", "LEAF_ROOT16", "LEAF_EQUAL_COUNT", "LEAF_ADS", "load_library"]
 
 
 def _torch():
@@ -68,17 +68,52 @@ def workspace_size(n_series: int, length: int, cfg: ParisConfig | None = None) -
     return int(out.value)
 
 
+class HostCollection:
+    """A collection kept out of HBM: pinned host memory from paris_host_alloc, mapped for the
+    device. Fill ``array`` (numpy float32 [n_series, length]) and pass the object to ``build``:
+    the index lives in HBM, the raw series are read over PCIe."""
+
+    def __init__(self, n_series: int, length: int):
+        import numpy as np
+        self.n_series, self.length = int(n_series), int(length)
+        host, dev = ctypes.c_void_p(), ctypes.c_void_p()
+        check(load_library().paris_host_alloc(4 * self.n_series * self.length, ctypes.byref(host),
+                                              ctypes.byref(dev)), "paris_host_alloc")
+        self._host, self.dev_ptr = host, int(dev.value)
+        buf = (ctypes.c_float * (self.n_series * self.length)).from_address(host.value)
+        self.array = np.ctypeslib.as_array(buf).reshape(self.n_series, self.length)
+        self.shape = (self.n_series, self.length)
+
+    def close(self):
+        if getattr(self, "_host", None) is not None and self._host.value:
+            self.array = None
+            load_library().paris_host_free(self._host)
+            self._host = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 class Index:
-    """A built index. Borrows the series tensor and owns a workspace tensor."""
+    """A built index. Borrows the series (a device tensor or a HostCollection) and owns a
+    workspace tensor."""
 
     def __init__(self, series, cfg: ParisConfig | None = None, stream=None):
         torch = _torch()
         lib = load_library()
-        p = _dev_ptr(series, torch.float32, 2, "series")
+        if isinstance(series, HostCollection):
+            p = ctypes.c_void_p(series.dev_ptr)
+            device = torch.device("cuda", torch.cuda.current_device())
+        else:
+            p = _dev_ptr(series, torch.float32, 2, "series")
+            device = series.device
         n_series, length = series.shape
         self.cfg = cfg or default_config()
         nbytes = workspace_size(n_series, length, self.cfg)
-        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=series.device)
+        self.workspace = torch.empty(nbytes, dtype=torch.uint8, device=device)
         self.series = series  # keep the borrowed collection alive
         self.n_series, self.length = int(n_series), int(length)
         self._h = ctypes.c_void_p()
@@ -87,7 +122,7 @@ class Index:
                               ctypes.byref(self._h)), "paris_build")
         # reused by every query() call (the per-query path is latency-bound)
         self._torch = torch
-        self._dev = series.device.index if series.device.index is not None else torch.cuda.current_device()
+        self._dev = device.index if device.index is not None else torch.cuda.current_device()
         self._query_fn = lib.paris_query_exact
         self._idx = ctypes.c_int64(-1)
         self._dist = ctypes.c_double(0.0)
@@ -258,7 +293,7 @@ class Index:
         nbytes = ctypes.c_size_t(0)
         check(lib.paris_batch_workspace_size(self._h, int(max_batch), ctypes.byref(nbytes)),
               "paris_batch_workspace_size")
-        ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.series.device)
+        ws = torch.empty(int(nbytes.value), dtype=torch.uint8, device=self.workspace.device)
         check(lib.paris_batch_attach(self._h, ctypes.c_void_p(ws.data_ptr()), int(nbytes.value),
                                      int(max_batch), _stream_ptr(stream)), "paris_batch_attach")
         self.batch_workspace = ws
@@ -386,7 +421,8 @@ __all__ += ["SeedModel", "init_params", "query_features", "train_seed_model"]
 
 
 def build(series, cfg: ParisConfig | None = None, stream=None, **cfg_kw) -> Index:
-    """Summarise a float32 [N, n] device tensor and build its index (synchronous)."""
+    """Summarise a float32 [N, n] device tensor (or a HostCollection) and build its index
+    (synchronous)."""
     if cfg is None:
         cfg = default_config(**cfg_kw)
     return Index(series, cfg, stream)

@@ -94,6 +94,8 @@ SIGNATURES = [
     ("paris_mlp_free", ctypes.c_int, [_P]),
     ("paris_leaf_of", ctypes.c_int, [_P, _P, _I64, _P, _P]),
     ("paris_set_seed_model", ctypes.c_int, [_P, _P, _I32]),
+    ("paris_host_alloc", ctypes.c_int, [ctypes.c_size_t, ctypes.POINTER(_P), ctypes.POINTER(_P)]),
+    ("paris_host_free", ctypes.c_int, [_P]),
     ("paris_status_string", ctypes.c_char_p, [ctypes.c_int]),
 ]
 

@@ -554,7 +554,11 @@ paris_status tune_scan(paris_index* h, hipStream_t st)
     // Infinity Cache (only possible when the collection is that large).
     const size_t raw = (size_t)h->N * h->n * 4;
     const size_t sweep = raw < ((size_t)1 << 30) ? raw : ((size_t)1 << 30);
-    const bool cold = (size_t)h->N * 16 > ((size_t)32 << 20) && sweep >= ((size_t)512 << 20);
+    // (a collection in host memory is read over PCIe and never evicts the device caches)
+    hipPointerAttribute_t pa;
+    const bool host_coll = hipPointerGetAttributes(&pa, h->X) == hipSuccess && pa.type == hipMemoryTypeHost;
+    (void)hipGetLastError();
+    const bool cold = !host_coll && (size_t)h->N * 16 > ((size_t)32 << 20) && sweep >= ((size_t)512 << 20);
     uint32_t* sink = reinterpret_cast<uint32_t*>(h->ws + h->plan.hdr) + 16;
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
@@ -1270,6 +1274,29 @@ paris_status paris_build(const float* series_dev, int64_t n_series, int32_t leng
     }
     *out = h;
     return PARIS_OK;
+}
+
+paris_status paris_host_alloc(size_t bytes, void** host_ptr, void** dev_ptr)
+{
+    if (!host_ptr || !dev_ptr || bytes == 0) return PARIS_EINVAL;
+    paris_status ds = device_ok();
+    if (ds != PARIS_OK) return ds;
+    void* hp = nullptr;
+    if (hipHostMalloc(&hp, bytes, hipHostMallocMapped) != hipSuccess || !hp) return PARIS_ENOMEM;
+    void* dp = nullptr;
+    if (hipHostGetDevicePointer(&dp, hp, 0) != hipSuccess || !dp) {
+        (void)hipHostFree(hp);
+        return PARIS_EHIP;
+    }
+    *host_ptr = hp;
+    *dev_ptr = dp;
+    return PARIS_OK;
+}
+
+paris_status paris_host_free(void* host_ptr)
+{
+    if (!host_ptr) return PARIS_OK;
+    return hipHostFree(host_ptr) == hipSuccess ? PARIS_OK : PARIS_EHIP;
 }
 
 paris_status paris_get_layout(const paris_index* h, paris_layout* o)
