@@ -7,10 +7,12 @@
  * only the best-so-far distance (Section 3.3.3); these calls return the index and the distance.
  *
  * Method: every series is summarised once (paris_build) into a 16-segment, 8-bit iSAX word
- * (Section 2.2: PAA segment means quantised against 255 Gaussian boundaries). A query
- * (paris_query_exact) takes an approximate-search seed as its first best-so-far distance
- * (Section 3.3), scans the whole array of words with the iSAX lower bound and keeps the series
- * the bound cannot prune (the LBC workers of Section 3.3.3), computes real distances of the
+ * (Section 2.2: PAA segment means quantised against 255 Gaussian boundaries), also kept at
+ * cardinality 4 (its symbols' 2-bit prefixes, 4 bytes per series). A query (paris_query_exact)
+ * takes an approximate-search seed as its first best-so-far distance (Section 3.3), scans the
+ * whole array of words with the iSAX lower bound (first on the cardinality-4 words, then on the
+ * full words of the series that pass) and keeps the series the bound cannot prune (the LBC
+ * workers of Section 3.3.3), computes real distances of the
  * survivors with early abandoning while an atomic minimum tightens the best-so-far (the RDC
  * workers), and resolves the final comparison in float64.
  *
@@ -318,8 +320,12 @@ paris_status paris_block_bound_bits(paris_index *idx, const float *queries_dev, 
  *   info          host out (may be NULL).
  *   table_dev     optional device out float32 [16][256]: per-segment lower-bound terms
  *                 L * delta(q_s, c)^2, rounded toward zero (so their sum never exceeds the bound).
- *   coarse_dev    optional device out float32 [16][32]: the same at 32 symbols (5-bit prefix);
- *                 entry g is the minimum of the 8 entries c = 8g .. 8g+7.
+ *   coarse_dev    optional device out float32 [4][256]: the coarse tables of the scan's first
+ *                 pass over the words at cardinality 4 (Section 2.2: a symbol's 2-bit prefix is
+ *                 its symbol at cardinality 4). With T2[s][c] the minimum of the 64 entries
+ *                 64c .. 64c+63 of table_dev's row s, entry (j, b) is
+ *                 (T2[4j][b0] + T2[4j+1][b1]) + (T2[4j+2][b2] + T2[4j+3][b3]) in float32, where
+ *                 b = b0 + 4 b1 + 16 b2 + 64 b3.
  * Synchronous.
  */
 paris_status paris_query_info_get(paris_index *idx, const float *query_dev, paris_query_info *info,

@@ -259,7 +259,7 @@ class Index:
         t8 = t5 = None
         if tables:
             t8 = torch.empty((16, 256), dtype=torch.float32, device=q.device)
-            t5 = torch.empty((16, 32), dtype=torch.float32, device=q.device)
+            t5 = torch.empty((4, 256), dtype=torch.float32, device=q.device)
         check(load_library().paris_query_info_get(
             self._h, qp, ctypes.byref(info), ctypes.c_void_p(t8.data_ptr()) if tables else None,
             ctypes.c_void_p(t5.data_ptr()) if tables else None, _stream_ptr(stream)), "paris_query_info_get")

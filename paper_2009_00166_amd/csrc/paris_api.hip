@@ -22,6 +22,12 @@ using namespace paris;
 namespace {
 
 constexpr uint32_t kMagic = 0x50415249u;  // "PARI"
+// launch shapes of the lower-bound scan: (threads, blocks per CU, 16-byte loads of 4 coarse
+// words per lane in flight)
+constexpr int kScanCands = 8;
+constexpr ScanShape kScanCandidates[kScanCands] = {{512, 2, 1}, {512, 2, 2}, {512, 4, 1}, {512, 1, 4},
+                                                   {256, 4, 1}, {256, 4, 2}, {256, 8, 1}, {256, 3, 4}};
+constexpr int kTunePer = 6;   // queries per candidate in the online phase
 // mapped host buffer of an index: the query result, then the k-NN answers 256 bytes on
 constexpr size_t kHostResBytes = 256 + kKnnMax * sizeof(KnnHit);
 static_assert(sizeof(QResult) <= 256, "the k-NN answers follow the result at 256 bytes");
@@ -32,7 +38,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 // Workspace layout. The radix-sort scratch (alternate keys / positions / histograms) is only
 // needed during the build and aliases the survivor and completed-candidate buffers.
 struct Plan {
-    size_t hdr, sax, saxs, keys, perm, roff, qs, t8, t5, knn, surv, done, total;
+    size_t hdr, sax, saxs, csax, keys, perm, roff, qs, t8, tc, knn, surv, done, total;
     size_t keys_alt, perm_alt, hist;
     // ADS+ tree (leaf mode 2): nodes, and the scratch of a build round (todo ids, chunk starts,
     // splits; chunks, their counts and destinations); 0 otherwise
@@ -58,12 +64,13 @@ void make_plan(long long N, Plan* p, const paris_config* cfg)
     p->hdr = take(256);
     p->sax = take((size_t)N * 16);
     p->saxs = take((size_t)N * 16);
+    p->csax = take((size_t)(N + 3) / 4 * 16);
     p->keys = take((size_t)N * 8);
     p->perm = take((size_t)N * 4);
     p->roff = take(65537 * 4);
     p->qs = take(sizeof(QState));
     p->t8 = take(kSeg * kSym * 4);
-    p->t5 = take(kSeg * kCoarse * 4);
+    p->tc = take(kGroups * kGroupCodes * 4);
     p->knn = take(kKnnMax * 8);
     p->surv = take((size_t)N * 8);
     // every survivor completes at most once, plus the head survivor computed first (it is also
@@ -202,6 +209,11 @@ struct paris_index {
     KnnHit* host_knn_dev;
     Margins mg;
     ScanShape scan;
+    // online scan tuning: the first kScanCands * kTunePer queries cycle through the candidate
+    // shapes, each scan timed by events bound to its dispatch; the smallest median wins
+    int scan_online;        // queries left in the online phase (0: done or off)
+    bool scan_decide;       // the phase is over and its events await reading
+    hipEvent_t tune_ev[kScanCands * kTunePer][2];
     int refine_blocks;
     int refine_lanes;
     int bsf_private;        // 1 (default): per-group best-so-far copies; 0: one shared best-so-far
@@ -256,6 +268,7 @@ QueryArgs args_for(const paris_index* h)
     a.n = h->n;
     a.sax = ws + h->plan.sax;
     a.saxs = ws + h->plan.saxs;
+    a.csax = reinterpret_cast<const uint32_t*>(ws + h->plan.csax);
     a.keys = reinterpret_cast<const unsigned long long*>(ws + h->plan.keys);
     a.perm = reinterpret_cast<const uint32_t*>(ws + h->plan.perm);
     a.roff = reinterpret_cast<const uint32_t*>(ws + h->plan.roff);
@@ -264,7 +277,7 @@ QueryArgs args_for(const paris_index* h)
     a.seed_cap = h->cfg.seed_cap;
     a.qs = reinterpret_cast<QState*>(ws + h->plan.qs);
     a.t8 = reinterpret_cast<float*>(ws + h->plan.t8);
-    a.t5 = reinterpret_cast<float*>(ws + h->plan.t5);
+    a.tc = reinterpret_cast<float*>(ws + h->plan.tc);
     a.surv = reinterpret_cast<uint2*>(ws + h->plan.surv);
     a.surv_cap = (uint32_t)h->N;
     a.done = reinterpret_cast<uint2*>(ws + h->plan.done);
@@ -448,7 +461,7 @@ paris_status build_tree(const Plan& plan, uint8_t* ws, long long N, int cap, hip
 struct QueryScratch {
     QState* qs;
     float* t8;
-    float* t5;
+    float* tc;
     uint2* surv;
     uint32_t surv_cap;
     uint2* done;
@@ -464,7 +477,7 @@ paris_status run_query(paris_index* h, const float* q, hipStream_t st, long long
     if (scratch_in) {
         a.qs = scratch_in->qs;
         a.t8 = scratch_in->t8;
-        a.t5 = scratch_in->t5;
+        a.tc = scratch_in->tc;
         a.surv = scratch_in->surv;
         a.surv_cap = scratch_in->surv_cap;
         a.done = scratch_in->done;
@@ -483,6 +496,34 @@ paris_status run_query(paris_index* h, const float* q, hipStream_t st, long long
         }
     }
     hipEvent_t* ev = h->ev[set];
+    if (h->scan_decide) {
+        // the online phase's scans finished before their queries' results were read back
+        HIP_TRY(hipEventSynchronize(h->tune_ev[kScanCands * kTunePer - 1][1]));
+        float best = 1e30f;
+        for (int c = 0; c < kScanCands; ++c) {
+            float t[kTunePer];
+            for (int k = 0; k < kTunePer; ++k) {
+                const int slot = k * kScanCands + c;
+                t[k] = 1e30f;
+                float ms = 0.f;
+                if (hipEventElapsedTime(&ms, h->tune_ev[slot][0], h->tune_ev[slot][1]) == hipSuccess) t[k] = ms;
+            }
+            for (int i = 1; i < kTunePer; ++i)   // insertion sort
+                for (int j = i; j > 0 && t[j] < t[j - 1]; --j) { const float x = t[j]; t[j] = t[j - 1]; t[j - 1] = x; }
+            const float med = 0.5f * (t[kTunePer / 2 - 1] + t[kTunePer / 2]);
+            if (med < best) { best = med; h->scan = kScanCandidates[c]; }
+        }
+        h->scan_decide = false;
+    }
+    ScanShape shape = h->scan;
+    hipEvent_t se0 = nullptr, se1 = nullptr;
+    if (!timed && h->scan_online > 0) {
+        const int slot = kScanCands * kTunePer - h->scan_online;
+        shape = kScanCandidates[slot % kScanCands];
+        se0 = h->tune_ev[slot][0];
+        se1 = h->tune_ev[slot][1];
+        if (--h->scan_online == 0) h->scan_decide = true;
+    }
     if (timed && all) HIP_TRY(hipEventRecord(ev[0], st));
     if (h->learned) {
         const paris_mlp* m = h->model;
@@ -497,7 +538,7 @@ paris_status run_query(paris_index* h, const float* q, hipStream_t st, long long
     // first kernel); the scan alone: events bound to the scan kernel's dispatch
     if (timed && all) HIP_TRY(hipEventRecord(ev[1], st));
     const bool bind = timed && !all;
-    HIP_TRY(launch_lbscan(a, -1.f, h->scan, st, bind ? ev[1] : nullptr, bind ? ev[2] : nullptr));
+    HIP_TRY(launch_lbscan(a, -1.f, shape, st, bind ? ev[1] : se0, bind ? ev[2] : se1));
     if (timed && all) HIP_TRY(hipEventRecord(ev[2], st));
     HIP_TRY(launch_refine_resolve(a, q, out_idx, out_dist, qi, st));
     if (timed && all) HIP_TRY(hipEventRecord(ev[3], st));
@@ -540,13 +581,13 @@ paris_status tune_scan(paris_index* h, hipStream_t st)
     if (env) {
         int t = 0, b = 0, u = 4;
         const int got = std::sscanf(env, "%d,%d,%d", &t, &b, &u);
-        if (got >= 2 && (t == 256 || t == 512) && b >= 1 && b <= 32 && (u == 2 || u == 4 || u == 8)) {
+        if (got >= 2 && (t == 256 || t == 512) && b >= 1 && b <= 32 && (u == 1 || u == 2 || u == 4)) {
             h->scan = ScanShape{t, b, u};
             return PARIS_OK;
         }
     }
-    const ScanShape cands[] = {{512, 1, 2}, {512, 2, 2}, {512, 4, 2}, {512, 2, 4},
-                               {512, 4, 4}, {256, 4, 4}, {256, 8, 2}, {256, 4, 8}};
+    // (threads, blocks per CU, 16-byte loads of 4 coarse words per lane in flight)
+    const ScanShape* cands = kScanCandidates;
     const QueryArgs a = args_for(h);
     HIP_TRY(launch_prepare_seed(a, h->X, st));  // tables of series 0
     // Cold runs matter when the iSAX array outgrows the L2s; they are preceded by a read-only
@@ -571,7 +612,8 @@ paris_status tune_scan(paris_index* h, hipStream_t st)
             for (int j = i; j > 0 && t[j] < t[j - 1]; --j) { const float x = t[j]; t[j] = t[j - 1]; t[j - 1] = x; }
         return t[kReps / 2];
     };
-    for (const ScanShape& s : cands) {
+    for (int ci = 0; ci < kScanCands; ++ci) {
+        const ScanShape& s = cands[ci];
         float score = 0.f;
         for (int pass = 0; pass < (cold ? 2 : 1); ++pass) {
             float t[kReps];
@@ -1172,6 +1214,7 @@ paris_status paris_build(const float* series_dev, int64_t n_series, int32_t leng
     auto* perm = reinterpret_cast<uint32_t*>(ws + plan.perm);
     HIP_TRY(hipMemsetAsync(err, 0, 256, st));
     HIP_TRY(launch_summarise(series_dev, n_series, length, ws + plan.sax, keys, perm, err, st));
+    HIP_TRY(launch_coarse_words(ws + plan.sax, n_series, reinterpret_cast<uint32_t*>(ws + plan.csax), st));
     HIP_TRY(launch_sort_keys(keys, perm, reinterpret_cast<unsigned long long*>(ws + plan.keys_alt),
                              reinterpret_cast<uint32_t*>(ws + plan.perm_alt),
                              reinterpret_cast<uint32_t*>(ws + plan.hist), n_series, st));
@@ -1200,7 +1243,7 @@ paris_status paris_build(const float* series_dev, int64_t n_series, int32_t leng
     h->ws_bytes = workspace_bytes;
     h->plan = plan;
     h->mg = margins_for_length(length);
-    h->scan = ScanShape{512, 4, 4};
+    h->scan = ScanShape{512, 2, 2};
     h->refine_blocks = kRefineBlocks;
     if (const char* rb = std::getenv("PARIS_REFINE_BLOCKS")) {
         const int v = std::atoi(rb);
@@ -1211,6 +1254,9 @@ paris_status paris_build(const float* series_dev, int64_t n_series, int32_t leng
         const int v = std::atoi(rl);
         if (v == 4 || v == 8 || v == 16) h->refine_lanes = v;
     }
+    h->scan_online = 0;
+    h->scan_decide = false;
+    for (int k = 0; k < kScanCands * kTunePer; ++k) h->tune_ev[k][0] = h->tune_ev[k][1] = nullptr;
     h->bsf_private = 1;   // measured faster on the GPU; paris_set_bsf_sharing(h, 1) for ParIS+'s
     h->timing = false;
     h->timing_mode = 0;
@@ -1262,6 +1308,13 @@ paris_status paris_build(const float* series_dev, int64_t n_series, int32_t leng
     paris_status ts = PARIS_OK;
     if (launch_reset(a, st) != hipSuccess) ts = PARIS_EHIP;
     if (ts == PARIS_OK) ts = tune_scan(h, st);
+    if (ts == PARIS_OK && std::getenv("PARIS_SCAN_SHAPE") == nullptr) {
+        // the build's choice (on a threshold of 0) is refined on the first real queries
+        bool ok = true;
+        for (int k = 0; k < kScanCands * kTunePer && ok; ++k)
+            ok = hipEventCreate(&h->tune_ev[k][0]) == hipSuccess && hipEventCreate(&h->tune_ev[k][1]) == hipSuccess;
+        if (ok) h->scan_online = kScanCands * kTunePer;
+    }
     if (ts != PARIS_OK) {
         (void)hipHostFree(h->host_qs);
         (void)hipHostFree(h->host_res);
@@ -1446,8 +1499,8 @@ constexpr size_t kNaSurvCap = (size_t)PARIS_NOALLOC_MAX_SURVIVORS;
 constexpr size_t kNaDoneCap = (size_t)PARIS_NOALLOC_MAX_COMPLETED;
 constexpr size_t kNaQs = 0;
 constexpr size_t kNaT8 = na_align(kNaQs + sizeof(QState));
-constexpr size_t kNaT5 = na_align(kNaT8 + (size_t)kSeg * kSym * 4);
-constexpr size_t kNaSurv = na_align(kNaT5 + (size_t)kSeg * kCoarse * 4);
+constexpr size_t kNaTc = na_align(kNaT8 + (size_t)kSeg * kSym * 4);
+constexpr size_t kNaSurv = na_align(kNaTc + (size_t)kGroups * kGroupCodes * 4);
 constexpr size_t kNaDone = na_align(kNaSurv + kNaSurvCap * 8);
 constexpr size_t kNaBytes = na_align(kNaDone + kNaDoneCap * 8);
 static_assert(kNaBytes <= ((size_t)20 << 20), "the allocation-free scratch stays below 20 MiB");
@@ -1493,7 +1546,7 @@ paris_status paris_query_exact_noalloc(paris_index* h, const float* query_dev, i
     QueryScratch sc;
     sc.qs = reinterpret_cast<QState*>(base + kNaQs);
     sc.t8 = reinterpret_cast<float*>(base + kNaT8);
-    sc.t5 = reinterpret_cast<float*>(base + kNaT5);
+    sc.tc = reinterpret_cast<float*>(base + kNaTc);
     sc.surv = reinterpret_cast<uint2*>(base + kNaSurv);
     sc.surv_cap = (uint32_t)kNaSurvCap;
     sc.done = reinterpret_cast<uint2*>(base + kNaDone);
@@ -1565,7 +1618,8 @@ paris_status paris_query_info_get(paris_index* h, const float* query_dev, paris_
     const QueryArgs a = args_for(h);
     HIP_TRY(launch_prepare_seed(a, query_dev, st));
     if (table_dev) HIP_TRY(hipMemcpyAsync(table_dev, a.t8, kSeg * kSym * 4, hipMemcpyDeviceToDevice, st));
-    if (coarse_dev) HIP_TRY(hipMemcpyAsync(coarse_dev, a.t5, kSeg * kCoarse * 4, hipMemcpyDeviceToDevice, st));
+    if (coarse_dev)
+        HIP_TRY(hipMemcpyAsync(coarse_dev, a.tc, kGroups * kGroupCodes * 4, hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipMemcpyAsync(h->host_qs, a.qs, sizeof(QState), hipMemcpyDeviceToHost, st));
     HIP_TRY(launch_reset(a, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -1690,6 +1744,9 @@ paris_status paris_free(paris_index* h)
             if (h->ev[set][k]) (void)hipEventDestroy(h->ev[set][k]);
     for (int k = 0; k < 6; ++k)
         if (h->bev[k]) (void)hipEventDestroy(h->bev[k]);
+    for (int k = 0; k < kScanCands * kTunePer; ++k)
+        for (int e = 0; e < 2; ++e)
+            if (h->tune_ev[k][e]) (void)hipEventDestroy(h->tune_ev[k][e]);
     delete h;
     return PARIS_OK;
 }

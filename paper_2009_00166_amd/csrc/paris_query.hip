@@ -67,22 +67,6 @@ __device__ __forceinline__ float fine_lb(const uint4 w, const float* __restrict_
     return (part[0] + part[1]) + (part[2] + part[3]);
 }
 
-// coarse bound: sum over the 16 segments of T5[s][sym_s >> 3]
-__device__ __forceinline__ float coarse_lb(const uint4 w, const float* __restrict__ t5)
-{
-    float part[4];
-#pragma unroll
-    for (int k = 0; k < 4; ++k) {
-        const uint32_t x = word_at(w, k);
-        const float a = t5[(4 * k + 0) * 32 + ((x >> 3) & 31)];
-        const float b = t5[(4 * k + 1) * 32 + ((x >> 11) & 31)];
-        const float c = t5[(4 * k + 2) * 32 + ((x >> 19) & 31)];
-        const float d = t5[(4 * k + 3) * 32 + ((x >> 27) & 31)];
-        part[k] = (a + b) + (c + d);
-    }
-    return (part[0] + part[1]) + (part[2] + part[3]);
-}
-
 __device__ __forceinline__ void reset_state(QState* qs)
 {
     qs->bsf_key = kBsfInit;
@@ -308,11 +292,22 @@ __global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* 
     }
     if (!batch && blockIdx.x == 0) {
         for (int e = tid; e < kSeg * kSym; e += 256) A.t8[e] = t8[e];
-        for (int e = tid; e < kSeg * kCoarse; e += 256) {
-            const float* p = t8 + (e >> 5) * kSym + (e & 31) * 8;
+        // coarse tables: T2[s][c] = min of the 64 fine entries whose symbol's top 2 bits are c
+        // (the term of the region of cardinality 4, never above a member's fine term); entry
+        // (j, b) = (T2[4j][b0] + T2[4j+1][b1]) + (T2[4j+2][b2] + T2[4j+3][b3]), b = b0 + 4 b1 +
+        // 16 b2 + 64 b3 (the first half of the fine bound's summation tree)
+        __shared__ float t2[kSeg * 4];
+        if (tid < kSeg * 4) {
+            const float* p = t8 + (tid >> 2) * kSym + (tid & 3) * 64;
             float m = p[0];
-            for (int k = 1; k < 8; ++k) m = fminf(m, p[k]);
-            A.t5[e] = m;
+            for (int k = 1; k < 64; ++k) m = fminf(m, p[k]);
+            t2[tid] = m;
+        }
+        __syncthreads();
+        for (int e = tid; e < kGroups * kGroupCodes; e += 256) {
+            const int j = e >> 8, b = e & 255;
+            const float* g = t2 + 16 * j;   // segments 4j .. 4j+3, 4 entries each
+            A.tc[e] = (g[0 + (b & 3)] + g[4 + ((b >> 2) & 3)]) + (g[8 + ((b >> 4) & 3)] + g[12 + (b >> 6)]);
         }
         if (tid < kSeg) {
             A.qs->paa[tid] = qpaa[tid];
@@ -645,59 +640,61 @@ hipError_t launch_prepare_seed_batch(const QueryArgs& a, const SeedBatch& b_in, 
 }
 
 // ------------------------------------------------------------------------------------------
-// lbscan (LBC workers): one 16-byte iSAX word per lane per step, U steps loaded ahead into
-// registers (the next group is fetched while the current one is evaluated).
-//   coarse bound: sum over s of T5[s][sym_s >> 3] from LDS. All lanes of a wave read table s at
-//   the same time and table s is 32 consecutive words, so every LDS read is conflict-free
-//   (distinct banks or broadcasts) whatever the symbols are;
-//   fine bound (only lanes the coarse bound did not prune): sum of T8[s][sym_s], also in LDS;
-//   survivors (fine bound <= threshold) are appended with one atomicAdd per wave: ballot, then
-//   each lane's rank among the set lanes below it (mbcnt).
+// lbscan (LBC workers), in two passes over the iSAX words:
+//   coarse: the words at cardinality 4 (4 bytes per series, 4 series per 16-byte load, U loads
+//   per lane in flight): the bound is the sum of 4 lookups in the coarse tables (LDS), one per
+//   group of 4 segments indexed directly by the word's byte. Series whose coarse bound does not
+//   exceed the threshold are staged in LDS (wave ballot, mbcnt rank, one LDS atomic per wave);
+//   fine: once kPass are staged (and at the end), the block loads their full 8-bit words, 4 per
+//   thread at once, and sums T8[s][sym_s] (LDS); survivors (fine bound <= threshold) are staged
+//   again and flushed to the global list with one global atomic per flush, when the staging could
+//   overflow and at the end.
+// Both bounds are float32 sums of 16 terms, each term at most the exact term of the series
+// (entries rounded toward zero; a coarse entry is the minimum over its region's fine entries), so
+// either bound is at most (1 + gamma_15) times the exact bound and pruning on either is covered
+// by the threshold's margin.
 // ------------------------------------------------------------------------------------------
-// Survivors are staged per block in LDS (one LDS atomic per wave) and flushed to the global
-// list with one global atomic per flush: a single global counter hit by every wave with a
-// survivor serialises the scan when survivors are many.
-__device__ __forceinline__ void flush_survivors(const QueryArgs& A, uint2* sbuf, uint32_t* scount,
-                                                uint32_t* sbase)
+__device__ __forceinline__ float coarse4(const uint32_t c, const float* __restrict__ tc)
 {
-    const uint32_t cnt = *scount;
-    if (threadIdx.x == 0) *sbase = cnt ? atomicAdd(&A.qs->n_surv, cnt) : 0u;
-    __syncthreads();
-    const uint32_t b = *sbase;
-    for (uint32_t k = threadIdx.x; k < cnt; k += blockDim.x)
-        if (b + k < A.surv_cap) A.surv[b + k] = sbuf[k];
-    __syncthreads();
-    if (threadIdx.x == 0) *scount = 0;
-    __syncthreads();
+    return (tc[0 * kGroupCodes + (c & 255u)] + tc[1 * kGroupCodes + ((c >> 8) & 255u)]) +
+           (tc[2 * kGroupCodes + ((c >> 16) & 255u)] + tc[3 * kGroupCodes + (c >> 24)]);
 }
 
 template <int U, int BS>
 __global__ __launch_bounds__(BS) void k_lbscan(QueryArgs A, float fixed_thr)
 {
-    __shared__ float t5[kSeg * kCoarse];
+    constexpr int kE = 4;                      // staged series per thread and fine step
+    constexpr int kPass = kE * BS;             // staged coarse passers handled per fine step
+    constexpr int kCap = kPass + 4 * BS * U;   // a step of the coarse pass adds at most 4 BS U
+    constexpr int kSurv = 2 * kPass;           // staged survivors (flushed beyond kSurv - kPass)
+    __shared__ float tc[kGroups * kGroupCodes];
     __shared__ float t8[kSeg * kSym];
-    __shared__ uint2 sbuf[2 * BS * U];
-    __shared__ uint32_t scount, sbase;
+    __shared__ uint32_t cbuf[kCap];
+    __shared__ uint2 sbuf[kSurv];
+    __shared__ uint32_t ccount, scount, sbase;
     __shared__ unsigned long long shead;
     const int tid = threadIdx.x, lane = tid & 63;
-    constexpr int bs = BS;
+    const uint4* __restrict__ cw = reinterpret_cast<const uint4*>(A.csax);
     const uint4* __restrict__ sax = reinterpret_cast<const uint4*>(A.sax);
     const long long N = A.N;
-    const long long stride = (long long)gridDim.x * bs;
-    long long base = (long long)blockIdx.x * bs;
-    if (tid == 0) { scount = 0; shead = ~0ull; }
+    const long long NG = (N + 3) / 4;          // groups of 4 series (one 16-byte load)
+    const long long stride = (long long)gridDim.x * BS;
+    long long base = (long long)blockIdx.x * BS;
+    if (tid == 0) { ccount = 0; scount = 0; shead = ~0ull; }
 
     uint4 nxt[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {  // first words are in flight while the tables load
-        const long long i = base + u * stride + tid;
-        nxt[u] = (i < N) ? sax[i] : make_uint4(0, 0, 0, 0);
+        const long long g = base + u * stride + tid;
+        nxt[u] = (g < NG) ? cw[g] : make_uint4(0, 0, 0, 0);
     }
-    for (int e = tid; e < kSeg * kCoarse; e += bs) t5[e] = A.t5[e];
     {
+        const float4* s4 = reinterpret_cast<const float4*>(A.tc);
+        float4* d4 = reinterpret_cast<float4*>(tc);
+        for (int e = tid; e < kGroups * kGroupCodes / 4; e += BS) d4[e] = s4[e];
         const float4* s8 = reinterpret_cast<const float4*>(A.t8);
         float4* d8 = reinterpret_cast<float4*>(t8);
-        for (int e = tid; e < kSeg * kSym / 4; e += bs) d8[e] = s8[e];
+        for (int e = tid; e < kSeg * kSym / 4; e += BS) d8[e] = s8[e];
     }
     float thr;
     if (fixed_thr >= 0.f) {
@@ -709,50 +706,110 @@ __global__ __launch_bounds__(BS) void k_lbscan(QueryArgs A, float fixed_thr)
     }
     __syncthreads();
 
-    for (; base < N; base += stride * U) {
+    // survivors staged in LDS to the global list (one global atomic per flush); whole block
+    auto flush = [&]() {
+        __syncthreads();
+        const uint32_t cnt = scount;
+        if (tid == 0) sbase = cnt ? atomicAdd(&A.qs->n_surv, cnt) : 0u;
+        __syncthreads();
+        const uint32_t b = sbase;
+        for (uint32_t k = tid; k < cnt; k += BS)
+            if (b + k < A.surv_cap) A.surv[b + k] = sbuf[k];
+        __syncthreads();
+        if (tid == 0) scount = 0;
+        __syncthreads();
+    };
+    // fine bound of the staged series [0, count), kE per thread at a time with all their words in
+    // flight; survivors are staged and flushed only when the staging could overflow
+    auto fine = [&](uint32_t count) {
+        for (uint32_t a = 0; a < count; a += kPass) {
+            uint32_t idx[kE];
+            uint4 w[kE];
+#pragma unroll
+            for (int k = 0; k < kE; ++k) {   // every load issued before any is used
+                const uint32_t e = a + (uint32_t)(tid + k * BS);
+                idx[k] = e < count ? cbuf[e] : 0xFFFFFFFFu;
+                w[k] = idx[k] != 0xFFFFFFFFu ? sax[idx[k]] : make_uint4(0u, 0u, 0u, 0u);
+            }
+            unsigned long long mhead = ~0ull;
+#pragma unroll
+            for (int k = 0; k < kE; ++k) {
+                const float lb8 = fine_lb(w[k], t8);
+                const bool pass = idx[k] != 0xFFFFFFFFu && lb8 <= thr;
+                const unsigned long long m = __ballot(pass);
+                if (m) {   // at most kPass appends per step, onto at most kSurv - kPass staged
+                    const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                    const int leader = __ffsll((long long)m) - 1;
+                    uint32_t bp = 0;
+                    if (lane == leader) bp = atomicAdd(&scount, (uint32_t)__popcll(m));
+                    bp = __shfl(bp, leader);
+                    if (pass) {
+                        sbuf[bp + rank] = make_uint2(idx[k], __float_as_uint(lb8));
+                        const unsigned long long hk = pack_key(lb8, idx[k]);
+                        mhead = hk < mhead ? hk : mhead;
+                    }
+                }
+            }
+            if (mhead != ~0ull) atomicMin(&shead, mhead);
+            __syncthreads();
+            if (scount > (uint32_t)(kSurv - kPass)) flush();   // uniform
+        }
+    };
+
+    for (; base < NG; base += stride * U) {
         uint4 cur[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) cur[u] = nxt[u];
         const long long nb = base + stride * U;
-        if (nb < N) {
+        if (nb < NG) {
 #pragma unroll
             for (int u = 0; u < U; ++u) {
-                const long long i = nb + u * stride + tid;
-                nxt[u] = (i < N) ? sax[i] : make_uint4(0, 0, 0, 0);
+                const long long g = nb + u * stride + tid;
+                nxt[u] = (g < NG) ? cw[g] : make_uint4(0, 0, 0, 0);
             }
         }
-        unsigned long long mhead = ~0ull;
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const long long i = base + u * stride + tid;
-            const float lb5 = coarse_lb(cur[u], t5);
-            bool pass = (i < N) && (lb5 <= thr);
-            float lb8 = 0.f;
-            if (pass) {
-                lb8 = fine_lb(cur[u], t8);
-                pass = lb8 <= thr;
-            }
-            const unsigned long long m = __ballot(pass);
-            if (m) {  // at most BS * U appends per outer step: the buffer holds two steps
-                const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                                __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                const int leader = __ffsll((long long)m) - 1;
-                uint32_t basepos = 0;
-                if (lane == leader) basepos = atomicAdd(&scount, (uint32_t)__popcll(m));
-                basepos = __shfl(basepos, leader);
-                if (pass) {
-                    sbuf[basepos + rank] = make_uint2((uint32_t)i, __float_as_uint(lb8));
-                    const unsigned long long hk = pack_key(lb8, (uint32_t)i);
-                    mhead = hk < mhead ? hk : mhead;
+            const long long i0 = 4 * (base + u * stride + tid);
+            // series of this load inside the collection (the padding of the last load is not)
+            const long long left = N - i0;
+            const int lim = left >= 4 ? 4 : (left > 0 ? (int)left : 0);
+            float c[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) c[k] = coarse4(word_at(cur[u], k), tc);   // 16 reads in flight
+            bool pass[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) pass[k] = (c[k] <= thr) & (k < lim);
+            if (__ballot(pass[0] | pass[1] | pass[2] | pass[3])) {
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const unsigned long long m = __ballot(pass[k]);
+                    if (m) {   // at most 4 BS U appends per step: the staging holds kCap
+                        const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                            (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+                        const int leader = __ffsll((long long)m) - 1;
+                        uint32_t bp = 0;
+                        if (lane == leader) bp = atomicAdd(&ccount, (uint32_t)__popcll(m));
+                        bp = __shfl(bp, leader);
+                        if (pass[k]) cbuf[bp + rank] = (uint32_t)(i0 + k);
+                    }
                 }
             }
         }
-        if (mhead != ~0ull) atomicMin(&shead, mhead);
         __syncthreads();
-        if (scount >= (uint32_t)(bs * U)) flush_survivors(A, sbuf, &scount, &sbase);
+        const uint32_t cc = ccount;
+        if (cc >= (uint32_t)kPass) {   // uniform
+            fine(cc);
+            if (tid == 0) ccount = 0;
+            __syncthreads();
+        }
     }
     __syncthreads();
-    if (scount) flush_survivors(A, sbuf, &scount, &sbase);
+    const uint32_t cc = ccount;
+    if (cc) fine(cc);
+    __syncthreads();
+    if (scount) flush();   // uniform
     if (tid == 0 && shead != ~0ull) atomicMin(&A.qs->head_key, shead);
 }
 
@@ -781,7 +838,8 @@ template <int U, int BS>
 static hipError_t launch_scan_t(const QueryArgs& a, float thr, int per_cu, int cus, hipStream_t st,
                                 hipEvent_t e0, hipEvent_t e1)
 {
-    const long long need = (a.N + (long long)BS * U - 1) / ((long long)BS * U);
+    const long long groups = (a.N + 3) / 4;
+    const long long need = (groups + (long long)BS * U - 1) / ((long long)BS * U);
     long long grid = (long long)cus * (per_cu > 0 ? per_cu : 4);
     if (grid > need) grid = need;
     if (grid < 1) grid = 1;
@@ -806,9 +864,9 @@ hipError_t launch_lbscan(const QueryArgs& a, float threshold_sq, ScanShape shape
             cus = 256;
     }
     const bool wide = shape.threads == 512;
-    if (shape.unroll == 8)
-        return wide ? launch_scan_t<8, 512>(a, threshold_sq, shape.per_cu, cus, st, e0, e1)
-                    : launch_scan_t<8, 256>(a, threshold_sq, shape.per_cu, cus, st, e0, e1);
+    if (shape.unroll == 1)
+        return wide ? launch_scan_t<1, 512>(a, threshold_sq, shape.per_cu, cus, st, e0, e1)
+                    : launch_scan_t<1, 256>(a, threshold_sq, shape.per_cu, cus, st, e0, e1);
     if (shape.unroll == 2)
         return wide ? launch_scan_t<2, 512>(a, threshold_sq, shape.per_cu, cus, st, e0, e1)
                     : launch_scan_t<2, 256>(a, threshold_sq, shape.per_cu, cus, st, e0, e1);
@@ -899,15 +957,17 @@ __device__ void resolve_block(const QueryArgs& A, const float* __restrict__ q, l
     }
     rd[tid] = bd;
     ri[tid] = bi;
-    __syncthreads();
-    for (int off = 128; off > 0; off >>= 1) {
-        if (tid < off) {
-            const double d2 = rd[tid + off];
-            const long long i2 = ri[tid + off];
-            if (d2 < rd[tid] || (d2 == rd[tid] && i2 < ri[tid])) { rd[tid] = d2; ri[tid] = i2; }
-        }
+    if (ncand > kResolveList) {   // uniform: every thread holds a partial minimum
         __syncthreads();
-    }
+        for (int off = 128; off > 0; off >>= 1) {
+            if (tid < off) {
+                const double d2 = rd[tid + off];
+                const long long i2 = ri[tid + off];
+                if (d2 < rd[tid] || (d2 == rd[tid] && i2 < ri[tid])) { rd[tid] = d2; ri[tid] = i2; }
+            }
+            __syncthreads();
+        }
+    }   // otherwise thread 0 alone scored the candidates
     if (tid == 0) {
         uint32_t err = qs->err;
         if (qs->n_surv > A.surv_cap) err |= kErrSurvOverflow;
