@@ -84,6 +84,8 @@ typedef struct paris_stats {
     int64_t seed_index;    /* series found by the approximate search (-1 if none)            */
     double  seed_dist;     /* its float32-computed distance (+inf if none)                   */
     int64_t seed_lo, seed_hi;  /* sorted-position window examined by the approximate search  */
+    int64_t coarse_passed;     /* series whose bound on the words at cardinality 4 passed the
+                                  scan's first pass (their 8-bit words were then read)        */
 } paris_stats;
 
 typedef struct paris_index paris_index;  /* opaque, library-owned host handle */

@@ -24,7 +24,7 @@ class ParisStats(ctypes.Structure):
                 ("abandoned", ctypes.c_int64), ("bsf_updates", ctypes.c_int64),
                 ("resolved", ctypes.c_int64), ("seed_index", ctypes.c_int64),
                 ("seed_dist", ctypes.c_double), ("seed_lo", ctypes.c_int64),
-                ("seed_hi", ctypes.c_int64)]
+                ("seed_hi", ctypes.c_int64), ("coarse_passed", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}

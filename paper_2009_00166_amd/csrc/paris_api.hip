@@ -568,6 +568,7 @@ void fill_stats(const QResult& r, paris_stats* o)
     }
     o->seed_lo = r.win_lo;
     o->seed_hi = r.win_hi;
+    o->coarse_passed = r.n_coarse;
 }
 
 // Launch-shape autotuner for the lower-bound scan: every candidate shape scans the whole SAX
@@ -1043,6 +1044,7 @@ paris_status batch_core(paris_index* h, const float* queries_dev, long long n_qu
             agg->abandoned += one.abandoned;
             agg->bsf_updates += one.bsf_updates;
             agg->resolved += one.resolved;
+            agg->coarse_passed += one.coarse_passed;
         }
     }
     return PARIS_OK;

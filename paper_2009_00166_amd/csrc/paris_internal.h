@@ -21,7 +21,7 @@ constexpr int kResolveList = 256;  // in-band candidates resolved block-cooperat
 constexpr int kRefineBlocks = 512; // default refine grid (16 lane groups of 16 lanes per block)
 constexpr int kRefineMinBlocks = 128;  // refine blocks taking part with few survivors
 constexpr int kRefinePerBlock = 512;   // survivors per taking-part refine block
-constexpr int kKeyEvery = 8;       // refine: rows between re-reads of the shared best-so-far
+constexpr int kRefineBatch = 4;    // refine: survivors a lane group takes at once
 constexpr int kRefineVec = 4;      // float4 per lane per refine chunk (a 1 KiB piece of a row per group)
 
 // Best-so-far key: float32 bits of the squared distance (non-negative, so the bit pattern
@@ -52,6 +52,7 @@ struct QResult {
     unsigned long long seed_key;
     long long win_lo, win_hi;
     uint32_t n_surv, n_refined, n_abandon, n_bsf_upd, n_resolved, err;
+    uint32_t n_coarse;        // series whose cardinality-4 bound passed the scan's first pass
 };
 
 // Per-query device state. The last kernel of every query snapshots the result and leaves the
@@ -69,7 +70,7 @@ struct alignas(256) QState {
     unsigned long long bsf_key;
     unsigned long long seed_key;
     unsigned long long head_key;   // (fine bound bits, index) of the survivor with the smallest bound
-    uint32_t n_surv, n_refined, n_abandon, n_bsf_upd, n_done;
+    uint32_t n_surv, n_refined, n_abandon, n_bsf_upd, n_done, n_coarse;
     uint32_t err;
     uint32_t blocks_done;
     uint32_t pad1;

@@ -72,7 +72,7 @@ __device__ __forceinline__ void reset_state(QState* qs)
     qs->bsf_key = kBsfInit;
     qs->seed_key = kBsfInit;
     qs->head_key = ~0ull;
-    qs->n_surv = qs->n_refined = qs->n_abandon = qs->n_bsf_upd = qs->n_done = 0;
+    qs->n_surv = qs->n_refined = qs->n_abandon = qs->n_bsf_upd = qs->n_done = qs->n_coarse = 0;
     qs->err = 0;
     qs->blocks_done = 0;
 }
@@ -671,7 +671,7 @@ __global__ __launch_bounds__(BS) void k_lbscan(QueryArgs A, float fixed_thr)
     __shared__ float t8[kSeg * kSym];
     __shared__ uint32_t cbuf[kCap];
     __shared__ uint2 sbuf[kSurv];
-    __shared__ uint32_t ccount, scount, sbase;
+    __shared__ uint32_t ccount, scount, sbase, ctotal;
     __shared__ unsigned long long shead;
     const int tid = threadIdx.x, lane = tid & 63;
     const uint4* __restrict__ cw = reinterpret_cast<const uint4*>(A.csax);
@@ -680,7 +680,7 @@ __global__ __launch_bounds__(BS) void k_lbscan(QueryArgs A, float fixed_thr)
     const long long NG = (N + 3) / 4;          // groups of 4 series (one 16-byte load)
     const long long stride = (long long)gridDim.x * BS;
     long long base = (long long)blockIdx.x * BS;
-    if (tid == 0) { ccount = 0; scount = 0; shead = ~0ull; }
+    if (tid == 0) { ccount = 0; scount = 0; ctotal = 0; shead = ~0ull; }
 
     uint4 nxt[U];
 #pragma unroll
@@ -800,6 +800,7 @@ __global__ __launch_bounds__(BS) void k_lbscan(QueryArgs A, float fixed_thr)
         __syncthreads();
         const uint32_t cc = ccount;
         if (cc >= (uint32_t)kPass) {   // uniform
+            if (tid == 0) ctotal += cc;
             fine(cc);
             if (tid == 0) ccount = 0;
             __syncthreads();
@@ -811,6 +812,7 @@ __global__ __launch_bounds__(BS) void k_lbscan(QueryArgs A, float fixed_thr)
     __syncthreads();
     if (scount) flush();   // uniform
     if (tid == 0 && shead != ~0ull) atomicMin(&A.qs->head_key, shead);
+    if (tid == 0 && ctotal + cc) atomicAdd(&A.qs->n_coarse, ctotal + cc);
 }
 
 // Streams `bytes` of a buffer through the caches (a read-only sweep). The launch-shape tuner
@@ -980,6 +982,7 @@ __device__ void resolve_block(const QueryArgs& A, const float* __restrict__ q, l
         r.win_lo = qs->win_lo;
         r.win_hi = qs->win_hi;
         r.n_surv = qs->n_surv;
+        r.n_coarse = qs->n_coarse;
         r.n_refined = qs->n_refined;
         r.n_abandon = qs->n_abandon;
         r.n_bsf_upd = qs->n_bsf_upd;
@@ -1074,6 +1077,7 @@ __device__ void resolve_knn_block(const QueryArgs& A, const float* __restrict__ 
         r.win_lo = qs->win_lo;
         r.win_hi = qs->win_hi;
         r.n_surv = qs->n_surv;
+        r.n_coarse = qs->n_coarse;
         r.n_refined = qs->n_refined;
         r.n_abandon = qs->n_abandon;
         r.n_bsf_upd = qs->n_bsf_upd;
@@ -1152,110 +1156,133 @@ __global__ __launch_bounds__(256) void k_refine_resolve(QueryArgs A, const float
             }
         }
     }
-    // A row is read in chunks of 4 steps of 64 points (1 KiB), every lane's share of a chunk
-    // (4 F float4) loaded at once and the next chunk's loads issued before the current one is
-    // summed; the partial sum is compared with the threshold after every step (early abandoning).
-    // The next survivor's entry is fetched one iteration ahead. A survivor is first tested
-    // against the group's last threshold (the best-so-far only decreases, so a stale threshold
-    // prunes less, never wrongly); the shared best-so-far is re-read with every kKeyEvery-th
-    // row's first chunk (one address read by every group: reading it per row makes a hot spot)
-    // and once per chunk of longer rows.
-    // With bsf_private set (the non-sharing design of the paper's nb-ParIS+, Section 3.3; the
-    // default, since the re-reads of one hot address cost more than the few extra rows refined
-    // without them), a group never re-reads the shared best-so-far: it prunes against the
-    // seed's best-so-far and the smallest distance it has completed itself. The atomicMin below
-    // still runs, as the final minimum over the groups' copies; pruning with a larger threshold
-    // is never wrong.
     const bool priv = !KNN && A.bsf_private != 0;
     constexpr int CV = 4 * F;            // float4 per lane per chunk
     unsigned long long key0 = 0;
     if (l == 0) key0 = load_key(priv ? &A.qs->seed_key : &A.qs->bsf_key);
     key0 = __shfl(key0, lead);
     float thr = prune_threshold(fminf(key_dist(key0), local_best), A.mg.prune_rel);
-    uint2 e_next = grp < count ? A.surv[grp] : make_uint2(0u, 0u);
-    for (uint32_t c = grp; c < count; c += ngrp) {
-        const uint2 e = e_next;
-        if (c + ngrp < count) e_next = A.surv[c + ngrp];
-        const float lb = __uint_as_float(e.y);
-        if (lb > thr) continue;  // uniform in the group
-        const float4* r4 = reinterpret_cast<const float4*>(A.X + (long long)e.x * A.n);
-        const bool fresh = !priv && (refined % kKeyEvery) == 0;
-        unsigned long long key = key0;
-        if (fresh && l == 0) key = load_key(&A.qs->bsf_key);
-        float4 xa[CV];
+    // The points of a row after its first 64: the rest of its first 256 points (3 steps) loaded
+    // together, then 256 at a time, the partial sum compared with the threshold after every step
+    // of 64 points (the same steps, in the same order, as the first one). True: abandoned.
+    auto rest_of_row = [&](uint32_t row, float& acc) -> bool {
+        const float4* r4 = reinterpret_cast<const float4*>(A.X + (long long)row * A.n);
+        for (int s0 = 1; s0 * 16 < nv;) {
+            const int ns = s0 == 1 ? 3 : 4;
+            float4 xr[CV];
 #pragma unroll
-        for (int k = 0; k < CV; ++k) {
-            const int v = (k / F) * 16 + (k % F) * G + l;
-            xa[k] = v < nv ? r4[v] : make_float4(0.f, 0.f, 0.f, 0.f);
-        }
-        if (fresh) {
-            key = __shfl(key, lead);
-            thr = prune_threshold(fminf(key_dist(key), local_best), A.mg.prune_rel);
-            if (lb > thr) continue;  // re-check against the current best
-        }
-        ++refined;
-        float acc = 0.f;
-        bool ab = false;
-        for (int v0 = 0; v0 < nv; v0 += 64) {
-            const int v1 = v0 + 64;
-            const bool more = v1 < nv;
-            float4 xn[CV];
-            if (more) {
-                if (l == 0 && !priv) key = load_key(&A.qs->bsf_key);
-#pragma unroll
-                for (int k = 0; k < CV; ++k) {
-                    const int v = v1 + (k / F) * 16 + (k % F) * G + l;
-                    xn[k] = v < nv ? r4[v] : make_float4(0.f, 0.f, 0.f, 0.f);
-                }
+            for (int k = 0; k < CV; ++k) {
+                const int st = k / F;
+                const int v = (s0 + st) * 16 + (k % F) * G + l;
+                xr[k] = (st < ns && v < nv) ? r4[v] : make_float4(0.f, 0.f, 0.f, 0.f);
+            }
+            if (s0 > 1 && !priv) {   // longer rows: the shared best-so-far once per 256 points
+                unsigned long long key = 0ull;
+                if (l == 0) key = load_key(&A.qs->bsf_key);
+                key = __shfl(key, lead);
+                thr = prune_threshold(fminf(key_dist(key), local_best), A.mg.prune_rel);
             }
 #pragma unroll
             for (int st = 0; st < 4; ++st) {
-                if (v0 + st * 16 < nv) {
+                if (st < ns && (s0 + st) * 16 < nv) {
                     float part = 0.f;
 #pragma unroll
                     for (int f = 0; f < F; ++f) {
-                        const int v = v0 + st * 16 + f * G + l;
-                        part += v < nv ? sqdiff4(xa[st * F + f], q4[v]) : 0.f;
+                        const int v = (s0 + st) * 16 + f * G + l;
+                        part += v < nv ? sqdiff4(xr[st * F + f], q4[v]) : 0.f;
                     }
                     acc += group_sum<G>(part);
-                    if (acc > thr) { ab = true; break; }
+                    if (acc > thr) return true;
                 }
             }
-            if (ab || !more) break;
+            s0 += ns;
+        }
+        return false;
+    };
+    // A group takes kRefineBatch survivors at once: their entries, then the first 64 points of
+    // every one its bound does not prune, all loads of a stage in flight together (most rows are
+    // abandoned within those 64 points, so their other 768 bytes are never read). With sharing, the
+    // shared best-so-far is re-read once per batch (one address read by every group: per row
+    // it would be a hot spot).
+    // With bsf_private set (the non-sharing design of the paper's nb-ParIS+, Section 3.3; the
+    // default, since the re-reads of one hot address cost more than the few extra rows refined
+    // without them), a group never re-reads the shared best-so-far: it prunes against the
+    // seed's best-so-far and the smallest distance it has completed itself. The atomicMin below
+    // still runs, as the final minimum over the groups' copies; pruning with a larger threshold
+    // is never wrong.
+    for (uint32_t cb = grp; cb < count; cb += (uint32_t)kRefineBatch * ngrp) {
+        uint2 eb[kRefineBatch];
 #pragma unroll
-            for (int k = 0; k < CV; ++k) xa[k] = xn[k];
+        for (int d = 0; d < kRefineBatch; ++d) {
+            const uint32_t c = cb + (uint32_t)d * ngrp;
+            // past the list: index 0xFFFFFFFF (never a series: n_series <= 2^32 - 2), never taken
+            eb[d] = c < count ? A.surv[c] : make_uint2(0xFFFFFFFFu, 0u);
+        }
+        if (!priv) {
+            unsigned long long key = 0ull;
+            if (l == 0) key = load_key(&A.qs->bsf_key);
             key = __shfl(key, lead);
             thr = prune_threshold(fminf(key_dist(key), local_best), A.mg.prune_rel);
         }
-        if (ab) { ++abandoned; continue; }
-        if (priv) {   // acc is the group's sum, the same in every lane of the group
-            local_best = fminf(local_best, acc);
-            thr = prune_threshold(fminf(key_dist(key0), local_best), A.mg.prune_rel);
-        }
-        if (KNN) {
-            // recorded when within the band of the current k-th best (a superset of the final
-            // band), then offered to the k best slots by the whole group
-            const unsigned long long mine = pack_key(acc, e.x);
-            unsigned long long now = 0ull;
-            if (l == 0) now = load_key(&A.qs->bsf_key);
-            now = __shfl(now, lead);
-            if (l == 0 && (double)acc <= (double)key_dist(now) * (1.0 + A.mg.band_rel) + 1e-25) {
-                const uint32_t pos = atomicAdd(&A.qs->n_done, 1u);
-                if (pos < A.done_cap) A.done[pos] = make_uint2(e.x, __float_as_uint(acc));
-                wrote = true;
+        float4 x0[kRefineBatch][F];
+#pragma unroll
+        for (int d = 0; d < kRefineBatch; ++d) {
+            const bool live = eb[d].x != 0xFFFFFFFFu && __uint_as_float(eb[d].y) <= thr;
+            const float4* r4 = reinterpret_cast<const float4*>(A.X + (long long)(live ? eb[d].x : 0u) * A.n);
+#pragma unroll
+            for (int f = 0; f < F; ++f) {
+                const int v = f * G + l;
+                x0[d][f] = (live && v < nv) ? r4[v] : make_float4(0.f, 0.f, 0.f, 0.f);
             }
-            if (mine < now && knn_insert_group<G>(A.knn_slots, A.knn_k, mine, &A.qs->bsf_key, l, lead) &&
-                l == 0)
-                atomicAdd(&A.qs->n_bsf_upd, 1u);
-        } else if (l == 0) {
-            const unsigned long long mine = pack_key(acc, e.x);
-            const unsigned long long old = atomicMin(&A.qs->bsf_key, mine);
-            if (mine < old) atomicAdd(&A.qs->n_bsf_upd, 1u);
-            const unsigned long long now = mine < old ? mine : old;
-            if ((double)acc <= (double)key_dist(now) * (1.0 + A.mg.band_rel) + 1e-25) {
-                const uint32_t pos = atomicAdd(&A.qs->n_done, 1u);
-                if (pos < A.done_cap) A.done[pos] = make_uint2(e.x, __float_as_uint(acc));
-                wrote = true;
+        }
+#pragma unroll
+        for (int d = 0; d < kRefineBatch; ++d) {
+            const uint2 e = eb[d];
+            // uniform in the group; the threshold only drops, so a row not loaded above is skipped
+            if (e.x == 0xFFFFFFFFu || __uint_as_float(e.y) > thr) continue;
+            ++refined;
+            float acc;
+            {
+                float part = 0.f;
+    #pragma unroll
+                for (int f = 0; f < F; ++f) {
+                    const int v = f * G + l;
+                    part += v < nv ? sqdiff4(x0[d][f], q4[v]) : 0.f;
+                }
+                acc = group_sum<G>(part);
+            }
+            bool ab = acc > thr;
+            if (!ab && nv > 16) ab = rest_of_row(e.x, acc);
+            if (ab) { ++abandoned; continue; }
+            if (priv) {   // acc is the group's sum, the same in every lane of the group
+                local_best = fminf(local_best, acc);
+                thr = prune_threshold(fminf(key_dist(key0), local_best), A.mg.prune_rel);
+            }
+            if (KNN) {
+                // recorded when within the band of the current k-th best (a superset of the final
+                // band), then offered to the k best slots by the whole group
+                const unsigned long long mine = pack_key(acc, e.x);
+                unsigned long long now = 0ull;
+                if (l == 0) now = load_key(&A.qs->bsf_key);
+                now = __shfl(now, lead);
+                if (l == 0 && (double)acc <= (double)key_dist(now) * (1.0 + A.mg.band_rel) + 1e-25) {
+                    const uint32_t pos = atomicAdd(&A.qs->n_done, 1u);
+                    if (pos < A.done_cap) A.done[pos] = make_uint2(e.x, __float_as_uint(acc));
+                    wrote = true;
+                }
+                if (mine < now && knn_insert_group<G>(A.knn_slots, A.knn_k, mine, &A.qs->bsf_key, l, lead) &&
+                    l == 0)
+                    atomicAdd(&A.qs->n_bsf_upd, 1u);
+            } else if (l == 0) {
+                const unsigned long long mine = pack_key(acc, e.x);
+                const unsigned long long old = atomicMin(&A.qs->bsf_key, mine);
+                if (mine < old) atomicAdd(&A.qs->n_bsf_upd, 1u);
+                const unsigned long long now = mine < old ? mine : old;
+                if ((double)acc <= (double)key_dist(now) * (1.0 + A.mg.band_rel) + 1e-25) {
+                    const uint32_t pos = atomicAdd(&A.qs->n_done, 1u);
+                    if (pos < A.done_cap) A.done[pos] = make_uint2(e.x, __float_as_uint(acc));
+                    wrote = true;
+                }
             }
         }
     }
