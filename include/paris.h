@@ -112,6 +112,10 @@ typedef struct paris_layout {
     const void *tree_nodes_dev;
     int64_t n_tree_nodes;
     int64_t tree_max_leaf;      /* series in the largest leaf                                   */
+    /* distance screen launch shape picked at paris_batch_attach (all 0 without a batch
+       workspace): query-tile rows, persistent blocks per CU, series subtiles per wave, MFMA
+       form (16: 16x16x32, 32: 32x32x16)                                                      */
+    int32_t screen_rows, screen_blocks_per_cu, screen_subtiles, screen_mfma;
 } paris_layout;
 
 /* Query summaries as computed on the device (inspection and tests). */
@@ -126,6 +130,16 @@ typedef struct paris_query_info {
 
 /* Fills *cfg with the defaults (16 segments, 8 bits, ROOT16, 4096 leaves, seed_cap 16384). */
 paris_status paris_default_config(paris_config *cfg);
+
+/*
+ * Tuned launch shapes. paris_build times the scan's candidate shapes and then refines the
+ * choice on the first 48 queries; paris_batch_attach times the screen's. When the environment
+ * variable PARIS_TUNE_CACHE names a file, both decisions are appended to it (one text line
+ * each, keyed by kind, device architecture, series length, floor(log2 n_series) and, for the
+ * scan, collection in host memory, for the screen, 2 * max_batch + block bound on), and a
+ * later build or attach with a matching line takes that shape without timing anything.
+ * PARIS_SCAN_SHAPE / PARIS_SCREEN_SHAPE, when set, override the cache.
+ */
 
 /* Bytes of device workspace paris_build needs for this collection shape (host-only call). */
 paris_status paris_workspace_size(int64_t n_series, int32_t length, const paris_config *cfg,
@@ -409,8 +423,9 @@ paris_status paris_free(paris_index *idx);
  * float32 master copy, hidden activations and back-propagated gradients likewise; the
  * 16 features stay float32) with float32 accumulation; biases are float32. Loss: mean softmax
  * cross-entropy. Optimiser: Adam (Kingma and Ba 2015, Algorithm 1) on the master copy.
- * A network handle holds its own device memory (parameters, Adam moments, and activations for
- * max_rows rows). One call at a time per network and per index using it.
+ * A network keeps its parameters, Adam moments and the activations of max_rows rows in a
+ * caller-owned device workspace of paris_mlp_workspace_size() bytes; the library allocates no
+ * device memory for it. One call at a time per network and per index using it.
  */
 typedef struct paris_mlp paris_mlp;  /* opaque, library-owned host handle */
 
@@ -425,10 +440,17 @@ typedef struct paris_adam {
    64 .. 65536). */
 paris_status paris_mlp_param_count(int32_t n_leaves, int64_t *count);
 
-/* Create a network with all-zero parameters. max_rows (multiple of 64, 64 .. 65536) bounds
-   the rows of one training step; inference on more rows runs in pieces of max_rows.
-   Synchronous. Release with paris_mlp_free. */
-paris_status paris_mlp_create(int32_t n_leaves, int32_t max_rows, paris_mlp **out);
+/* bytes (host out): the device workspace a network of n_leaves leaves and max_rows rows needs. */
+paris_status paris_mlp_workspace_size(int32_t n_leaves, int32_t max_rows, int64_t *bytes);
+
+/* Create a network with all-zero parameters in workspace_dev (device, caller-owned, 256-byte
+   aligned, at least paris_mlp_workspace_size() bytes; it must outlive the network and is
+   zeroed here). max_rows (multiple of 64, 64 .. 65536) bounds the rows of one training step;
+   inference on more rows runs in pieces of max_rows. Synchronous. PARIS_EINVAL for a bad
+   shape, a NULL, misaligned or short workspace. Release with paris_mlp_free, which leaves the
+   workspace to its owner. */
+paris_status paris_mlp_create(int32_t n_leaves, int32_t max_rows, void *workspace_dev, int64_t workspace_bytes,
+                              paris_mlp **out);
 
 /* Copy parameters in (params_dev float32 [count], device) and reset Adam's moments and step
    count; or copy them out. Asynchronous on hip_stream. */

@@ -38,7 +38,9 @@ class ParisLayout(ctypes.Structure):
                 ("seed_cap", ctypes.c_int32), ("scan_threads", ctypes.c_int32),
                 ("scan_blocks_per_cu", ctypes.c_int32), ("scan_unroll", ctypes.c_int32),
                 ("tree_nodes_dev", ctypes.c_void_p), ("n_tree_nodes", ctypes.c_int64),
-                ("tree_max_leaf", ctypes.c_int64)]
+                ("tree_max_leaf", ctypes.c_int64), ("screen_rows", ctypes.c_int32),
+                ("screen_blocks_per_cu", ctypes.c_int32), ("screen_subtiles", ctypes.c_int32),
+                ("screen_mfma", ctypes.c_int32)]
 
 
 class ParisQueryInfo(ctypes.Structure):
@@ -82,7 +84,8 @@ SIGNATURES = [
     ("paris_get_batch_timing", ctypes.c_int, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int64)]),
     ("paris_free", ctypes.c_int, [_P]),
     ("paris_mlp_param_count", ctypes.c_int, [_I32, ctypes.POINTER(ctypes.c_int64)]),
-    ("paris_mlp_create", ctypes.c_int, [_I32, _I32, ctypes.POINTER(_P)]),
+    ("paris_mlp_workspace_size", ctypes.c_int, [_I32, _I32, ctypes.POINTER(ctypes.c_int64)]),
+    ("paris_mlp_create", ctypes.c_int, [_I32, _I32, _P, _I64, ctypes.POINTER(_P)]),
     ("paris_mlp_set_params", ctypes.c_int, [_P, _P, _P]),
     ("paris_mlp_get_params", ctypes.c_int, [_P, _P, _P]),
     ("paris_query_features", ctypes.c_int, [_P, _I64, _I32, _P, _P]),

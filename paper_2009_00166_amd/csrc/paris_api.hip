@@ -468,6 +468,110 @@ struct QueryScratch {
     uint32_t done_cap;
 };
 
+// ---- tuned launch shapes, kept across processes ------------------------------------------
+// PARIS_TUNE_CACHE names a text file with one tuned shape per line,
+//   <kind> <arch> <a> <b> <c> : <v0> <v1> <v2> <v3>
+// kind "scan": a = series length, b = floor(log2 N), c = 1 for a collection in host memory;
+//              values threads, blocks per CU, unroll, 0 (the online phase's decision);
+// kind "screen": a = screened dimensions, b = floor(log2 N), c = 2 * max_batch + block bound;
+//              values query-tile rows, blocks per CU, subtiles, MFMA form.
+// The last line with a matching key wins; other lines are ignored. Decisions are appended.
+std::mutex g_tune_mu;
+
+const char* tune_cache_path()
+{
+    const char* p = std::getenv("PARIS_TUNE_CACHE");
+    return p && p[0] ? p : nullptr;
+}
+
+// the device's architecture name up to its first feature flag (e.g. "gfx950")
+void arch_name(char* out, size_t cap)
+{
+    std::snprintf(out, cap, "unknown");
+    int dev = 0;
+    hipDeviceProp_t p;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&p, dev) != hipSuccess) return;
+    size_t i = 0;
+    for (; i + 1 < cap && p.gcnArchName[i] && p.gcnArchName[i] != ':' && p.gcnArchName[i] != ' '; ++i)
+        out[i] = p.gcnArchName[i];
+    out[i] = 0;
+    if (i == 0) std::snprintf(out, cap, "unknown");
+}
+
+int floor_log2(long long v)
+{
+    int b = 0;
+    while (v > 1) { v >>= 1; ++b; }
+    return b;
+}
+
+bool tune_cache_get(const char* kind, long long a, long long b, long long c, int v[4])
+{
+    const char* path = tune_cache_path();
+    if (!path) return false;
+    char arch[64];
+    arch_name(arch, sizeof arch);
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    FILE* f = std::fopen(path, "r");
+    if (!f) return false;
+    bool found = false;
+    char line[256];
+    while (std::fgets(line, sizeof line, f)) {
+        char k[32], ar[64];
+        long long la, lb, lc;
+        int w[4];
+        if (std::sscanf(line, "%31s %63s %lld %lld %lld : %d %d %d %d", k, ar, &la, &lb, &lc, &w[0], &w[1], &w[2],
+                        &w[3]) != 9)
+            continue;
+        if (std::strcmp(k, kind) || std::strcmp(ar, arch) || la != a || lb != b || lc != c) continue;
+        for (int i = 0; i < 4; ++i) v[i] = w[i];
+        found = true;
+    }
+    std::fclose(f);
+    return found;
+}
+
+void tune_cache_put(const char* kind, long long a, long long b, long long c, const int v[4])
+{
+    const char* path = tune_cache_path();
+    if (!path) return;
+    char arch[64];
+    arch_name(arch, sizeof arch);
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    FILE* f = std::fopen(path, "a");
+    if (!f) return;   // an unwritable cache only costs the next process a tuning run
+    std::fprintf(f, "%s %s %lld %lld %lld : %d %d %d %d\n", kind, arch, a, b, c, v[0], v[1], v[2], v[3]);
+    std::fclose(f);
+}
+
+bool collection_in_host(const paris_index* h)
+{
+    hipPointerAttribute_t pa;
+    const bool host = hipPointerGetAttributes(&pa, h->X) == hipSuccess && pa.type == hipMemoryTypeHost;
+    (void)hipGetLastError();
+    return host;
+}
+
+// a cached scan shape for this collection, if the cache holds a valid one
+bool scan_from_cache(paris_index* h)
+{
+    int v[4];
+    if (!tune_cache_get("scan", h->n, floor_log2(h->N), collection_in_host(h) ? 1 : 0, v)) return false;
+    for (int c = 0; c < kScanCands; ++c)
+        if (kScanCandidates[c].threads == v[0] && kScanCandidates[c].per_cu == v[1] &&
+            kScanCandidates[c].unroll == v[2]) {
+            h->scan = kScanCandidates[c];
+            return true;
+        }
+    return false;
+}
+
+void scan_to_cache(const paris_index* h)
+{
+    const int v[4] = {h->scan.threads, h->scan.per_cu, h->scan.unroll, 0};
+    tune_cache_put("scan", h->n, floor_log2(h->N), collection_in_host(h) ? 1 : 0, v);
+}
+
 paris_status run_query(paris_index* h, const float* q, hipStream_t st, long long* out_idx,
                        double* out_dist, long long qi, bool timed, QResult* host_res = nullptr,
                        const QueryScratch* scratch_in = nullptr)
@@ -514,6 +618,7 @@ paris_status run_query(paris_index* h, const float* q, hipStream_t st, long long
             if (med < best) { best = med; h->scan = kScanCandidates[c]; }
         }
         h->scan_decide = false;
+        scan_to_cache(h);
     }
     ScanShape shape = h->scan;
     hipEvent_t se0 = nullptr, se1 = nullptr;
@@ -597,9 +702,7 @@ paris_status tune_scan(paris_index* h, hipStream_t st)
     const size_t raw = (size_t)h->N * h->n * 4;
     const size_t sweep = raw < ((size_t)1 << 30) ? raw : ((size_t)1 << 30);
     // (a collection in host memory is read over PCIe and never evicts the device caches)
-    hipPointerAttribute_t pa;
-    const bool host_coll = hipPointerGetAttributes(&pa, h->X) == hipSuccess && pa.type == hipMemoryTypeHost;
-    (void)hipGetLastError();
+    const bool host_coll = collection_in_host(h);
     const bool cold = !host_coll && (size_t)h->N * 16 > ((size_t)32 << 20) && sweep >= ((size_t)512 << 20);
     uint32_t* sink = reinterpret_cast<uint32_t*>(h->ws + h->plan.hdr) + 16;
     hipEvent_t e0, e1;
@@ -965,6 +1068,18 @@ paris_status tune_screen(paris_index* h, hipStream_t st)
         }
     }
     const int m = h->max_batch;
+    const long long variant = 2LL * m + (h->block_lb ? 1 : 0);
+    {
+        int v[4];
+        if (tune_cache_get("screen", h->np, floor_log2(h->N), variant, v)) {
+            const bool ok16 = v[3] == 16 && (v[0] == 32 || v[0] == 64) && (v[2] == 2 || v[2] == 4) && !h->block_lb;
+            const bool ok32 = v[3] == 32 && (v[0] == 32 || v[0] == 64) && (v[2] == 1 || v[2] == 2);
+            if ((ok16 || ok32) && v[1] >= 1 && v[1] <= 8) {
+                h->screen = ScreenShape{v[0], cus * v[1], v[2], v[3]};
+                return PARIS_OK;
+            }
+        }
+    }
     HIP_TRY(hipMemsetAsync(h->bws + h->bp.qb, 0, (size_t)m * h->np * 2, st));
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
@@ -993,6 +1108,8 @@ paris_status tune_screen(paris_index* h, hipStream_t st)
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     h->screen = pick;
+    const int v[4] = {pick.qt, pick.grid / cus, pick.subs, pick.mfma};
+    tune_cache_put("screen", h->np, floor_log2(h->N), variant, v);
     return PARIS_OK;
 }
 
@@ -1309,8 +1426,9 @@ paris_status paris_build(const float* series_dev, int64_t n_series, int32_t leng
     const QueryArgs a = args_for(h);
     paris_status ts = PARIS_OK;
     if (launch_reset(a, st) != hipSuccess) ts = PARIS_EHIP;
-    if (ts == PARIS_OK) ts = tune_scan(h, st);
-    if (ts == PARIS_OK && std::getenv("PARIS_SCAN_SHAPE") == nullptr) {
+    const bool cached = std::getenv("PARIS_SCAN_SHAPE") == nullptr && scan_from_cache(h);
+    if (ts == PARIS_OK && !cached) ts = tune_scan(h, st);
+    if (ts == PARIS_OK && !cached && std::getenv("PARIS_SCAN_SHAPE") == nullptr) {
         // the build's choice (on a threshold of 0) is refined on the first real queries
         bool ok = true;
         for (int k = 0; k < kScanCands * kTunePer && ok; ++k)
@@ -1358,6 +1476,7 @@ paris_status paris_get_layout(const paris_index* h, paris_layout* o)
 {
     if (!handle_ok(h)) return PARIS_ESTATE;
     if (!o) return PARIS_EINVAL;
+    *o = paris_layout{};
     o->sax_dev = h->ws + h->plan.sax;
     o->keys_dev = reinterpret_cast<const uint64_t*>(h->ws + h->plan.keys);
     o->perm_dev = reinterpret_cast<const uint32_t*>(h->ws + h->plan.perm);
@@ -1370,6 +1489,16 @@ paris_status paris_get_layout(const paris_index* h, paris_layout* o)
     o->scan_threads = h->scan.threads;
     o->scan_blocks_per_cu = h->scan.per_cu;
     o->scan_unroll = h->scan.unroll;
+    if (h->screen_ok) {
+        int cus = 256, dev = 0;
+        if (hipGetDevice(&dev) != hipSuccess ||
+            hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+            cus = 256;
+        o->screen_rows = h->screen.qt;
+        o->screen_blocks_per_cu = h->screen.grid / cus;
+        o->screen_subtiles = h->screen.subs;
+        o->screen_mfma = h->screen.mfma;
+    }
     const bool tree = h->cfg.leaf_mode == PARIS_LEAF_ADS;
     o->tree_nodes_dev = tree ? static_cast<const void*>(h->ws + h->plan.tree) : nullptr;
     o->n_tree_nodes = tree ? h->n_tree_nodes : 0;
@@ -1761,11 +1890,66 @@ paris_status paris_mlp_param_count(int32_t n_leaves, int64_t* count)
     return PARIS_OK;
 }
 
-paris_status paris_mlp_create(int32_t n_leaves, int32_t max_rows, paris_mlp** out)
+}  // extern "C"
+
+namespace {
+
+// byte offsets of a network's arrays in its workspace (each 256-byte aligned); returns the total
+struct MlpArrays {
+    size_t master, wb, grad, m, v, P, H1, H2, Z, G3, G3b, G2, G2b, G1, G1b, lr, zq, total;
+};
+
+bool mlp_shape_ok(int32_t n_leaves, int32_t max_rows)
 {
-    if (!out || n_leaves < 64 || n_leaves > kMaxLeaves || n_leaves % 64 != 0 || max_rows < 64 ||
-        max_rows > 65536 || max_rows % 64 != 0)
-        return PARIS_EINVAL;
+    return n_leaves >= 64 && n_leaves <= kMaxLeaves && n_leaves % 64 == 0 && max_rows >= 64 && max_rows <= 65536 &&
+           max_rows % 64 == 0;
+}
+
+MlpArrays mlp_arrays(int32_t n_leaves, int32_t max_rows)
+{
+    const size_t np = (size_t)mlp_offsets(n_leaves).total, R = (size_t)max_rows, no = (size_t)n_leaves, H = kMlpHid;
+    MlpArrays a{};
+    size_t off = 0;
+    auto take = [&off](size_t bytes) { const size_t at = off; off = align_up(off + bytes); return at; };
+    a.master = take(np * 4);
+    a.wb = take(np * 2);
+    a.grad = take(np * 4);
+    a.m = take(np * 4);
+    a.v = take(np * 4);
+    a.P = take(R * kMlpIn * 4);
+    a.H1 = take(R * H * 2);
+    a.H2 = take(R * H * 2);
+    a.Z = take(R * no * 4);
+    a.G3 = take(R * no * 4);
+    a.G3b = take(R * no * 2);
+    a.G2 = take(R * H * 4);
+    a.G2b = take(R * H * 2);
+    a.G1 = take(R * H * 4);
+    a.G1b = take(R * H * 2);
+    a.lr = take(R * 4);
+    a.zq = take((no / 256 + 1) * kTopLeaves * 8);
+    a.total = off;
+    return a;
+}
+
+}  // namespace
+
+extern "C" {
+
+paris_status paris_mlp_workspace_size(int32_t n_leaves, int32_t max_rows, int64_t* bytes)
+{
+    if (!bytes || !mlp_shape_ok(n_leaves, max_rows)) return PARIS_EINVAL;
+    *bytes = (int64_t)mlp_arrays(n_leaves, max_rows).total;
+    return PARIS_OK;
+}
+
+paris_status paris_mlp_create(int32_t n_leaves, int32_t max_rows, void* workspace_dev, int64_t workspace_bytes,
+                              paris_mlp** out)
+{
+    if (!out || !mlp_shape_ok(n_leaves, max_rows) || !workspace_dev) return PARIS_EINVAL;
+    if (reinterpret_cast<uintptr_t>(workspace_dev) % kAlign != 0) return PARIS_EINVAL;
+    const MlpArrays a = mlp_arrays(n_leaves, max_rows);
+    if (workspace_bytes < (int64_t)a.total) return PARIS_EINVAL;
     paris_status ds = device_ok();
     if (ds != PARIS_OK) return ds;
     paris_mlp* m = new (std::nothrow) paris_mlp();
@@ -1776,39 +1960,27 @@ paris_status paris_mlp_create(int32_t n_leaves, int32_t max_rows, paris_mlp** ou
     m->max_rows = max_rows;
     m->off = mlp_offsets(n_leaves);
     m->step = 0;
-    const size_t np = (size_t)m->off.total, R = (size_t)max_rows, no = (size_t)n_leaves, H = kMlpHid;
-    size_t off = 0;
-    auto take = [&off](size_t bytes) { const size_t at = off; off = align_up(off + bytes); return at; };
-    const size_t o_master = take(np * 4), o_wb = take(np * 2), o_grad = take(np * 4), o_m = take(np * 4),
-                 o_v = take(np * 4), o_P = take(R * kMlpIn * 4), o_H1 = take(R * H * 2), o_H2 = take(R * H * 2),
-                 o_Z = take(R * no * 4), o_G3 = take(R * no * 4), o_G3b = take(R * no * 2), o_G2 = take(R * H * 4),
-                 o_G2b = take(R * H * 2), o_G1 = take(R * H * 4), o_G1b = take(R * H * 2), o_lr = take(R * 4),
-                 o_zq = take((no / 256 + 1) * kTopLeaves * 8);
-    if (hipMalloc(reinterpret_cast<void**>(&m->mem), off) != hipSuccess) {
-        delete m;
-        return PARIS_ENOMEM;
-    }
+    m->mem = static_cast<uint8_t*>(workspace_dev);
     uint8_t* b = m->mem;
-    m->master = reinterpret_cast<float*>(b + o_master);
-    m->wb = reinterpret_cast<uint16_t*>(b + o_wb);
-    m->grad = reinterpret_cast<float*>(b + o_grad);
-    m->am = reinterpret_cast<float*>(b + o_m);
-    m->av = reinterpret_cast<float*>(b + o_v);
-    m->P = reinterpret_cast<float*>(b + o_P);
-    m->H1 = reinterpret_cast<uint16_t*>(b + o_H1);
-    m->H2 = reinterpret_cast<uint16_t*>(b + o_H2);
-    m->Z = reinterpret_cast<float*>(b + o_Z);
-    m->G3 = reinterpret_cast<float*>(b + o_G3);
-    m->G3b = reinterpret_cast<uint16_t*>(b + o_G3b);
-    m->G2 = reinterpret_cast<float*>(b + o_G2);
-    m->G2b = reinterpret_cast<uint16_t*>(b + o_G2b);
-    m->G1 = reinterpret_cast<float*>(b + o_G1);
-    m->G1b = reinterpret_cast<uint16_t*>(b + o_G1b);
-    m->loss_row = reinterpret_cast<float*>(b + o_lr);
-    m->partq = reinterpret_cast<unsigned long long*>(b + o_zq);
+    m->master = reinterpret_cast<float*>(b + a.master);
+    m->wb = reinterpret_cast<uint16_t*>(b + a.wb);
+    m->grad = reinterpret_cast<float*>(b + a.grad);
+    m->am = reinterpret_cast<float*>(b + a.m);
+    m->av = reinterpret_cast<float*>(b + a.v);
+    m->P = reinterpret_cast<float*>(b + a.P);
+    m->H1 = reinterpret_cast<uint16_t*>(b + a.H1);
+    m->H2 = reinterpret_cast<uint16_t*>(b + a.H2);
+    m->Z = reinterpret_cast<float*>(b + a.Z);
+    m->G3 = reinterpret_cast<float*>(b + a.G3);
+    m->G3b = reinterpret_cast<uint16_t*>(b + a.G3b);
+    m->G2 = reinterpret_cast<float*>(b + a.G2);
+    m->G2b = reinterpret_cast<uint16_t*>(b + a.G2b);
+    m->G1 = reinterpret_cast<float*>(b + a.G1);
+    m->G1b = reinterpret_cast<uint16_t*>(b + a.G1b);
+    m->loss_row = reinterpret_cast<float*>(b + a.lr);
+    m->partq = reinterpret_cast<unsigned long long*>(b + a.zq);
     // all-zero parameters and moments until the caller sets parameters
-    if (hipMemset(m->mem, 0, off) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
-        (void)hipFree(m->mem);
+    if (hipMemset(m->mem, 0, a.total) != hipSuccess || hipDeviceSynchronize() != hipSuccess) {
         delete m;
         return PARIS_EHIP;
     }
@@ -1942,8 +2114,7 @@ paris_status paris_mlp_free(paris_mlp* m)
         }
     }
     m->magic = 0;
-    (void)hipDeviceSynchronize();
-    (void)hipFree(m->mem);
+    (void)hipDeviceSynchronize();   // the workspace goes back to its owner idle
     delete m;
     return PARIS_OK;
 }

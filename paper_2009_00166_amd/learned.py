@@ -66,14 +66,21 @@ def query_features(Q, stream=None):
 
 
 class SeedModel:
-    """The 16 -> 256 -> 256 -> n_leaves seed network (library-owned device memory)."""
+    """The 16 -> 256 -> 256 -> n_leaves seed network; its device workspace is a torch tensor."""
 
-    def __init__(self, n_leaves: int, max_rows: int = 4096, params=None):
+    def __init__(self, n_leaves: int, max_rows: int = 4096, params=None, device="cuda"):
+        torch = _torch()
         self.n_leaves = int(n_leaves)
         self.max_rows = int(max_rows)
         self.n_params = param_count(self.n_leaves)
+        lib = load_library()
+        nb = ctypes.c_int64()
+        check(lib.paris_mlp_workspace_size(self.n_leaves, self.max_rows, ctypes.byref(nb)), "paris_mlp_workspace_size")
+        # torch's caching allocator hands out 512-byte aligned blocks
+        self._ws = torch.empty(int(nb.value), dtype=torch.uint8, device=device)
         h = ctypes.c_void_p()
-        check(load_library().paris_mlp_create(self.n_leaves, self.max_rows, ctypes.byref(h)), "paris_mlp_create")
+        check(lib.paris_mlp_create(self.n_leaves, self.max_rows, ctypes.c_void_p(self._ws.data_ptr()), int(nb.value),
+                                   ctypes.byref(h)), "paris_mlp_create")
         self._h = h
         if params is not None:
             self.set_params(params)
@@ -145,6 +152,7 @@ class SeedModel:
         if getattr(self, "_h", None) is not None and self._h.value:
             load_library().paris_mlp_free(self._h)
             self._h = ctypes.c_void_p()
+        self._ws = None   # after the free: the network never outlives its workspace
 
     def __del__(self):
         try:

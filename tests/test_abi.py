@@ -117,9 +117,19 @@ def test_seed_network_argument_errors_before_any_launch():
     for bad in (0, 8, 100, 65600):
         assert lib.paris_mlp_param_count(bad, ctypes.byref(cnt)) == B.PARIS_EINVAL
     h = ctypes.c_void_p()
+    nb = ctypes.c_int64(0)
+    assert lib.paris_mlp_workspace_size(4096, 64, ctypes.byref(nb)) == B.PARIS_OK
+    # the parameters, their bfloat16 copy, gradient and two moments alone take 18 bytes each
+    assert nb.value >= 18 * 1_122_816
+    fake = ctypes.c_void_p(1 << 20)   # never dereferenced: every call below fails its argument checks
     for nl, rows in ((100, 64), (4096, 100), (4096, 0), (0, 64)):
-        assert lib.paris_mlp_create(nl, rows, ctypes.byref(h)) == B.PARIS_EINVAL
-    assert lib.paris_mlp_create(4096, 64, None) == B.PARIS_EINVAL
+        assert lib.paris_mlp_workspace_size(nl, rows, ctypes.byref(nb)) == B.PARIS_EINVAL
+        assert lib.paris_mlp_create(nl, rows, fake, 1 << 40, ctypes.byref(h)) == B.PARIS_EINVAL
+    assert lib.paris_mlp_create(4096, 64, fake, 1 << 40, None) == B.PARIS_EINVAL
+    assert lib.paris_mlp_create(4096, 64, None, 1 << 40, ctypes.byref(h)) == B.PARIS_EINVAL
+    assert lib.paris_mlp_create(4096, 64, ctypes.c_void_p((1 << 20) + 4), 1 << 40, ctypes.byref(h)) == B.PARIS_EINVAL
+    lib.paris_mlp_workspace_size(4096, 64, ctypes.byref(nb))
+    assert lib.paris_mlp_create(4096, 64, fake, nb.value - 1, ctypes.byref(h)) == B.PARIS_EINVAL
     null = ctypes.c_void_p()
     opt = B.ParisAdam(1e-3, 0.9, 0.999, 1e-8)
     assert lib.paris_mlp_set_params(null, null, null) == B.PARIS_ESTATE
