@@ -438,6 +438,8 @@ def main() -> int:
     # the window in CLOCK_MONOTONIC nanoseconds, to pick this region's launches out of a trace
     log(f"timed window monotonic ns {w0} {time.clock_gettime_ns(time.CLOCK_MONOTONIC)}")
     scan_ms, timed = index.timing()
+    lay = index.layout()
+    scan_shape = {"threads": lay.scan_threads, "blocks_per_cu": lay.scan_blocks_per_cu, "unroll": lay.scan_unroll}
     # one more pass, outside the timed region, with events around all three phases
     index.set_timing(True)
     step(record=False)
@@ -486,6 +488,7 @@ def main() -> int:
                    "seed_cap": 16384},
         "roofline": {"bound": "hbm", "kernel": "k_lbscan", "achieved": achieved,
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
+                     "launch_shape": scan_shape,
                      "cache_resident": bool(COARSE_BYTES_PER_SERIES * N < 256e6),
                      "achieved_cold": cold["achieved_GBps"] if cold else None,
                      "frac_cold": cold["frac"] if cold else None,

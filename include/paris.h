@@ -282,9 +282,9 @@ paris_status paris_query_batch_multi(paris_index *const *idx, int32_t n_idx, con
 /*
  * Batched pipeline resources (the batched pattern of the paper's worker pools: many queries,
  * one launch). paris_batch_workspace_size gives the bytes for chunks of up to max_batch queries
- * (1 .. 65536): a bfloat16 copy of the collection in leaf order [N][np] (np = the screened
- * dimensions rounded up to 32), its norms, the query buffers, per-query states, a candidate
- * list of min(4096 * max_batch, 2^32 - 16) entries (12 bytes each: query, series, float32
+ * (1 .. 65536): a bfloat16 copy of the collection in leaf order (np = the screened dimensions
+ * rounded up to 32; stored in MFMA fragment order, ceil(N / 32) blocks of 32 rows x np), its norms, the query buffers, per-query states, per-query
+ * bias rows of the screen (32 bytes each), a candidate list of min(4096 * max_batch, 2^32 - 16) entries (12 bytes each: query, series, float32
  * re-scored distance), per-query learned-seed leaves and PAA, the symbol envelope of every
  * run of 32 sorted positions (32 bytes) and the block bound's alive bits
  * (ceil(N / 128) * ceil(max_batch / 64) words of 8 bytes).

@@ -27,7 +27,7 @@ constexpr uint32_t kMagic = 0x50415249u;  // "PARI"
 constexpr int kScanCands = 8;
 constexpr ScanShape kScanCandidates[kScanCands] = {{512, 2, 1}, {512, 2, 2}, {512, 4, 1}, {512, 1, 4},
                                                    {256, 4, 1}, {256, 4, 2}, {256, 8, 1}, {256, 3, 4}};
-constexpr int kTunePer = 6;   // queries per candidate in the online phase
+constexpr int kTunePer = 6;   // queries of the online phase (each scanned with every candidate)
 // mapped host buffer of an index: the query result, then the k-NN answers 256 bytes on
 constexpr size_t kHostResBytes = 256 + kKnnMax * sizeof(KnnHit);
 static_assert(sizeof(QResult) <= 256, "the k-NN answers follow the result at 256 bytes");
@@ -209,8 +209,8 @@ struct paris_index {
     KnnHit* host_knn_dev;
     Margins mg;
     ScanShape scan;
-    // online scan tuning: the first kScanCands * kTunePer queries cycle through the candidate
-    // shapes, each scan timed by events bound to its dispatch; the smallest median wins
+    // online scan tuning: each of the first kTunePer queries is scanned with every candidate
+    // shape, each scan timed by events bound to its dispatch; the smallest total wins
     int scan_online;        // queries left in the online phase (0: done or off)
     bool scan_decide;       // the phase is over and its events await reading
     hipEvent_t tune_ev[kScanCands * kTunePer][2];
@@ -233,7 +233,7 @@ struct paris_index {
     int proj;   // segment length of the screen's projection (1: n <= 256, the series itself)
     bool screen_ok;
     struct {
-        size_t hdr, xb, xn, qin, qb, bq, cand, cand_d2, oidx, odist, fb, leaves, env, qpaa, mask, total;
+        size_t hdr, xb, xn, qin, qb, bq, qbias, cand, cand_d2, oidx, odist, fb, leaves, env, qpaa, mask, total;
         uint32_t cand_cap;
     } bp;
     ScreenShape screen;
@@ -603,32 +603,26 @@ paris_status run_query(paris_index* h, const float* q, hipStream_t st, long long
     if (h->scan_decide) {
         // the online phase's scans finished before their queries' results were read back
         HIP_TRY(hipEventSynchronize(h->tune_ev[kScanCands * kTunePer - 1][1]));
+        // paired comparison: every candidate scanned the same queries; the smallest total wins
         float best = 1e30f;
         for (int c = 0; c < kScanCands; ++c) {
-            float t[kTunePer];
+            float total = 0.f;
             for (int k = 0; k < kTunePer; ++k) {
                 const int slot = k * kScanCands + c;
-                t[k] = 1e30f;
                 float ms = 0.f;
-                if (hipEventElapsedTime(&ms, h->tune_ev[slot][0], h->tune_ev[slot][1]) == hipSuccess) t[k] = ms;
+                total += hipEventElapsedTime(&ms, h->tune_ev[slot][0], h->tune_ev[slot][1]) == hipSuccess ? ms : 1e30f;
             }
-            for (int i = 1; i < kTunePer; ++i)   // insertion sort
-                for (int j = i; j > 0 && t[j] < t[j - 1]; --j) { const float x = t[j]; t[j] = t[j - 1]; t[j - 1] = x; }
-            const float med = 0.5f * (t[kTunePer / 2 - 1] + t[kTunePer / 2]);
-            if (med < best) { best = med; h->scan = kScanCandidates[c]; }
+            if (total < best) { best = total; h->scan = kScanCandidates[c]; }
         }
         h->scan_decide = false;
         scan_to_cache(h);
     }
-    ScanShape shape = h->scan;
-    hipEvent_t se0 = nullptr, se1 = nullptr;
-    if (!timed && h->scan_online > 0) {
-        const int slot = kScanCands * kTunePer - h->scan_online;
-        shape = kScanCandidates[slot % kScanCands];
-        se0 = h->tune_ev[slot][0];
-        se1 = h->tune_ev[slot][1];
-        if (--h->scan_online == 0) h->scan_decide = true;
-    }
+    const ScanShape shape = h->scan;
+    // online phase: this query is scanned once with every candidate shape (in an order rotated
+    // per query, so that no candidate always runs first on a cold cache), each run bound to its
+    // own events; the last run's survivors are the ones refined
+    const int online = (!timed && h->scan_online > 0) ? kTunePer - h->scan_online : -1;
+    if (online >= 0 && --h->scan_online == 0) h->scan_decide = true;
     if (timed && all) HIP_TRY(hipEventRecord(ev[0], st));
     if (h->learned) {
         const paris_mlp* m = h->model;
@@ -643,7 +637,16 @@ paris_status run_query(paris_index* h, const float* q, hipStream_t st, long long
     // first kernel); the scan alone: events bound to the scan kernel's dispatch
     if (timed && all) HIP_TRY(hipEventRecord(ev[1], st));
     const bool bind = timed && !all;
-    HIP_TRY(launch_lbscan(a, -1.f, shape, st, bind ? ev[1] : se0, bind ? ev[2] : se1));
+    if (online >= 0) {
+        for (int r = 0; r < kScanCands; ++r) {
+            const int c = (r + online) % kScanCands;
+            if (r > 0) HIP_TRY(launch_scan_again(a, st));
+            const int slot = online * kScanCands + c;
+            HIP_TRY(launch_lbscan(a, -1.f, kScanCandidates[c], st, h->tune_ev[slot][0], h->tune_ev[slot][1]));
+        }
+    } else {
+        HIP_TRY(launch_lbscan(a, -1.f, shape, st, bind ? ev[1] : nullptr, bind ? ev[2] : nullptr));
+    }
     if (timed && all) HIP_TRY(hipEventRecord(ev[2], st));
     HIP_TRY(launch_refine_resolve(a, q, out_idx, out_dist, qi, st));
     if (timed && all) HIP_TRY(hipEventRecord(ev[3], st));
@@ -750,11 +753,12 @@ void make_batch_plan(paris_index* h, int max_batch)
     auto take = [&off](size_t bytes) { const size_t at = off; off = align_up(off + bytes); return at; };
     const size_t N = (size_t)h->N, M = (size_t)max_batch;
     h->bp.hdr = take(256);
-    h->bp.xb = take(N * h->np * 2);
+    h->bp.xb = take((N + 31) / 32 * 32 * h->np * 2);   // whole 32-row fragment blocks
     h->bp.xn = take(N * 4);
     h->bp.qin = take(M * h->n * 4);
     h->bp.qb = take(M * h->np * 2);
     h->bp.bq = take(M * sizeof(BQuery));
+    h->bp.qbias = take(M * 32);
     const size_t cap = M * 4096 < (size_t)0xFFFFFFF0u ? M * 4096 : (size_t)0xFFFFFFF0u;
     h->bp.cand_cap = (uint32_t)cap;
     h->bp.cand = take(cap * 8);
@@ -790,6 +794,7 @@ ScreenArgs screen_args(paris_index* h, int m, float* dump, bool masked = true)
     s.N = h->N;
     s.Qb = reinterpret_cast<const uint16_t*>(h->bws + h->bp.qb);
     s.bq = bqs(h);
+    s.qbias = reinterpret_cast<uint16_t*>(h->bws + h->bp.qbias);
     s.M = m;
     s.cand = reinterpret_cast<uint2*>(h->bws + h->bp.cand);
     s.cand_d2 = reinterpret_cast<float*>(h->bws + h->bp.cand_d2);
@@ -1433,7 +1438,7 @@ paris_status paris_build(const float* series_dev, int64_t n_series, int32_t leng
         bool ok = true;
         for (int k = 0; k < kScanCands * kTunePer && ok; ++k)
             ok = hipEventCreate(&h->tune_ev[k][0]) == hipSuccess && hipEventCreate(&h->tune_ev[k][1]) == hipSuccess;
-        if (ok) h->scan_online = kScanCands * kTunePer;
+        if (ok) h->scan_online = kTunePer;
     }
     if (ts != PARIS_OK) {
         (void)hipHostFree(h->host_qs);

@@ -96,6 +96,17 @@ __device__ __forceinline__ float seg_mean(const float* __restrict__ x, int j, in
     return (float)(acc / (double)P);
 }
 
+// Element offset of dimension d of row p in the bfloat16 copy. Rows are stored in fragment
+// order: blocks of 32 rows, each a run of np / 16 k-steps of 64 lanes x 8 values, lane
+// 32 h + c holding dimensions 16 s + 8 h .. + 7 of row 32 b + c. That is the B operand of
+// v_mfma_f32_32x32x16_bf16 for k-step s of the 32 series of block b, so the screen reads a
+// wave's series fragments with loads of 1 KiB contiguous; 8 consecutive dimensions of a row
+// (a 16-byte chunk starting at a multiple of 8) stay contiguous for the 16-wide form.
+__host__ __device__ __forceinline__ long long xb_off(long long p, int d, int np)
+{
+    return ((((p >> 5) * (np >> 4) + (d >> 4)) * 64) + ((d >> 3) & 1) * 32 + (p & 31)) * 8 + (d & 7);
+}
+
 // Row p of the copy is series perm[p] (leaf order), so that a run of consecutive rows shares
 // long iSAX prefixes and the block bound of the screen (k_block_mask) stays tight.
 __global__ __launch_bounds__(256) void k_to_bf16(const float* __restrict__ X, const uint32_t* __restrict__ perm,
@@ -108,11 +119,10 @@ __global__ __launch_bounds__(256) void k_to_bf16(const float* __restrict__ X, co
     const int nd = n / P;
     for (long long i = wave; i < N; i += nw) {
         const float* row = X + (long long)perm[i] * n;
-        uint16_t* out = Xb + i * np;
         float sq = 0.f;
         for (int j = lane; j < np; j += 64) {
             const float v = j < nd ? seg_mean(row, j, P) : 0.f;
-            out[j] = to_bf16(v);
+            Xb[xb_off(i, j, np)] = to_bf16(v);
             sq += v * v;
         }
         for (int off = 32; off > 0; off >>= 1) sq += __shfl_xor(sq, off);
@@ -418,7 +428,7 @@ __global__ __launch_bounds__(256, SUBS == 2 ? 2 : 1) void k_screen(ScreenArgs S)
             const bool ok = x < N;
 #pragma unroll
             for (int ks = 0; ks < KS; ++ks) {
-                if (ok) bfr[sub][ks] = *reinterpret_cast<const bf16x8*>(S.Xb + x * NP + ks * 32 + kg * 8);
+                if (ok) bfr[sub][ks] = *reinterpret_cast<const bf16x8*>(S.Xb + xb_off(x, ks * 32 + kg * 8, NP));
                 else bfr[sub][ks] = bf16x8{};
             }
             // bias step: lanes of k-group 0 carry [1, RU(-b_x), 0 ...]
@@ -529,6 +539,16 @@ __global__ __launch_bounds__(256, SUBS == 2 ? 2 : 1) void k_screen(ScreenArgs S)
     if (ccount) flush_cands();
 }
 
+// 16 bytes per lane from base + voffset (bytes) into LDS at lds + 8 lane (bfloat16 elements; lds
+// is wave-uniform): buffer_load_dwordx4 ... lds through a raw descriptor of `bytes` bytes, so a
+// read past the end returns zeros.
+__device__ __forceinline__ void lds_dma16(const uint16_t* base, int bytes, int voffset, uint16_t* lds)
+{
+    const __amdgpu_buffer_rsrc_t rs =
+        __builtin_amdgcn_make_buffer_rsrc(const_cast<uint16_t*>(base), (short)0, bytes, 0x00020000);
+    __builtin_amdgcn_raw_ptr_buffer_load_lds(rs, (__attribute__((address_space(3))) void*)lds, 16, voffset, 0, 0, 0);
+}
+
 // The same screen on v_mfma_f32_32x32x16_bf16: a 32 x 32 output tile per instruction doubles
 // the work per operand byte, so a query fragment read from LDS feeds twice the arithmetic of
 // the 16 x 16 form. A wave holds S subtiles of 32 series (k-steps of 16, plus the bias step) in
@@ -537,7 +557,12 @@ __global__ __launch_bounds__(256, SUBS == 2 ? 2 : 1) void k_screen(ScreenArgs S)
 // and B (series); accumulator element i of lane l is row 8 (i / 4) + 4 (l / 32) + i % 4, column
 // l % 32. Bias step: query rows carry [hi(-a_q), lo(-a_q), 1, 1] and series rows
 // [1, 1, hi(-b_x), lo(-b_x)] in k-elements 0..3, zeros elsewhere.
-template <int KS16, int QT, int S>
+// Work units are (work item of 4 S 32 sorted positions, group of queries), claimed from a
+// counter one ahead; a unit builds its alive list, reads its series fragments (1 KiB contiguous
+// per load: the copy is in fragment order), then runs its query tiles. The register budget of
+// two waves per SIMD (256) holds the S series fragment sets, the accumulators and a query
+// fragment pipeline two k-steps deep with nothing live across units.
+template <int KS16, int QT, int S, bool DUMP>
 __global__ __launch_bounds__(256, 2) void k_screen32(ScreenArgs Sa)
 {
     static_assert(S == 1 || S == 2, "one or two 32-series subtiles per wave");
@@ -552,9 +577,11 @@ __global__ __launch_bounds__(256, 2) void k_screen32(ScreenArgs Sa)
     constexpr int SWM = CH % 8 == 0 ? 7 : 3;
     static_assert(CH % (SWM + 1) == 0, "the swizzle must permute the chunks of a row");
     constexpr int TCH = QT * CH;        // chunks per query tile
+    static_assert(TCH % 64 == 0, "a wave's 64 chunk positions are all inside the tile or all past it");
     constexpr int LOADS = (TCH + 255) / 256;    // direct-to-LDS loads per lane per tile
     // queries per alive list: two blocks per CU must fit in LDS next to the two tile buffers
     constexpr int GROUP = QT * NP >= 64 * 256 ? kScreenGroup / 2 : kScreenGroup;
+    static_assert(GROUP % QT == 0, "a tile never reads past the list");
     // Query tiles go from global memory straight into LDS (global_load_lds_dwordx4: no staging
     // registers, so nothing holds the MFMAs back while the next tile is in flight). A row's
     // 16-byte chunk c sits at chunk c ^ (row & SWM) of the row, so the 8 rows that one LDS cycle
@@ -566,7 +593,7 @@ __global__ __launch_bounds__(256, 2) void k_screen32(ScreenArgs Sa)
     // queries of the current group whose block bound did not prune the item (ascending)
     __shared__ uint16_t s_list[GROUP];
     __shared__ uint32_t s_cnt;
-    __shared__ long long s_item;
+    __shared__ long long s_item, s_next;
     __shared__ uint2 cbuf[kCandStage];
     __shared__ uint32_t ccount, cbase;
     // largest survivor accumulator of every query seen by this block (batches of at most
@@ -575,21 +602,23 @@ __global__ __launch_bounds__(256, 2) void k_screen32(ScreenArgs Sa)
     constexpr int LDS_BASE = 4 * QT * NP + 64 * QT + 2 * GROUP + 8 * kCandStage + 256;   // bytes
     constexpr int AQ = LDS_BASE + 4 * kAmaxQueries <= 80 * 1024 - 512 ? kAmaxQueries : 1;
     __shared__ uint32_t s_amax[AQ];
-    const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+    const int tid = threadIdx.x, l = tid & 63;
+    // the wave index, known to the compiler as uniform: per-wave addresses stay in scalar registers
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
     if (tid == 0) ccount = 0;
-    const bool track = AQ > 1 && Sa.M <= AQ && Sa.dump == nullptr;
+    const bool track = AQ > 1 && Sa.M <= AQ && !DUMP;
     if (track)
         for (int e = tid; e < Sa.M; e += 256) s_amax[e] = 0u;
     // A candidate at list position pos: (query, series) and its accumulator truncated to the top
     // 16 bits (so at most the accumulator), from which the re-score derives distance bounds.
     // Staged entries carry (query | top 16 bits of the accumulator, sorted position).
-    auto store_cand = [&](uint32_t pos, uint32_t qa, uint32_t p) {
+    auto store_cand = [&](uint32_t pos, uint32_t qa, uint32_t p) __attribute__((always_inline)) {
         if (pos < Sa.cand_cap) {
             Sa.cand[pos] = make_uint2(qa & 0xFFFFu, Sa.perm ? Sa.perm[p] : p);
             Sa.cand_d2[pos] = __uint_as_float(qa & 0xFFFF0000u);
         }
     };
-    auto flush_cands = [&]() {
+    auto flush_cands = [&]() __attribute__((always_inline)) {
         const uint32_t cnt = min(ccount, (uint32_t)kCandStage);
         if (tid == 0) cbase = atomicAdd(&Sa.hdr->n_cand, cnt);
         __syncthreads();
@@ -603,82 +632,96 @@ __global__ __launch_bounds__(256, 2) void k_screen32(ScreenArgs Sa)
     const int M = Sa.M;
     const long long N = Sa.N;
     const long long n_items = (N + XB - 1) / XB;
-    const bool dump = Sa.dump != nullptr;
-    const bool masked = Sa.mask != nullptr && !dump;
+    const bool masked = Sa.mask != nullptr && !DUMP;
     const int words = (M + 63) >> 6;
+    // work units: (work item, group of GROUP queries), item-major; one group for M <= GROUP
+    const int n_groups = (M + GROUP - 1) / GROUP;
+    const long long n_units = n_items * n_groups;
     int g0 = 0, cnt = 0;   // current query group and its number of listed queries
 
-    // query of list entry i of the current group (i < cnt)
-    auto query_of = [&](int i) -> int { return g0 + (masked ? (int)s_list[i] : i); };
+    // query of list entry i of the current group; entries past the list (i >= cnt, i < GROUP)
+    // read query g0, whose rows then carry a bias that never passes. The list is read at a
+    // clamped index whether or not it is in use, so the reads need no branch.
+    auto query_at = [&](int i) __attribute__((always_inline)) -> int {
+        const int ic = i < cnt ? i : 0;
+        const int li = (int)s_list[ic];
+        return i < cnt ? g0 + (masked ? li : ic) : g0;
+    };
     // series index of sorted position p (the bfloat16 rows are stored in leaf order)
-    auto series_of = [&](long long p) -> uint32_t { return Sa.perm ? Sa.perm[p] : (uint32_t)p; };
+    auto series_of = [&](uint32_t p) __attribute__((always_inline)) -> uint32_t { return Sa.perm ? Sa.perm[p] : p; };
 
-    // bias rows: [hi, lo, 1, 1, 0 ...]; the last 12 stay zero
-    for (int e = tid; e < QT * 2; e += 256) {
-        *reinterpret_cast<uint4*>(&qb0[e * 8]) = make_uint4(0, 0, 0, 0);
-        *reinterpret_cast<uint4*>(&qb1[e * 8]) = make_uint4(0, 0, 0, 0);
-    }
-
-    // tile t of the current list into qdata[buf] (asynchronous: complete after the next full
-    // wait) and its raw bias constants into registers; rows past the list read query g0 (their
-    // bias never passes). The two tile buffers are distinct arrays addressed with a compile-time
-    // index (the tile loop is unrolled by two), so the compiler can see that the next tile's
-    // direct loads never write the buffer being read and need not wait for them before the LDS
-    // reads.
-    auto tile_load = [&](int t, auto BUF, uint2& bias) {
+    // The queries of tile t's rows that this lane loads, data chunks and (in the first 2 QT / 64
+    // waves) the bias-row chunk w 64 + l, half a row each: every list read is issued before any
+    // of them is used.
+    struct TileRows {
+        int q[LOADS];
+        int qb;
+    };
+    auto tile_rows = [&](int t) __attribute__((always_inline)) {
+        TileRows r;
+#pragma unroll
+        for (int j = 0; j < LOADS; ++j) {
+            const int pos = (j * 4 + w) * 64 + l;
+            r.q[j] = query_at(t * QT + min(pos / CH, QT - 1));
+        }
+        r.qb = query_at(t * QT + min((w * 64 + l) >> 1, QT - 1));
+        return r;
+    };
+    // tile t into qd[BUF] (asynchronous: complete after the next full wait) and its raw bias
+    // constants into registers. The two tile buffers are distinct arrays addressed with a
+    // compile-time index (the tile loop is unrolled by two), so the compiler can see that the
+    // next tile's direct loads never write the buffer being read and need not wait for them
+    // before the LDS reads. The loads are buffer loads (buffer_load_dwordx4 ... lds) through a
+    // descriptor covering the M query rows: unlike the flat-encoded global form, they leave the
+    // LDS reads' counter in order, so a fragment read waits only for itself.
+    auto tile_issue = [&](const TileRows& r, auto BUF) __attribute__((always_inline)) {
         uint16_t* dst = decltype(BUF)::value == 0 ? qd0 : qd1;
+        if (w * 64 < 2 * QT)   // uniform: bias rows, [hi(-a_q), lo(-a_q), 1, 1, 0 ...], 32 bytes each
+            lds_dma16(Sa.qbias, M * 32, (r.qb * 16 + (l & 1) * 8) * 2,
+                      (decltype(BUF)::value == 0 ? qb0 : qb1) + w * 64 * 8);
 #pragma unroll
         for (int j = 0; j < LOADS; ++j) {
             const int pos = (j * 4 + w) * 64 + l;             // chunk position in the tile
-            if (pos < TCH) {
+            if ((j * 4 + w) * 64 < TCH) {                     // uniform per wave
                 const int row = pos / CH, pc = pos - row * CH;
                 const int c = pc ^ (row & SWM);
-                const int i = t * QT + row;
-                const int q = i < cnt ? query_of(i) : g0;
-                const uint16_t* src = Sa.Qb + (long long)q * NP + c * 8;
-                __builtin_amdgcn_global_load_lds(
-                    (__attribute__((address_space(1))) const void*)src,
-                    (__attribute__((address_space(3))) void*)(dst + (j * 4 + w) * 64 * 8), 16, 0, 0);
+                lds_dma16(Sa.Qb, M * NP * 2, (r.q[j] * NP + c * 8) * 2, dst + (j * 4 + w) * 64 * 8);
             }
         }
-        if (tid < QT) {
-            const int i = t * QT + tid;
-            const bool ok = i < cnt;
-            const int q = ok ? query_of(i) : g0;
-            bias.x = __float_as_uint(Sa.bq[q].a);
-            bias.y = dump ? 2u : (ok ? 1u : 0u);
-        }
-    };
-    auto bias_store = [&](auto BUF, uint2 bias) {
-        uint16_t* dst = decltype(BUF)::value == 0 ? qb0 : qb1;
-        if (tid < QT) {
-            const float a = bias.y == 1u ? __uint_as_float(bias.x) : (bias.y == 2u ? 0.f : __builtin_inff());
-            const float t1 = a < __builtin_inff() ? -a : kNoPass;
-            uint2 bp = bias_pair(t1);  // [hi(-a_q), lo(-a_q), 1.0, 1.0]
-            bp.y = 0x3F803F80u;
-            *reinterpret_cast<uint2*>(&dst[tid * 16]) = bp;
-        }
     };
 
+    // Work units are claimed one ahead (the claim's latency is off the path between units).
+    if (tid == 0) s_next = (long long)atomicAdd(&Sa.hdr->next_item, 1u);
     for (;;) {
         __syncthreads();
-        if (tid == 0) s_item = (long long)atomicAdd(&Sa.hdr->next_item, 1u);
+        if (tid == 0) {
+            s_item = s_next;
+            s_next = s_next < n_units ? (long long)atomicAdd(&Sa.hdr->next_item, 1u) : n_units;
+        }
         __syncthreads();
-        const long long item = s_item;
-        if (item >= n_items) break;  // uniform: every wave reaches this exit
-        const long long xb0 = item * XB + w * XW;
+        // values read from LDS, made wave-uniform for the compiler (scalar registers, uniform
+        // branches): every lane read the same word (units fit 31 bits: N / 128 items x 16 groups)
+        const int unit = __builtin_amdgcn_readfirstlane((int)s_item);
+        if (unit >= n_units) break;  // uniform: every wave reaches this exit
+        const long long item = unit / n_groups;
+        g0 = (unit - (int)item * n_groups) * GROUP;
+        // this wave's first sorted position (sorted positions fit 32 bits: N <= 2^32 - 1) and the
+        // wave-uniform bases its rows are addressed from with 32-bit lane offsets
+        const uint32_t xw0 = (uint32_t)(item * XB + w * XW);
+        // the wave's fragments of series block b = xw0 / 32 + sub start at Xb + b KS16 512
+        const uint16_t* xfrag = Sa.Xb + (long long)(xw0 >> 5) * KS16 * 512 + l * 8;
+        const float* xnorm = Sa.xn + xw0;
 
         bf16x8 bfr[S][KT];
-        bool loaded = false;   // uniform: the series rows are read at the first non-empty group
-        uint32_t tiles = 0;
-        for (g0 = 0; g0 < M; g0 += GROUP) {
+        {
             if (masked) {
                 // the group's alive bits -> ascending list of queries (one wave, prefix sum of
                 // the word popcounts); the barrier first: every wave has read the last count
                 __syncthreads();
                 if (w == 0) {
                     const int w0 = g0 >> 6, gw = min(GROUP / 64, words - w0);
-                    unsigned long long bits = l < gw ? Sa.mask[item * words + w0 + l] : 0ull;
+                    const unsigned long long* mrow = Sa.mask + item * words + w0;
+                    unsigned long long bits = l < gw ? mrow[l] : 0ull;
                     const uint32_t pc = (uint32_t)__popcll(bits);
                     uint32_t inc = pc;
 #pragma unroll
@@ -694,24 +737,24 @@ __global__ __launch_bounds__(256, 2) void k_screen32(ScreenArgs Sa)
                     if (l == 63) s_cnt = inc;
                 }
                 __syncthreads();
-                cnt = (int)s_cnt;
+                cnt = __builtin_amdgcn_readfirstlane((int)s_cnt);
             } else {
                 cnt = min(GROUP, M - g0);
             }
             if (cnt == 0) continue;   // uniform
-            if (!loaded) {
-                loaded = true;
+            {
 #pragma unroll
                 for (int sub = 0; sub < S; ++sub) {
-                    const long long x = xb0 + sub * 32 + col;
-                    const bool ok = x < N;
+                    const uint32_t xl = sub * 32 + col;
+                    const bool ok = xw0 + xl < N;
+                    const uint16_t* xr = xfrag + sub * KS16 * 512;
 #pragma unroll
                     for (int ks = 0; ks < KS16; ++ks) {
-                        if (ok) bfr[sub][ks] = *reinterpret_cast<const bf16x8*>(Sa.Xb + x * NP + ks * 16 + kh * 8);
+                        if (ok) bfr[sub][ks] = *reinterpret_cast<const bf16x8*>(xr + ks * 512);
                         else bfr[sub][ks] = bf16x8{};
                     }
                     float t2 = kNoPass;
-                    if (ok) t2 = dump ? 0.f : -__double2float_rd((1.0 - (double)Sa.c_screen) * (double)Sa.xn[x] * 0.5);
+                    if (ok) t2 = DUMP ? 0.f : -__double2float_rd((1.0 - (double)Sa.c_screen) * (double)xnorm[xl] * 0.5);
                     uint4 bb = make_uint4(0, 0, 0, 0);
                     if (kh == 0) {
                         bb.x = 0x3F803F80u;   // [1.0, 1.0, hi(-b_x), lo(-b_x)]
@@ -721,22 +764,19 @@ __global__ __launch_bounds__(256, 2) void k_screen32(ScreenArgs Sa)
                 }
             }
             const int n_qt = (cnt + QT - 1) / QT;
-            tiles += (uint32_t)n_qt;
 
-            {
-                uint2 bias = make_uint2(0u, 0u);
-                tile_load(0, std::integral_constant<int, 0>{}, bias);
-                bias_store(std::integral_constant<int, 0>{}, bias);
-                __builtin_amdgcn_s_waitcnt(0);
-            }
+            tile_issue(tile_rows(0), std::integral_constant<int, 0>{});
+            __builtin_amdgcn_s_waitcnt(0);
             __syncthreads();
 
-            auto tile = [&](int t, auto CUR) {
+            auto tile = [&](int t, auto CUR) __attribute__((always_inline)) {
                 constexpr int B = decltype(CUR)::value;
                 const std::integral_constant<int, 1 - B> NEXT{};
-                uint2 bias = make_uint2(0u, 0u);
                 const bool more = t + 1 < n_qt;
-                if (more) tile_load(t + 1, NEXT, bias);  // lands in LDS during the MFMAs
+                // the next tile's list entries now; its loads go out after the first k-step's
+                // MFMAs, by when the list reads have returned
+                TileRows nr;
+                if (more) nr = tile_rows(t + 1);
 
                 f32x16 acc[QS][S];
 #pragma unroll
@@ -747,34 +787,47 @@ __global__ __launch_bounds__(256, 2) void k_screen32(ScreenArgs Sa)
                         for (int i = 0; i < 16; ++i) acc[qs][sub][i] = 0.f;
                 const uint16_t* tb = B == 0 ? qd0 : qd1;
                 const uint16_t* tbb = (B == 0 ? qb0 : qb1) + col * 16 + kh * 8;
-                auto a_frag = [&](int qs, int ks) -> bf16x8 {
+                // chunk (2 ks + kh) ^ (row & SWM) of row qs 32 + col: with SWM = 7 the bits above
+                // bit 2 of 2 ks pass the XOR unchanged, so it is a lane offset for ks mod 4 plus
+                // the constant 8 (ks / 4) chunks (an immediate offset of the LDS read)
+                auto a_frag = [&](int qs, int ks) __attribute__((always_inline)) -> bf16x8 {
                     const int row = qs * 32 + col;
                     if (ks == KS16) return *reinterpret_cast<const bf16x8*>(tbb + qs * 32 * 16);
-                    const int c = (2 * ks + kh) ^ (row & SWM);
-                    return *reinterpret_cast<const bf16x8*>(tb + row * NP + c * 8);
+                    if constexpr (SWM == 7) {
+                        const int c = ((2 * (ks & 3) + kh) ^ (col & 7)) + 8 * (ks >> 2);
+                        return *reinterpret_cast<const bf16x8*>(tb + row * NP + c * 8);
+                    } else {
+                        const int c = (2 * ks + kh) ^ (row & SWM);
+                        return *reinterpret_cast<const bf16x8*>(tb + row * NP + c * 8);
+                    }
                 };
-                bf16x8 a[QS], an[QS];
+                // query fragments read two k-steps ahead of their MFMAs; the scheduling barriers
+                // keep each read issued before the MFMAs of the step it runs ahead of
+                bf16x8 fa[KT][QS];
 #pragma unroll
-                for (int qs = 0; qs < QS; ++qs) a[qs] = a_frag(qs, 0);
+                for (int qs = 0; qs < QS; ++qs) fa[0][qs] = a_frag(qs, 0);
+                if constexpr (KT > 1) {
+#pragma unroll
+                    for (int qs = 0; qs < QS; ++qs) fa[1][qs] = a_frag(qs, 1);
+                }
 #pragma unroll
                 for (int ks = 0; ks < KT; ++ks) {
-                    if (ks + 1 < KT) {
+                    if (ks + 2 < KT) {
 #pragma unroll
-                        for (int qs = 0; qs < QS; ++qs) an[qs] = a_frag(qs, ks + 1);
+                        for (int qs = 0; qs < QS; ++qs) fa[ks + 2][qs] = a_frag(qs, ks + 2);
                     }
+                    __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
                     for (int qs = 0; qs < QS; ++qs)
 #pragma unroll
                         for (int sub = 0; sub < S; ++sub)
-                            acc[qs][sub] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a[qs], bfr[sub][ks], acc[qs][sub],
-                                                                                   0, 0, 0);
-                    if (ks + 1 < KT) {
-#pragma unroll
-                        for (int qs = 0; qs < QS; ++qs) a[qs] = an[qs];
-                    }
+                            acc[qs][sub] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[ks][qs], bfr[sub][ks],
+                                                                                   acc[qs][sub], 0, 0, 0);
+                    __builtin_amdgcn_sched_barrier(0);
+                    if (ks == 0 && more) tile_issue(nr, NEXT);   // lands in LDS during the MFMAs
                 }
 
-                if (dump) {
+                if constexpr (DUMP) {
 #pragma unroll
                     for (int qs = 0; qs < QS; ++qs)
 #pragma unroll
@@ -782,89 +835,81 @@ __global__ __launch_bounds__(256, 2) void k_screen32(ScreenArgs Sa)
 #pragma unroll
                             for (int i = 0; i < 16; ++i) {
                                 const int r = t * QT + qs * 32 + 8 * (i >> 2) + 4 * kh + (i & 3);
-                                const long long p = xb0 + sub * 32 + col;
+                                const uint32_t p = xw0 + sub * 32 + col;
                                 if (r < cnt && p < N)
-                                    Sa.dump[(long long)query_of(r) * N + series_of(p)] = acc[qs][sub][i];
+                                    Sa.dump[(long long)query_at(r) * N + series_of(p)] = acc[qs][sub][i];
                             }
                 } else {
+                    // One wave-wide test (the lanes' largest accumulators) for the common tile
+                    // without a passing pair. Otherwise every accumulator slot (qs, sub, i) is
+                    // tested with its own ballot (a scalar branch per slot); a slot with passing
+                    // lanes drops rows past the list and series past N, reserves the remaining
+                    // lanes' cbuf entries with one LDS atomic (ranks from mbcnt) and writes them.
                     float m = kNoPass;
 #pragma unroll
                     for (int qs = 0; qs < QS; ++qs)
 #pragma unroll
                         for (int sub = 0; sub < S; ++sub)
 #pragma unroll
-                            for (int i = 0; i < 16; ++i) m = fmaxf(m, acc[qs][sub][i]);
-                    const bool hit = m >= 0.f;
-                    if (__ballot(hit)) {
-                        // this lane's passing pairs as bits (qs S + sub) 16 + i, one LDS atomic per
-                        // wave for their slots (wave prefix sum), then each lane writes its own
-                        static_assert(QS * S * 16 <= 64, "one 64-bit mask per lane");
-                        unsigned long long bits = 0ull;
+                            for (int i = 0; i < 16; i += 4)
+                                m = fmaxf(m, fmaxf(fmaxf(acc[qs][sub][i], acc[qs][sub][i + 1]),
+                                                   fmaxf(acc[qs][sub][i + 2], acc[qs][sub][i + 3])));
+                    if (__ballot(m >= 0.f)) {
 #pragma unroll
                         for (int qs = 0; qs < QS; ++qs)
 #pragma unroll
                             for (int sub = 0; sub < S; ++sub)
 #pragma unroll
                                 for (int i = 0; i < 16; ++i) {
+                                    const float av = acc[qs][sub][i];
+                                    if (__ballot(av >= 0.f) == 0ull) continue;   // uniform
                                     const int r = t * QT + qs * 32 + 8 * (i >> 2) + 4 * kh + (i & 3);
-                                    const long long p = xb0 + sub * 32 + col;
-                                    if (acc[qs][sub][i] >= 0.f && r < cnt && p < N)
-                                        bits |= 1ull << ((qs * S + sub) * 16 + i);
+                                    const uint32_t p = xw0 + sub * 32 + col;
+                                    const bool take = av >= 0.f && r < cnt && p < N;
+                                    const unsigned long long mk = __ballot(take);
+                                    if (take) {
+                                        const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                                            (uint32_t)(mk >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)mk, 0u));
+                                        uint32_t base = 0;
+                                        if (rank == 0) base = atomicAdd(&ccount, (uint32_t)__popcll(mk));
+                                        base = __builtin_amdgcn_readlane(base, __builtin_ctzll(mk));
+                                        const uint32_t qh = (uint32_t)query_at(r);
+                                        // av >= 0: its bits order as its values
+                                        if (track) atomicMax(&s_amax[qh], __float_as_uint(av));
+                                        const uint2 c = make_uint2(qh | (__float_as_uint(av) & 0xFFFF0000u), p);
+                                        const uint32_t kk = base + rank;
+                                        if (kk < (uint32_t)kCandStage) {
+                                            cbuf[kk] = c;
+                                        } else {  // more than the stage holds in one tile
+                                            store_cand(atomicAdd(&Sa.hdr->n_cand, 1u), c.x, c.y);
+                                        }
+                                    }
                                 }
-                        const uint32_t nb = (uint32_t)__popcll(bits);
-                        uint32_t inc = nb;
-#pragma unroll
-                        for (int o = 1; o < 64; o <<= 1) {
-                            const uint32_t v = __shfl_up(inc, o);
-                            if (l >= o) inc += v;
-                        }
-                        uint32_t base = 0;
-                        if (l == 63) base = atomicAdd(&ccount, inc);
-                        base = __shfl(base, 63);
-                        uint32_t k = base + inc - nb;
-                        while (bits) {
-                            const int bi = __builtin_ctzll(bits);
-                            bits &= bits - 1ull;
-                            const int qs = bi / (S * 16), sub = (bi >> 4) % S, i = bi & 15;
-                            const int r = t * QT + qs * 32 + 8 * (i >> 2) + 4 * kh + (i & 3);
-                            const long long p = xb0 + sub * 32 + col;
-                            float av = 0.f;   // the hit's accumulator (>= 0), selected without dynamic indexing
-#pragma unroll
-                            for (int qq = 0; qq < QS; ++qq)
-#pragma unroll
-                                for (int ss = 0; ss < S; ++ss)
-#pragma unroll
-                                    for (int ii = 0; ii < 16; ++ii)
-                                        if ((qq * S + ss) * 16 + ii == bi) av = acc[qq][ss][ii];
-                            const uint32_t qh = (uint32_t)query_of(r);
-                            if (track) atomicMax(&s_amax[qh], __float_as_uint(av));   // av >= 0: bits order as values
-                            const uint2 c = make_uint2(qh | (__float_as_uint(av) & 0xFFFF0000u), (uint32_t)p);
-                            if (k < (uint32_t)kCandStage) {
-                                cbuf[k] = c;
-                            } else {  // more than the stage holds in one tile
-                                store_cand(atomicAdd(&Sa.hdr->n_cand, 1u), c.x, c.y);
-                            }
-                            ++k;
-                        }
                     }
                 }
-                if (more) bias_store(NEXT, bias);
                 __builtin_amdgcn_s_waitcnt(0);   // this wave's direct-to-LDS loads have landed
                 __syncthreads();
                 if (ccount >= (uint32_t)(kCandStage / 2)) flush_cands();  // uniform: read after the barrier
             };
+            if (tid == 0) atomicAdd(&Sa.hdr->n_tiles, (uint32_t)n_qt);
             for (int t = 0; t < n_qt; t += 2) {
                 tile(t, std::integral_constant<int, 0>{});
                 if (t + 1 < n_qt) tile(t + 1, std::integral_constant<int, 1>{});
             }
         }
-        if (tid == 0 && tiles) atomicAdd(&Sa.hdr->n_tiles, tiles);
     }
     __syncthreads();
     if (ccount) flush_cands();
     if (track)
         for (int q = tid; q < Sa.M; q += 256)
             if (s_amax[q]) atomicMax(&Sa.bq[q].ub, s_amax[q]);
+}
+
+template <int KS16, int QT, int S>
+static void launch_screen32_shape(const ScreenArgs& s, int grid, hipStream_t st)
+{
+    if (s.dump) k_screen32<KS16, QT, S, true><<<grid, 256, 0, st>>>(s);
+    else k_screen32<KS16, QT, S, false><<<grid, 256, 0, st>>>(s);
 }
 
 template <int KS16>
@@ -874,14 +919,14 @@ static hipError_t launch_screen32_ks(const ScreenArgs& s, ScreenShape shape, hip
     if constexpr (KS16 > 16) {
         // more than 256 dimensions: one 32-series subtile per wave and 32-row query tiles (the
         // series fragments alone take 4 (KS16 + 1) registers)
-        k_screen32<KS16, 32, 1><<<grid, 256, 0, st>>>(s);
+        launch_screen32_shape<KS16, 32, 1>(s, grid, st);
     } else {
         if (shape.subs == 1) {
-            if (shape.qt == 64) k_screen32<KS16, 64, 1><<<grid, 256, 0, st>>>(s);
-            else k_screen32<KS16, 32, 1><<<grid, 256, 0, st>>>(s);
+            if (shape.qt == 64) launch_screen32_shape<KS16, 64, 1>(s, grid, st);
+            else launch_screen32_shape<KS16, 32, 1>(s, grid, st);
         } else {
-            if (shape.qt == 64) k_screen32<KS16, 64, 2><<<grid, 256, 0, st>>>(s);
-            else k_screen32<KS16, 32, 2><<<grid, 256, 0, st>>>(s);
+            if (shape.qt == 64) launch_screen32_shape<KS16, 64, 2>(s, grid, st);
+            else launch_screen32_shape<KS16, 32, 2>(s, grid, st);
         }
     }
     return hipGetLastError();
@@ -917,11 +962,27 @@ hipError_t launch_block_mask(const ScreenArgs& s, ScreenShape shape, hipStream_t
     return hipGetLastError();
 }
 
+// The 32-wide screen's bias row of every query: [hi(-a_q), lo(-a_q), 1, 1, 0 x 12] in bfloat16
+// (a query without a threshold, a_q = +inf, takes kNoPass: never passes); with dump, a_q = 0.
+__global__ __launch_bounds__(256) void k_query_bias(const BQuery* __restrict__ bq, int M, bool dump,
+                                                    uint16_t* __restrict__ rows)
+{
+    const int q = blockIdx.x * 256 + threadIdx.x;
+    if (q >= M) return;
+    const float a = dump ? 0.f : bq[q].a;
+    const float t1 = a < __builtin_inff() ? -a : kNoPass;
+    const uint2 bp = bias_pair(t1);
+    uint4* r = reinterpret_cast<uint4*>(rows + (long long)q * 16);
+    r[0] = make_uint4(bp.x, 0x3F803F80u, 0u, 0u);
+    r[1] = make_uint4(0u, 0u, 0u, 0u);
+}
+
 hipError_t launch_screen(const ScreenArgs& s_in, int np, ScreenShape shape, hipStream_t st)
 {
     ScreenArgs s = s_in;
     if (!screen_uses_mask(s, shape)) s.mask = nullptr;
     if (shape.mfma == 32) {
+        if (s.M > 0) k_query_bias<<<(s.M + 255) / 256, 256, 0, st>>>(s.bq, s.M, s.dump != nullptr, s.qbias);
         switch (np / 32) {
         case 1: return launch_screen32_ks<2>(s, shape, st);
         case 2: return launch_screen32_ks<4>(s, shape, st);

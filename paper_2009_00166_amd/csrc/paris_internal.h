@@ -231,6 +231,7 @@ struct ScreenArgs {
     long long N;
     const uint16_t* Qb;    // [M][np] bfloat16 queries
     BQuery* bq;
+    uint16_t* qbias;       // [M][16] bfloat16 bias row of every query (written by launch_screen)
     int M;
     uint2* cand;           // (query, series)
     float* cand_d2;        // per candidate: the screen's accumulator, truncated (re-score input)
@@ -379,6 +380,7 @@ struct ScanShape {
 };
 
 hipError_t launch_reset(const QueryArgs& a, hipStream_t st);
+hipError_t launch_scan_again(const QueryArgs& a, hipStream_t st);
 hipError_t launch_touch(const void* p, size_t bytes, uint32_t* sink, hipStream_t st);
 // query summaries, tables, window, and the lower-bound-guided approximate-search seed
 hipError_t launch_prepare_seed(const QueryArgs& a, const float* q, hipStream_t st);

@@ -88,6 +88,19 @@ hipError_t launch_reset(const QueryArgs& a, hipStream_t st)
     return hipGetLastError();
 }
 
+// Before the lower-bound scan of the same query runs again: its survivor and first-pass counts
+// start from zero (its other outputs, head_key and seed_key, come out the same every run).
+__global__ void k_scan_again(QState* qs)
+{
+    if (threadIdx.x == 0) qs->n_surv = qs->n_coarse = 0;
+}
+
+hipError_t launch_scan_again(const QueryArgs& a, hipStream_t st)
+{
+    k_scan_again<<<1, 64, 0, st>>>(a.qs);
+    return hipGetLastError();
+}
+
 // ------------------------------------------------------------------------------------------
 // exact k-NN: the k best (distance, index) keys found so far, in k slots of global memory.
 // The slots hold distinct series (kBsfInit, whose index is never a series', marks an empty
