@@ -263,13 +263,21 @@ __global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* 
         s_k64 = k;
         s_root = (uint32_t)(k >> 48);
     }
-    for (int e = tid; e < kSeg * kSym; e += 256) {
-        const int s = e >> 8, c = e & 255;
-        const double x = qpaa[s], lo = beta[c], hi = beta[c + 1];
-        double d = 0.0;
-        if (x < lo) d = lo - x;          // query mean BELOW the region
-        else if (x > hi) d = x - hi;     // ABOVE the region
-        t8[e] = __double2float_rz((double)L * (d * d));
+    {
+        // thread tid owns symbol c = tid of every segment: its region's breakpoints are read
+        // once, the 16 means all at once. The distance from the mean to the region, branch-free:
+        // max(lo - x, 0) + max(x - hi, 0) is lo - x below the region, x - hi above it and 0
+        // inside (one term is positive at most; the end regions' infinite breakpoints give 0)
+        const int c = tid;
+        const double lo = beta[c], hi = beta[c + 1];
+        double xs[kSeg];
+#pragma unroll
+        for (int s = 0; s < kSeg; ++s) xs[s] = qpaa[s];
+#pragma unroll
+        for (int s = 0; s < kSeg; ++s) {
+            const double d = fmax(lo - xs[s], 0.0) + fmax(xs[s] - hi, 0.0);
+            t8[s * kSym + c] = __double2float_rz((double)L * (d * d));
+        }
     }
     __syncthreads();
     if (batch && blockIdx.x == 0) {
@@ -309,12 +317,19 @@ __global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* 
         // (the term of the region of cardinality 4, never above a member's fine term); entry
         // (j, b) = (T2[4j][b0] + T2[4j+1][b1]) + (T2[4j+2][b2] + T2[4j+3][b3]), b = b0 + 4 b1 +
         // 16 b2 + 64 b3 (the first half of the fine bound's summation tree)
+        // The fine entries are rounded values of L d^2 with d the distance from the query mean
+        // to the symbol's region; rounding and squaring are monotone and the 64 regions of a
+        // cardinality-4 symbol are adjacent, so their smallest entry is the rounded L d^2 of the
+        // distance to the union [beta(64 c), beta(64 c + 64)] (the same double expression as the
+        // fine entry of the end region nearest the mean, or 0 inside): the minimum, exactly.
         __shared__ float t2[kSeg * 4];
         if (tid < kSeg * 4) {
-            const float* p = t8 + (tid >> 2) * kSym + (tid & 3) * 64;
-            float m = p[0];
-            for (int k = 1; k < 64; ++k) m = fminf(m, p[k]);
-            t2[tid] = m;
+            const int sg = tid >> 2, c = tid & 3;
+            const double x = qpaa[sg], lo = beta[64 * c], hi = beta[64 * c + 64];
+            double d = 0.0;
+            if (x < lo) d = lo - x;
+            else if (x > hi) d = x - hi;
+            t2[tid] = __double2float_rz((double)L * (d * d));
         }
         __syncthreads();
         for (int e = tid; e < kGroups * kGroupCodes; e += 256) {
@@ -744,27 +759,38 @@ __global__ __launch_bounds__(BS) void k_lbscan(QueryArgs A, float fixed_thr)
                 idx[k] = e < count ? cbuf[e] : 0xFFFFFFFFu;
                 w[k] = idx[k] != 0xFFFFFFFFu ? sax[idx[k]] : make_uint4(0u, 0u, 0u, 0u);
             }
-            unsigned long long mhead = ~0ull;
+            // the wave's survivors of the kE series per lane: one ballot per k, one LDS atomic
+            // for all of them, ranks from mbcnt (at most kPass appends per step, onto at most
+            // kSurv - kPass staged)
+            float lb8[kE];
+            bool pass[kE];
+            unsigned long long m[kE];
+            uint32_t tot = 0;
 #pragma unroll
             for (int k = 0; k < kE; ++k) {
-                const float lb8 = fine_lb(w[k], t8);
-                const bool pass = idx[k] != 0xFFFFFFFFu && lb8 <= thr;
-                const unsigned long long m = __ballot(pass);
-                if (m) {   // at most kPass appends per step, onto at most kSurv - kPass staged
-                    const uint32_t rank = __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                                    __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                    const int leader = __ffsll((long long)m) - 1;
-                    uint32_t bp = 0;
-                    if (lane == leader) bp = atomicAdd(&scount, (uint32_t)__popcll(m));
-                    bp = __shfl(bp, leader);
-                    if (pass) {
-                        sbuf[bp + rank] = make_uint2(idx[k], __float_as_uint(lb8));
-                        const unsigned long long hk = pack_key(lb8, idx[k]);
+                lb8[k] = fine_lb(w[k], t8);
+                pass[k] = idx[k] != 0xFFFFFFFFu && lb8[k] <= thr;
+                m[k] = __ballot(pass[k]);
+                tot += (uint32_t)__popcll(m[k]);
+            }
+            if (tot) {   // uniform
+                uint32_t bp = 0;
+                if (lane == 0) bp = atomicAdd(&scount, tot);
+                bp = __shfl(bp, 0);
+                unsigned long long mhead = ~0ull;
+#pragma unroll
+                for (int k = 0; k < kE; ++k) {
+                    if (pass[k]) {
+                        const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                            (uint32_t)(m[k] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m[k], 0u));
+                        sbuf[bp + rank] = make_uint2(idx[k], __float_as_uint(lb8[k]));
+                        const unsigned long long hk = pack_key(lb8[k], idx[k]);
                         mhead = hk < mhead ? hk : mhead;
                     }
+                    bp += (uint32_t)__popcll(m[k]);
                 }
+                if (mhead != ~0ull) atomicMin(&shead, mhead);
             }
-            if (mhead != ~0ull) atomicMin(&shead, mhead);
             __syncthreads();
             if (scount > (uint32_t)(kSurv - kPass)) flush();   // uniform
         }
@@ -791,22 +817,30 @@ __global__ __launch_bounds__(BS) void k_lbscan(QueryArgs A, float fixed_thr)
             float c[4];
 #pragma unroll
             for (int k = 0; k < 4; ++k) c[k] = coarse4(word_at(cur[u], k), tc);   // 16 reads in flight
+            // the wave's passers of this load: one ballot per series of the 4, one LDS atomic
+            // for all of them, ranks from mbcnt (at most 4 BS U appends per step: the staging
+            // holds kCap)
             bool pass[4];
+            unsigned long long m[4];
+            uint32_t tot = 0;
 #pragma unroll
-            for (int k = 0; k < 4; ++k) pass[k] = (c[k] <= thr) & (k < lim);
-            if (__ballot(pass[0] | pass[1] | pass[2] | pass[3])) {
+            for (int k = 0; k < 4; ++k) {
+                pass[k] = (c[k] <= thr) & (k < lim);
+                m[k] = __ballot(pass[k]);
+                tot += (uint32_t)__popcll(m[k]);
+            }
+            if (tot) {   // uniform
+                uint32_t bp = 0;
+                if (lane == 0) bp = atomicAdd(&ccount, tot);
+                bp = __shfl(bp, 0);
 #pragma unroll
                 for (int k = 0; k < 4; ++k) {
-                    const unsigned long long m = __ballot(pass[k]);
-                    if (m) {   // at most 4 BS U appends per step: the staging holds kCap
+                    if (pass[k]) {
                         const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
-                            (uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-                        const int leader = __ffsll((long long)m) - 1;
-                        uint32_t bp = 0;
-                        if (lane == leader) bp = atomicAdd(&ccount, (uint32_t)__popcll(m));
-                        bp = __shfl(bp, leader);
-                        if (pass[k]) cbuf[bp + rank] = (uint32_t)(i0 + k);
+                            (uint32_t)(m[k] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m[k], 0u));
+                        cbuf[bp + rank] = (uint32_t)(i0 + k);
                     }
+                    bp += (uint32_t)__popcll(m[k]);
                 }
             }
         }
