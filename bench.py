@@ -171,8 +171,11 @@ def bsf_sharing_ablation(index, X, n: int, count: int = 200):
         ms, k = index.timing()
         index.set_timing(False)
         ref_ms = ms[2] / max(k, 1)
-        row_bytes = 4 * n            # a refined row is read in 1 KiB pieces: the whole row at n <= 256
+        # a refined row's first 64 points (256 B) are read with it; the rest only when those did
+        # not abandon it: refined x 4n bounds the bytes from above, refined x 256 B from below
+        row_bytes = 4 * n
         read = mean("refined") * row_bytes
+        read_lo = mean("refined") * min(row_bytes, 256)
         return {"queries_per_s": qps, "mean_lb_survivors": mean("lb_survivors"),
                 "mean_refined": mean("refined"), "mean_abandoned": mean("abandoned"),
                 "mean_bsf_updates": mean("bsf_updates"),
@@ -181,9 +184,11 @@ def bsf_sharing_ablation(index, X, n: int, count: int = 200):
                                     "bytes_per_launch": read, "avg_launch_ms": ref_ms,
                                     "achieved": read / (ref_ms * 1e-3) / 1e9, "peak": HBM_PEAK_GBPS,
                                     "unit": "GB/s", "frac": read / (ref_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
-                                    "note": "bytes = refined rows x 4n (rows are loaded whole for n <= 256, "
-                                            "abandoned or not); time from events recorded around the "
-                                            "refine + resolve launch (includes its dispatch gap)"}}, got
+                                    "note": "bytes = refined rows x 4n, an upper bound (a row abandoned within its first "
+                                            "64 points reads 256 B: bytes_lower_bound); time from events recorded "
+                                            "around the refine + resolve launch (includes its dispatch gap)",
+                                    "bytes_lower_bound": read_lo,
+                                    "achieved_lower_bound": read_lo / (ref_ms * 1e-3) / 1e9}}, got
 
     # alternate the modes twice and keep each one's faster pass, so neither gains from going last
     res = {True: [], False: []}
