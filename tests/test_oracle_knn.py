@@ -8,6 +8,7 @@ from scipy.spatial.distance import cdist
 
 import synth
 from oracle import exact_search, exact_search_knn, isax, knn_bruteforce, nn_bruteforce, paa
+from oracle.reference import lower_bound_sq, query_summary, seed_window, sorted_order
 
 
 def test_definition_against_library():
@@ -52,3 +53,33 @@ def test_ties_and_k_beyond_n():
     idx, d2, _ = exact_search_knn(q, small, 12, isax(paa(small)), seed_cap=16)
     ri, rd = knn_bruteforce(q, small, 12)
     assert len(idx) == 7 and np.array_equal(idx, ri) and np.array_equal(d2, rd)
+
+
+@pytest.mark.parametrize("k", [5, 20])
+def test_twin_refines_between_its_pruning_bounds(k):
+    """The twin's pruning against bounds computed without it: every series outside the seed window
+    whose lower bound is at most the final k-th distance must be refined (the threshold never
+    drops below it), and none whose bound exceeds the k-th distance among the window's members
+    (the threshold never rises above it); on this workload the second bound is well below the
+    series outside the window, so a twin that does not prune fails it."""
+    X = synth.random_walks(3000, 128, seed=27)
+    S = isax(paa(X))
+    L = 128 // 16
+    Qn, _, _ = synth.noisy_queries(X, 3, seed=28, sigma=0.2)
+    perm, keys = sorted_order(S)
+    for q in Qn:
+        idx, d2, refined = exact_search_knn(q, X, k, S, mode="equal_count", seed_cap=64, n_leaves=32)
+        ri, rd = knn_bruteforce(q, X, k)
+        assert np.array_equal(idx, ri) and np.array_equal(d2, rd)
+        qs = query_summary(q)
+        a, b = seed_window(qs, keys, L, "equal_count", 64, 32)
+        members = np.sort(perm[a:b])
+        assert len(members) >= k
+        outside = np.ones(len(X), bool)
+        outside[members] = False
+        lb = lower_bound_sq(qs.paa[None, :], S, L)
+        first_kth = float(knn_bruteforce(q, X[members], k)[1][-1])
+        lo = int(np.sum(outside & (lb <= float(rd[-1]))))
+        hi = int(np.sum(outside & (lb <= first_kth * (1.0 + 1e-9) + 1e-12)))
+        assert lo <= refined <= hi
+        assert hi < int(outside.sum()) // 2
