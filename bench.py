@@ -498,6 +498,7 @@ def main() -> int:
                      "achieved_cold": cold["achieved_GBps"] if cold else None,
                      "frac_cold": cold["frac"] if cold else None,
                      "single_pass_equivalent_GBps": single_pass_GBps,
+                     "single_pass_equivalent_frac": single_pass_GBps / HBM_PEAK_GBPS,
                      # the committed counter summary covers the 10M x 256 launch only
                      "traffic": measured_traffic("k_lbscan") if (N, n) == (10_000_000, 256) else None,
                      "bytes_per_launch": lb_bytes, "avg_launch_ms": lb_ms,
@@ -865,6 +866,7 @@ def multi_section(args):
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": gbps / HBM_PEAK_GBPS, "traffic": None,
                      "bytes_per_launch": lb_bytes, "avg_launch_ms": lb_ms,
                      "single_pass_equivalent_GBps": SAX_BYTES_PER_SERIES * specs[0][0] / (lb_ms * 1e-3) / 1e9,
+                     "single_pass_equivalent_frac": SAX_BYTES_PER_SERIES * specs[0][0] / (lb_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
                      "note": "bytes = 4 B per series (cardinality-4 word) + 16 B per first-pass passer + 8 B "
                              "per survivor, means over the 200 timed queries"},
         "screen_survivors_per_query": st["lb_survivors"] / B, "fallback_queries": st["resolved"],
