@@ -311,7 +311,11 @@ __global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* 
         }
         __syncthreads();
     }
-    if (!batch && blockIdx.x == 0) {
+    // per-query path: the launch has one block more than chunks; that last block publishes the
+    // scan's tables and the query's summary and does no seed work, so that the publishing is off
+    // the critical path of the chunk blocks
+    const bool publisher = !batch && blockIdx.x == gridDim.x - 1;
+    if (publisher) {
         for (int e = tid; e < kSeg * kSym; e += 256) A.t8[e] = t8[e];
         // coarse tables: T2[s][c] = min of the 64 fine entries whose symbol's top 2 bits are c
         // (the term of the region of cardinality 4, never above a member's fine term); entry
@@ -341,6 +345,7 @@ __global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* 
             A.qs->paa[tid] = qpaa[tid];
             A.qs->sym[tid] = (uint8_t)qsym[tid];
         }
+        return;   // uniform: the whole block
     }
 
     // approximate-search window (sorted positions), numbered in chunks of kSeedChunk positions
@@ -547,7 +552,7 @@ __global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* 
             // the previous round's, their distances offered to the k best slots. r spreads the
             // knn_r * k seed distances over the window's chunks (knn_r: seeds per answer); the
             // learned seed's chunk count comes from the host.
-            long long nch = learned ? (long long)gridDim.x : (hi - lo + kSeedChunk - 1) / kSeedChunk;
+            long long nch = learned ? (long long)gridDim.x - 1 : (hi - lo + kSeedChunk - 1) / kSeedChunk;
             if (nch < 1) nch = 1;
             long long r = ((long long)A.knn_r * A.knn_k + nch - 1) / nch;
             if (r > kSeedBatchChunks) r = kSeedBatchChunks;
@@ -654,7 +659,7 @@ int seed_grid(const QueryArgs& a)
 hipError_t launch_prepare_seed(const QueryArgs& a, const float* q, hipStream_t st)
 {
     SeedBatch none{nullptr, nullptr, nullptr, 0, 1, nullptr, nullptr, 0};
-    k_prepare_seed<<<seed_grid(a), 256, (size_t)a.n * sizeof(float), st>>>(a, q, none);
+    k_prepare_seed<<<seed_grid(a) + 1, 256, (size_t)a.n * sizeof(float), st>>>(a, q, none);
     return hipGetLastError();
 }
 
