@@ -36,7 +36,8 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBPS = 8000.0   # MI355X HBM3E peak (8 TB/s)
 SAX_BYTES_PER_SERIES = 16
-COARSE_BYTES_PER_SERIES = 4   # the word at cardinality 4, read by the scan's first pass
+ENV_BYTES_PER_SERIES = 1      # a run's symbol envelope (32 B per 32 series), read by the scan's run pass
+SURVIVOR_BYTES = 12           # a survivor's series index (perm, 4 B) and its list entry (8 B)
 
 
 def log(msg: str) -> None:
@@ -462,10 +463,11 @@ def main() -> int:
     total_q = M * args.steps
     args._plain_qps = total_q / elapsed
     lb_ms = scan_ms[1] / max(timed, 1)
-    # algorithmic bytes of a scan launch: the cardinality-4 word of every series (4 B), the 8-bit
-    # word of every series passing the first pass (16 B) and every survivor's entry (8 B)
-    lb_bytes = (COARSE_BYTES_PER_SERIES * N + SAX_BYTES_PER_SERIES * mean("coarse_passed")
-                + 8 * mean("lb_survivors"))
+    # algorithmic bytes of a scan launch: the symbol envelope of every run of 32 series (1 B per
+    # series), the 8-bit word of every series of the runs that pass (16 B) and every survivor's
+    # series index and entry (12 B)
+    lb_bytes = (ENV_BYTES_PER_SERIES * N + SAX_BYTES_PER_SERIES * mean("words_read")
+                + SURVIVOR_BYTES * mean("lb_survivors"))
     achieved = lb_bytes / (lb_ms * 1e-3) / 1e9
     single_pass_GBps = SAX_BYTES_PER_SERIES * N / (lb_ms * 1e-3) / 1e9
     if cold:
@@ -494,7 +496,7 @@ def main() -> int:
         "roofline": {"bound": "hbm", "kernel": "k_lbscan", "achieved": achieved,
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
                      "launch_shape": scan_shape,
-                     "cache_resident": bool(COARSE_BYTES_PER_SERIES * N < 256e6),
+                     "cache_resident": bool(ENV_BYTES_PER_SERIES * N < 256e6),
                      "achieved_cold": cold["achieved_GBps"] if cold else None,
                      "frac_cold": cold["frac"] if cold else None,
                      "single_pass_equivalent_GBps": single_pass_GBps,
@@ -502,22 +504,22 @@ def main() -> int:
                      # the committed counter summary covers the 10M x 256 launch only
                      "traffic": measured_traffic("k_lbscan") if (N, n) == (10_000_000, 256) else None,
                      "bytes_per_launch": lb_bytes, "avg_launch_ms": lb_ms,
-                     "note": "bytes per launch = 4 B per series (the iSAX word at cardinality 4 read by the "
-                             "first pass) + 16 B per series passing it (its 8-bit word) + 8 B per survivor, "
-                             "the means over 200 queries; avg_launch_ms from HIP start/stop events bound to "
-                             "the scan kernel's dispatch (every 8th query of the timed region); "
-                             "single_pass_equivalent_GBps = 16 B per series / that time (the rate a single pass "
-                             f"over the 8-bit words would need); the {COARSE_BYTES_PER_SERIES * N / 1e6:g} MB "
-                             "array of cardinality-4 words "
-                             + ("fits the 256 MB Infinity Cache (achieved_cold / frac_cold: the same kernel after "
-                                "a 1 GiB read-only sweep before every query)" if COARSE_BYTES_PER_SERIES * N < 256e6
-                                else "exceeds the 256 MB Infinity Cache (streamed from HBM)")},
+                     "note": "bytes per launch = 1 B per series (the symbol envelopes of the runs of 32 "
+                             "leaf-order series, read by the run pass) + 16 B per series of the runs that pass "
+                             "(its 8-bit word) + 12 B per survivor (series index and list entry), the means over "
+                             "200 queries; avg_launch_ms from HIP start/stop events bound to the scan kernel's "
+                             "dispatch (every 8th query of the timed region); single_pass_equivalent_GBps = 16 B "
+                             "per series / that time (the rate a scan of every 8-bit word would need); the "
+                             f"{ENV_BYTES_PER_SERIES * N / 1e6:g} MB of envelopes "
+                             + ("fit the 256 MB Infinity Cache (achieved_cold / frac_cold: the same kernel after "
+                                "a 1 GiB read-only sweep before every query)" if ENV_BYTES_PER_SERIES * N < 256e6
+                                else "exceed the 256 MB Infinity Cache (streamed from HBM)")},
         "lbscan_cold": cold,
         "phases_ms_per_query": dict(zip(["prepare_seed", "lbscan", "refine_resolve"],
                                         [p / max(phased, 1) for p in phase_ms])),
         "build_ms": build_s * 1e3,
         "build_GBps_raw": X.nbytes / build_s / 1e9,
-        "mean_counters": {k: mean(k) for k in ("coarse_passed", "lb_survivors", "refined", "abandoned",
+        "mean_counters": {k: mean(k) for k in ("words_read", "lb_survivors", "refined", "abandoned",
                                                "bsf_updates", "resolved")},
         "answers_match_source_frac": None if src is None else float(np.mean(answers == src)),
         "bsf_sharing_ablation": nb,
@@ -849,8 +851,8 @@ def multi_section(args):
     ix0.set_timing(False)
     st0 = [ix0.query(r, with_stats=True)[2] for r in rows]
     lb_ms = scan_ms[1] / max(timed, 1)
-    lb_bytes = (COARSE_BYTES_PER_SERIES * specs[0][0] + SAX_BYTES_PER_SERIES * np.mean([x["coarse_passed"] for x in st0])
-                + 8 * np.mean([x["lb_survivors"] for x in st0]))
+    lb_bytes = (ENV_BYTES_PER_SERIES * specs[0][0] + SAX_BYTES_PER_SERIES * np.mean([x["words_read"] for x in st0])
+                + SURVIVOR_BYTES * np.mean([x["lb_survivors"] for x in st0]))
     gbps = lb_bytes / (lb_ms * 1e-3) / 1e9
     rec = {
         "metric": "exact 1-NN queries/s, mixed batches over 100M x 128 + 20M x 512 + 5M x 1024 fp32",
@@ -867,8 +869,8 @@ def multi_section(args):
                      "bytes_per_launch": lb_bytes, "avg_launch_ms": lb_ms,
                      "single_pass_equivalent_GBps": SAX_BYTES_PER_SERIES * specs[0][0] / (lb_ms * 1e-3) / 1e9,
                      "single_pass_equivalent_frac": SAX_BYTES_PER_SERIES * specs[0][0] / (lb_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
-                     "note": "bytes = 4 B per series (cardinality-4 word) + 16 B per first-pass passer + 8 B "
-                             "per survivor, means over the 200 timed queries"},
+                     "note": "bytes = 1 B per series (run envelopes) + 16 B per series of the runs that pass + "
+                             "12 B per survivor, means over the 200 timed queries"},
         "screen_survivors_per_query": st["lb_survivors"] / B, "fallback_queries": st["resolved"],
     }
     if not args.no_cpu_baseline:

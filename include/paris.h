@@ -7,12 +7,13 @@
  * only the best-so-far distance (Section 3.3.3); these calls return the index and the distance.
  *
  * Method: every series is summarised once (paris_build) into a 16-segment, 8-bit iSAX word
- * (Section 2.2: PAA segment means quantised against 255 Gaussian boundaries), also kept at
- * cardinality 4 (its symbols' 2-bit prefixes, 4 bytes per series). A query (paris_query_exact)
- * takes an approximate-search seed as its first best-so-far distance (Section 3.3), scans the
- * whole array of words with the iSAX lower bound (first on the cardinality-4 words, then on the
- * full words of the series that pass) and keeps the series the bound cannot prune (the LBC
- * workers of Section 3.3.3), computes real distances of the
+ * (Section 2.2: PAA segment means quantised against 255 Gaussian boundaries); the words are also
+ * kept in leaf order with the symbol envelope (per-segment smallest and largest symbol) of every
+ * run of 32 consecutive positions. A query (paris_query_exact) takes an approximate-search seed
+ * as its first best-so-far distance (Section 3.3), scans the collection with the iSAX lower bound
+ * (every run's bound over its envelope first, then the words of the series of the runs it does
+ * not prune) and keeps the series the bound cannot prune (the LBC workers of Section 3.3.3),
+ * computes real distances of the
  * survivors with early abandoning while an atomic minimum tightens the best-so-far (the RDC
  * workers), and resolves the final comparison in float64.
  *
@@ -84,8 +85,8 @@ typedef struct paris_stats {
     int64_t seed_index;    /* series found by the approximate search (-1 if none)            */
     double  seed_dist;     /* its float32-computed distance (+inf if none)                   */
     int64_t seed_lo, seed_hi;  /* sorted-position window examined by the approximate search  */
-    int64_t coarse_passed;     /* series whose bound on the words at cardinality 4 passed the
-                                  scan's first pass (their 8-bit words were then read)        */
+    int64_t words_read;        /* series whose 8-bit words the scan read: the series of the
+                                  runs whose envelope bound did not prune them                */
 } paris_stats;
 
 typedef struct paris_index paris_index;  /* opaque, library-owned host handle */
@@ -285,8 +286,7 @@ paris_status paris_query_batch_multi(paris_index *const *idx, int32_t n_idx, con
  * (1 .. 65536): a bfloat16 copy of the collection in leaf order (np = the screened dimensions
  * rounded up to 32; stored in MFMA fragment order, ceil(N / 32) blocks of 32 rows x np), its norms, the query buffers, per-query states, per-query
  * bias rows of the screen (32 bytes each), a candidate list of min(4096 * max_batch, 2^32 - 16) entries (12 bytes each: query, series, float32
- * re-scored distance), per-query learned-seed leaves and PAA, the symbol envelope of every
- * run of 32 sorted positions (32 bytes) and the block bound's alive bits
+ * re-scored distance), per-query learned-seed leaves and PAA and the block bound's alive bits
  * (ceil(N / 128) * ceil(max_batch / 64) words of 8 bytes).
  * paris_batch_attach borrows that device memory (256-byte aligned) for the life of the handle
  * (or until the next attach), converts the collection, times the screen's tile shapes (on a
@@ -336,16 +336,10 @@ paris_status paris_block_bound_bits(paris_index *idx, const float *queries_dev, 
  *   info          host out (may be NULL).
  *   table_dev     optional device out float32 [16][256]: per-segment lower-bound terms
  *                 L * delta(q_s, c)^2, rounded toward zero (so their sum never exceeds the bound).
- *   coarse_dev    optional device out float32 [4][256]: the coarse tables of the scan's first
- *                 pass over the words at cardinality 4 (Section 2.2: a symbol's 2-bit prefix is
- *                 its symbol at cardinality 4). With T2[s][c] the minimum of the 64 entries
- *                 64c .. 64c+63 of table_dev's row s, entry (j, b) is
- *                 (T2[4j][b0] + T2[4j+1][b1]) + (T2[4j+2][b2] + T2[4j+3][b3]) in float32, where
- *                 b = b0 + 4 b1 + 16 b2 + 64 b3.
  * Synchronous.
  */
 paris_status paris_query_info_get(paris_index *idx, const float *query_dev, paris_query_info *info,
-                                  float *table_dev, float *coarse_dev, void *hip_stream);
+                                  float *table_dev, void *hip_stream);
 
 /*
  * The lower-bound scan alone (Section 3.3.3, LBC worker) against a caller-given threshold on

@@ -18,6 +18,6 @@ from .reference import (  # noqa: F401
     paa, isax, root_key, k64, lower_bound_sq, ed_sq, nn_bruteforce, sorted_order,
     root_offsets, equal_count_bounds, seed_window, exact_search, exact_search_nb, ExactStats, query_summary,
     knn_bruteforce, exact_search_knn,
-    lb_table, lb_coarse_table, approximate_seed, approximate_seed_k, block_lower_bound_sq, seed_members,
+    lb_table, approximate_seed, approximate_seed_k, block_lower_bound_sq, seed_members,
 )
 from .ads import AdsTree, ads_query_leaf, ads_tree, next_bit  # noqa: F401

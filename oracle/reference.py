@@ -168,13 +168,6 @@ def lb_table(qpaa: np.ndarray, L: int, bits: int = 8) -> np.ndarray:
     return np.float64(L) * (d * d)
 
 
-def lb_coarse_table(qpaa: np.ndarray, L: int) -> np.ndarray:
-    """float64[w][32]: ``lb_table`` at cardinality 32 (5 bits): the region of a 5-bit symbol is
-    the union of the eight 8-bit regions sharing its prefix, so each entry is the minimum of the
-    eight 8-bit entries and the coarse sum is a weaker but still valid lower bound."""
-    return lb_table(qpaa, L, bits=5)
-
-
 def ed_sq(q: np.ndarray, X: np.ndarray) -> np.ndarray:
     """Squared Euclidean distance (Section 2.1), float64, fixed operation order.
 

@@ -256,17 +256,16 @@ class Index:
         torch = _torch()
         qp = _dev_ptr(q, torch.float32, 1, "query")
         info = ParisQueryInfo()
-        t8 = t5 = None
+        t8 = None
         if tables:
             t8 = torch.empty((16, 256), dtype=torch.float32, device=q.device)
-            t5 = torch.empty((4, 256), dtype=torch.float32, device=q.device)
         check(load_library().paris_query_info_get(
             self._h, qp, ctypes.byref(info), ctypes.c_void_p(t8.data_ptr()) if tables else None,
-            ctypes.c_void_p(t5.data_ptr()) if tables else None, _stream_ptr(stream)), "paris_query_info_get")
+            _stream_ptr(stream)), "paris_query_info_get")
         d = {"paa": list(info.paa), "sym": list(info.sym), "root": int(info.root), "k64": int(info.k64),
              "win_lo": int(info.win_lo), "win_hi": int(info.win_hi)}
         if tables:
-            d["table"], d["coarse"] = t8, t5
+            d["table"] = t8
         return d
 
     def lb_scan(self, q, threshold_sq: float, capacity: int | None = None, stream=None):

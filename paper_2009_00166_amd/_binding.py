@@ -24,7 +24,7 @@ class ParisStats(ctypes.Structure):
                 ("abandoned", ctypes.c_int64), ("bsf_updates", ctypes.c_int64),
                 ("resolved", ctypes.c_int64), ("seed_index", ctypes.c_int64),
                 ("seed_dist", ctypes.c_double), ("seed_lo", ctypes.c_int64),
-                ("seed_hi", ctypes.c_int64), ("coarse_passed", ctypes.c_int64)]
+                ("seed_hi", ctypes.c_int64), ("words_read", ctypes.c_int64)]
 
     def as_dict(self) -> dict:
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -71,7 +71,7 @@ SIGNATURES = [
                                                  ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ParisStats), _P]),
     ("paris_query_batch", ctypes.c_int, [_P, _P, _I64, _P, _P, ctypes.POINTER(ParisStats), _P]),
     ("paris_query_batch_multi", ctypes.c_int, [_P, _I32, _P, _P, _P, _P, ctypes.POINTER(ParisStats), _P]),
-    ("paris_query_info_get", ctypes.c_int, [_P, _P, ctypes.POINTER(ParisQueryInfo), _P, _P, _P]),
+    ("paris_query_info_get", ctypes.c_int, [_P, _P, ctypes.POINTER(ParisQueryInfo), _P, _P]),
     ("paris_lb_scan", ctypes.c_int, [_P, _P, _F32, _P, _P, _I64, ctypes.POINTER(ctypes.c_int64), _P]),
     ("paris_batch_workspace_size", ctypes.c_int, [_P, _I32, ctypes.POINTER(ctypes.c_size_t)]),
     ("paris_batch_attach", ctypes.c_int, [_P, _P, ctypes.c_size_t, _I32, _P]),

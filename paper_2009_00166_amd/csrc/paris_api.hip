@@ -22,8 +22,8 @@ using namespace paris;
 namespace {
 
 constexpr uint32_t kMagic = 0x50415249u;  // "PARI"
-// launch shapes of the lower-bound scan: (threads, blocks per CU, 16-byte loads of 4 coarse
-// words per lane in flight)
+// launch shapes of the lower-bound scan: (threads, blocks per CU, run envelopes per thread in
+// flight)
 constexpr int kScanCands = 8;
 constexpr ScanShape kScanCandidates[kScanCands] = {{512, 2, 1}, {512, 2, 2}, {512, 4, 1}, {512, 1, 4},
                                                    {256, 4, 1}, {256, 4, 2}, {256, 8, 1}, {256, 3, 4}};
@@ -38,7 +38,7 @@ size_t align_up(size_t v) { return (v + kAlign - 1) & ~(kAlign - 1); }
 // Workspace layout. The radix-sort scratch (alternate keys / positions / histograms) is only
 // needed during the build and aliases the survivor and completed-candidate buffers.
 struct Plan {
-    size_t hdr, sax, saxs, csax, keys, perm, roff, qs, t8, tc, knn, surv, done, total;
+    size_t hdr, sax, saxs, env, keys, perm, roff, qs, t8, knn, surv, done, total;
     size_t keys_alt, perm_alt, hist;
     // ADS+ tree (leaf mode 2): nodes, and the scratch of a build round (todo ids, chunk starts,
     // splits; chunks, their counts and destinations); 0 otherwise
@@ -64,13 +64,12 @@ void make_plan(long long N, Plan* p, const paris_config* cfg)
     p->hdr = take(256);
     p->sax = take((size_t)N * 16);
     p->saxs = take((size_t)N * 16);
-    p->csax = take((size_t)(N + 3) / 4 * 16);
+    p->env = take((size_t)(N + kEnvRun - 1) / kEnvRun * 32);
     p->keys = take((size_t)N * 8);
     p->perm = take((size_t)N * 4);
     p->roff = take(65537 * 4);
     p->qs = take(sizeof(QState));
     p->t8 = take(kSeg * kSym * 4);
-    p->tc = take(kGroups * kGroupCodes * 4);
     p->knn = take(kKnnMax * 8);
     p->surv = take((size_t)N * 8);
     // every survivor completes at most once, plus the head survivor computed first (it is also
@@ -233,7 +232,7 @@ struct paris_index {
     int proj;   // segment length of the screen's projection (1: n <= 256, the series itself)
     bool screen_ok;
     struct {
-        size_t hdr, xb, xn, qin, qb, bq, qbias, cand, cand_d2, oidx, odist, fb, leaves, env, qpaa, mask, total;
+        size_t hdr, xb, xn, qin, qb, bq, qbias, cand, cand_d2, oidx, odist, fb, leaves, qpaa, mask, total;
         uint32_t cand_cap;
     } bp;
     ScreenShape screen;
@@ -268,7 +267,7 @@ QueryArgs args_for(const paris_index* h)
     a.n = h->n;
     a.sax = ws + h->plan.sax;
     a.saxs = ws + h->plan.saxs;
-    a.csax = reinterpret_cast<const uint32_t*>(ws + h->plan.csax);
+    a.env = ws + h->plan.env;
     a.keys = reinterpret_cast<const unsigned long long*>(ws + h->plan.keys);
     a.perm = reinterpret_cast<const uint32_t*>(ws + h->plan.perm);
     a.roff = reinterpret_cast<const uint32_t*>(ws + h->plan.roff);
@@ -277,7 +276,6 @@ QueryArgs args_for(const paris_index* h)
     a.seed_cap = h->cfg.seed_cap;
     a.qs = reinterpret_cast<QState*>(ws + h->plan.qs);
     a.t8 = reinterpret_cast<float*>(ws + h->plan.t8);
-    a.tc = reinterpret_cast<float*>(ws + h->plan.tc);
     a.surv = reinterpret_cast<uint2*>(ws + h->plan.surv);
     a.surv_cap = (uint32_t)h->N;
     a.done = reinterpret_cast<uint2*>(ws + h->plan.done);
@@ -461,7 +459,6 @@ paris_status build_tree(const Plan& plan, uint8_t* ws, long long N, int cap, hip
 struct QueryScratch {
     QState* qs;
     float* t8;
-    float* tc;
     uint2* surv;
     uint32_t surv_cap;
     uint2* done;
@@ -581,7 +578,6 @@ paris_status run_query(paris_index* h, const float* q, hipStream_t st, long long
     if (scratch_in) {
         a.qs = scratch_in->qs;
         a.t8 = scratch_in->t8;
-        a.tc = scratch_in->tc;
         a.surv = scratch_in->surv;
         a.surv_cap = scratch_in->surv_cap;
         a.done = scratch_in->done;
@@ -676,7 +672,7 @@ void fill_stats(const QResult& r, paris_stats* o)
     }
     o->seed_lo = r.win_lo;
     o->seed_hi = r.win_hi;
-    o->coarse_passed = r.n_coarse;
+    o->words_read = r.n_read;
 }
 
 // Launch-shape autotuner for the lower-bound scan: every candidate shape scans the whole SAX
@@ -695,7 +691,7 @@ paris_status tune_scan(paris_index* h, hipStream_t st)
             return PARIS_OK;
         }
     }
-    // (threads, blocks per CU, 16-byte loads of 4 coarse words per lane in flight)
+    // (threads, blocks per CU, run envelopes per thread in flight)
     const ScanShape* cands = kScanCandidates;
     const QueryArgs a = args_for(h);
     HIP_TRY(launch_prepare_seed(a, h->X, st));  // tables of series 0
@@ -767,7 +763,6 @@ void make_batch_plan(paris_index* h, int max_batch)
     h->bp.odist = take(M * 8);
     h->bp.fb = take(M * 4);
     h->bp.leaves = take(M * kTopLeaves * 4);
-    h->bp.env = take((N + kEnvRun - 1) / kEnvRun * 32);
     h->bp.qpaa = take(M * kSeg * 8);
     // alive bits for the smallest work item of the 32-wide screen (128 sorted positions)
     h->bp.mask = take((N + 127) / 128 * ((M + 63) / 64) * 8);
@@ -804,7 +799,7 @@ ScreenArgs screen_args(paris_index* h, int m, float* dump, bool masked = true)
     s.dump = dump;
     s.perm = reinterpret_cast<const uint32_t*>(h->ws + h->plan.perm);
     s.mask = masked && h->block_lb ? reinterpret_cast<unsigned long long*>(h->bws + h->bp.mask) : nullptr;
-    s.env = h->bws + h->bp.env;
+    s.env = h->ws + h->plan.env;
     s.qpaa = reinterpret_cast<const double*>(h->bws + h->bp.qpaa);
     s.seg_len = (double)(h->n / kSeg);
     s.seed_rel = h->seed_rel;
@@ -1166,7 +1161,7 @@ paris_status batch_core(paris_index* h, const float* queries_dev, long long n_qu
             agg->abandoned += one.abandoned;
             agg->bsf_updates += one.bsf_updates;
             agg->resolved += one.resolved;
-            agg->coarse_passed += one.coarse_passed;
+            agg->words_read += one.words_read;
         }
     }
     return PARIS_OK;
@@ -1218,7 +1213,6 @@ paris_status paris_batch_attach(paris_index* h, void* workspace_dev, size_t work
     if (launch_to_bf16(h->X, reinterpret_cast<const uint32_t*>(h->ws + h->plan.perm), h->N, h->n, h->np, h->proj,
                        reinterpret_cast<uint16_t*>(h->bws + h->bp.xb), reinterpret_cast<float*>(h->bws + h->bp.xn),
                        st) != hipSuccess ||
-        launch_block_env(h->ws + h->plan.saxs, h->N, h->bws + h->bp.env, st) != hipSuccess ||
         launch_xn_max(reinterpret_cast<const float*>(h->bws + h->bp.xn), h->N, bhdr(h), st) != hipSuccess)
         s = PARIS_EHIP;
     if (s == PARIS_OK) s = tune_screen(h, st);
@@ -1338,7 +1332,6 @@ paris_status paris_build(const float* series_dev, int64_t n_series, int32_t leng
     auto* perm = reinterpret_cast<uint32_t*>(ws + plan.perm);
     HIP_TRY(hipMemsetAsync(err, 0, 256, st));
     HIP_TRY(launch_summarise(series_dev, n_series, length, ws + plan.sax, keys, perm, err, st));
-    HIP_TRY(launch_coarse_words(ws + plan.sax, n_series, reinterpret_cast<uint32_t*>(ws + plan.csax), st));
     HIP_TRY(launch_sort_keys(keys, perm, reinterpret_cast<unsigned long long*>(ws + plan.keys_alt),
                              reinterpret_cast<uint32_t*>(ws + plan.perm_alt),
                              reinterpret_cast<uint32_t*>(ws + plan.hist), n_series, st));
@@ -1350,6 +1343,7 @@ paris_status paris_build(const float* series_dev, int64_t n_series, int32_t leng
         HIP_TRY(launch_tree_keys(ws + plan.sax, perm, n_series, keys, st));
     }
     HIP_TRY(launch_gather_sax(ws + plan.sax, perm, n_series, ws + plan.saxs, st));
+    HIP_TRY(launch_block_env(ws + plan.saxs, n_series, ws + plan.env, st));
     uint32_t herr = 0;
     HIP_TRY(hipMemcpyAsync(&herr, err, 4, hipMemcpyDeviceToHost, st));
     HIP_TRY(hipStreamSynchronize(st));
@@ -1635,8 +1629,7 @@ constexpr size_t kNaSurvCap = (size_t)PARIS_NOALLOC_MAX_SURVIVORS;
 constexpr size_t kNaDoneCap = (size_t)PARIS_NOALLOC_MAX_COMPLETED;
 constexpr size_t kNaQs = 0;
 constexpr size_t kNaT8 = na_align(kNaQs + sizeof(QState));
-constexpr size_t kNaTc = na_align(kNaT8 + (size_t)kSeg * kSym * 4);
-constexpr size_t kNaSurv = na_align(kNaTc + (size_t)kGroups * kGroupCodes * 4);
+constexpr size_t kNaSurv = na_align(kNaT8 + (size_t)kSeg * kSym * 4);
 constexpr size_t kNaDone = na_align(kNaSurv + kNaSurvCap * 8);
 constexpr size_t kNaBytes = na_align(kNaDone + kNaDoneCap * 8);
 static_assert(kNaBytes <= ((size_t)20 << 20), "the allocation-free scratch stays below 20 MiB");
@@ -1682,7 +1675,6 @@ paris_status paris_query_exact_noalloc(paris_index* h, const float* query_dev, i
     QueryScratch sc;
     sc.qs = reinterpret_cast<QState*>(base + kNaQs);
     sc.t8 = reinterpret_cast<float*>(base + kNaT8);
-    sc.tc = reinterpret_cast<float*>(base + kNaTc);
     sc.surv = reinterpret_cast<uint2*>(base + kNaSurv);
     sc.surv_cap = (uint32_t)kNaSurvCap;
     sc.done = reinterpret_cast<uint2*>(base + kNaDone);
@@ -1746,7 +1738,7 @@ paris_status paris_query_batch_multi(paris_index* const* idx, int32_t n_idx, con
 }
 
 paris_status paris_query_info_get(paris_index* h, const float* query_dev, paris_query_info* info, float* table_dev,
-                                  float* coarse_dev, void* hip_stream)
+                                  void* hip_stream)
 {
     if (!handle_ok(h)) return PARIS_ESTATE;
     if (!query_dev || reinterpret_cast<uintptr_t>(query_dev) % 16 != 0) return PARIS_EINVAL;
@@ -1754,8 +1746,6 @@ paris_status paris_query_info_get(paris_index* h, const float* query_dev, paris_
     const QueryArgs a = args_for(h);
     HIP_TRY(launch_prepare_seed(a, query_dev, st));
     if (table_dev) HIP_TRY(hipMemcpyAsync(table_dev, a.t8, kSeg * kSym * 4, hipMemcpyDeviceToDevice, st));
-    if (coarse_dev)
-        HIP_TRY(hipMemcpyAsync(coarse_dev, a.tc, kGroups * kGroupCodes * 4, hipMemcpyDeviceToDevice, st));
     HIP_TRY(hipMemcpyAsync(h->host_qs, a.qs, sizeof(QState), hipMemcpyDeviceToHost, st));
     HIP_TRY(launch_reset(a, st));
     HIP_TRY(hipStreamSynchronize(st));

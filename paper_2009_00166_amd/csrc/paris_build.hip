@@ -294,39 +294,6 @@ hipError_t launch_gather_sax(const uint8_t* sax, const uint32_t* perm, long long
     return hipGetLastError();
 }
 
-// The iSAX word at cardinality 4 (Section 2.2: a symbol's prefix is its symbol at a lower
-// cardinality): the top 2 bits of every 8-bit symbol, segment 4j + i in bits 2i .. 2i+1 of byte
-// j. The array is padded to a multiple of 4 series (padding words are 0 and never read as
-// series: the scan checks the index).
-__global__ __launch_bounds__(256) void k_coarse_words(const uint4* __restrict__ sax, long long N, long long NP,
-                                                      uint32_t* __restrict__ csax)
-{
-    for (long long i = (long long)blockIdx.x * 256 + threadIdx.x; i < NP; i += (long long)gridDim.x * 256) {
-        uint32_t c = 0;
-        if (i < N) {
-            const uint4 w = sax[i];
-            const uint32_t ws[4] = {w.x, w.y, w.z, w.w};
-#pragma unroll
-            for (int j = 0; j < 4; ++j) {
-                uint32_t b = 0;
-#pragma unroll
-                for (int k = 0; k < 4; ++k) b |= ((ws[j] >> (8 * k + 6)) & 3u) << (2 * k);
-                c |= b << (8 * j);
-            }
-        }
-        csax[i] = c;
-    }
-}
-
-hipError_t launch_coarse_words(const uint8_t* sax, long long N, uint32_t* csax, hipStream_t st)
-{
-    const long long NP = (N + 3) / 4 * 4;
-    long long blocks = (NP + 255) / 256;
-    if (blocks > 8192) blocks = 8192;
-    k_coarse_words<<<(unsigned)blocks, 256, 0, st>>>(reinterpret_cast<const uint4*>(sax), N, NP, csax);
-    return hipGetLastError();
-}
-
 hipError_t launch_root_offsets(const unsigned long long* keys, long long N, uint32_t* roff, hipStream_t st)
 {
     k_root_offsets<<<(65537 + 255) / 256, 256, 0, st>>>(keys, N, roff);

@@ -10,8 +10,6 @@ namespace paris {
 
 constexpr int kSeg = 16;           // w, segments per iSAX word
 constexpr int kSym = 256;          // 8-bit symbols
-constexpr int kGroups = 4;         // coarse tables: one per group of 4 consecutive segments
-constexpr int kGroupCodes = 256;   // 2 bits of each of the group's 4 segments
 constexpr int kMaxLength = 2048;   // longest series the summarise kernel stages in LDS
 constexpr int kSeedChunk = 512;    // sorted positions per seed block: its smallest bound is refined
 constexpr int kSeedBatchChunks = 32;  // seed chunks per block of the batched seed
@@ -52,7 +50,7 @@ struct QResult {
     unsigned long long seed_key;
     long long win_lo, win_hi;
     uint32_t n_surv, n_refined, n_abandon, n_bsf_upd, n_resolved, err;
-    uint32_t n_coarse;        // series whose cardinality-4 bound passed the scan's first pass
+    uint32_t n_read;          // series whose 8-bit words the scan read (runs it did not prune)
 };
 
 // Per-query device state. The last kernel of every query snapshots the result and leaves the
@@ -70,7 +68,7 @@ struct alignas(256) QState {
     unsigned long long bsf_key;
     unsigned long long seed_key;
     unsigned long long head_key;   // (fine bound bits, index) of the survivor with the smallest bound
-    uint32_t n_surv, n_refined, n_abandon, n_bsf_upd, n_done, n_coarse;
+    uint32_t n_surv, n_refined, n_abandon, n_bsf_upd, n_done, n_read;
     uint32_t err;
     uint32_t blocks_done;
     uint32_t pad1;
@@ -93,7 +91,6 @@ hipError_t launch_root_offsets(const unsigned long long* keys, long long N, uint
                                hipStream_t st);
 hipError_t launch_gather_sax(const uint8_t* sax, const uint32_t* perm, long long N, uint8_t* saxs, hipStream_t st);
 // the words at cardinality 4 (the top 2 bits of every symbol), 4 bytes per series
-hipError_t launch_coarse_words(const uint8_t* sax, long long N, uint32_t* csax, hipStream_t st);
 
 // ---- ADS+ tree (leaf mode 2) ----
 constexpr int kRoots = 65536;       // root subtrees: node r is root key r
@@ -145,17 +142,15 @@ struct QueryArgs {
     int n;
     const uint8_t* sax;
     const uint8_t* saxs;          // the same words in leaf order (saxs[p] = sax[perm[p]])
-    const uint32_t* csax;         // the words at cardinality 4: 2 bits per segment, 32 bits per
-                                  // series (segment 4j + i in bits 2i of byte j), padded to a
-                                  // multiple of 4 series
+    const uint8_t* env;           // [ceil(N / 32)][32] symbol envelope of every run of 32
+                                  // leaf-order positions: the smallest symbol of each segment,
+                                  // then the largest
     const unsigned long long* keys;
     const uint32_t* perm;
     const uint32_t* roff;
     int leaf_mode, n_leaves, seed_cap;
     QState* qs;
     float* t8;        // [16][256]
-    float* tc;        // [4][256] coarse tables: entry (j, b) bounds segments 4j .. 4j+3 whose
-                      // cardinality-4 symbols are the 2-bit fields of b
     uint2* surv;      // (index, lb2 bits)
     uint32_t surv_cap;
     uint2* done;      // (index, d2 fp32 bits)
@@ -376,7 +371,7 @@ hipError_t launch_leaf_of(const uint8_t* sax, const unsigned long long* keys, co
 struct ScanShape {
     int threads;   // 256 or 512
     int per_cu;    // blocks per compute unit
-    int unroll;    // 16-byte loads (4 coarse words each) per lane in flight: 1, 2 or 4
+    int unroll;    // run envelopes per thread in flight: 1, 2 or 4
 };
 
 hipError_t launch_reset(const QueryArgs& a, hipStream_t st);

@@ -72,7 +72,7 @@ __device__ __forceinline__ void reset_state(QState* qs)
     qs->bsf_key = kBsfInit;
     qs->seed_key = kBsfInit;
     qs->head_key = ~0ull;
-    qs->n_surv = qs->n_refined = qs->n_abandon = qs->n_bsf_upd = qs->n_done = qs->n_coarse = 0;
+    qs->n_surv = qs->n_refined = qs->n_abandon = qs->n_bsf_upd = qs->n_done = qs->n_read = 0;
     qs->err = 0;
     qs->blocks_done = 0;
 }
@@ -92,7 +92,7 @@ hipError_t launch_reset(const QueryArgs& a, hipStream_t st)
 // start from zero (its other outputs, head_key and seed_key, come out the same every run).
 __global__ void k_scan_again(QState* qs)
 {
-    if (threadIdx.x == 0) qs->n_surv = qs->n_coarse = 0;
+    if (threadIdx.x == 0) qs->n_surv = qs->n_read = 0;
 }
 
 hipError_t launch_scan_again(const QueryArgs& a, hipStream_t st)
@@ -169,10 +169,10 @@ hipError_t launch_knn_reset(const QueryArgs& a, hipStream_t st)
 // ------------------------------------------------------------------------------------------
 // prepare + seed. Every block computes the query summaries (same arithmetic as the build), the
 // table T8[s][c] = L * delta(q_s, region c)^2 (float64, rounded toward zero to float32) in LDS,
-// and the approximate-search window (sorted positions). Block 0 also publishes T8, the coarse
-// table T5[s][g] = min_{k<8} T8[s][8g+k] and the summaries. Then block b takes window chunk b
-// (kSeedChunk sorted positions), finds the member with the smallest fine bound, computes its
-// float32 squared distance with one wave and folds it into the best-so-far (atomicMin).
+// and the approximate-search window (sorted positions). On the per-query path one extra block
+// publishes T8 and the summaries for the scan; block b < the window's chunk count takes window
+// chunk b (kSeedChunk sorted positions), finds the member with the smallest fine bound, computes
+// its float32 squared distance with one wave and folds it into the best-so-far (atomicMin).
 // ------------------------------------------------------------------------------------------
 // Lower bound of key in sorted keys[a, b) found by the whole block with 256-way splits.
 __device__ long long block_lower_bound(const unsigned long long* __restrict__ keys, long long a, long long b,
@@ -317,30 +317,6 @@ __global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* 
     const bool publisher = !batch && blockIdx.x == gridDim.x - 1;
     if (publisher) {
         for (int e = tid; e < kSeg * kSym; e += 256) A.t8[e] = t8[e];
-        // coarse tables: T2[s][c] = min of the 64 fine entries whose symbol's top 2 bits are c
-        // (the term of the region of cardinality 4, never above a member's fine term); entry
-        // (j, b) = (T2[4j][b0] + T2[4j+1][b1]) + (T2[4j+2][b2] + T2[4j+3][b3]), b = b0 + 4 b1 +
-        // 16 b2 + 64 b3 (the first half of the fine bound's summation tree)
-        // The fine entries are rounded values of L d^2 with d the distance from the query mean
-        // to the symbol's region; rounding and squaring are monotone and the 64 regions of a
-        // cardinality-4 symbol are adjacent, so their smallest entry is the rounded L d^2 of the
-        // distance to the union [beta(64 c), beta(64 c + 64)] (the same double expression as the
-        // fine entry of the end region nearest the mean, or 0 inside): the minimum, exactly.
-        __shared__ float t2[kSeg * 4];
-        if (tid < kSeg * 4) {
-            const int sg = tid >> 2, c = tid & 3;
-            const double x = qpaa[sg], lo = beta[64 * c], hi = beta[64 * c + 64];
-            double d = 0.0;
-            if (x < lo) d = lo - x;
-            else if (x > hi) d = x - hi;
-            t2[tid] = __double2float_rz((double)L * (d * d));
-        }
-        __syncthreads();
-        for (int e = tid; e < kGroups * kGroupCodes; e += 256) {
-            const int j = e >> 8, b = e & 255;
-            const float* g = t2 + 16 * j;   // segments 4j .. 4j+3, 4 entries each
-            A.tc[e] = (g[0 + (b & 3)] + g[4 + ((b >> 2) & 3)]) + (g[8 + ((b >> 4) & 3)] + g[12 + (b >> 6)]);
-        }
         if (tid < kSeg) {
             A.qs->paa[tid] = qpaa[tid];
             A.qs->sym[tid] = (uint8_t)qsym[tid];
@@ -673,61 +649,80 @@ hipError_t launch_prepare_seed_batch(const QueryArgs& a, const SeedBatch& b_in, 
 }
 
 // ------------------------------------------------------------------------------------------
-// lbscan (LBC workers), in two passes over the iSAX words:
-//   coarse: the words at cardinality 4 (4 bytes per series, 4 series per 16-byte load, U loads
-//   per lane in flight): the bound is the sum of 4 lookups in the coarse tables (LDS), one per
-//   group of 4 segments indexed directly by the word's byte. Series whose coarse bound does not
-//   exceed the threshold are staged in LDS (wave ballot, mbcnt rank, one LDS atomic per wave);
-//   fine: once kPass are staged (and at the end), the block loads their full 8-bit words, 4 per
-//   thread at once, and sums T8[s][sym_s] (LDS); survivors (fine bound <= threshold) are staged
-//   again and flushed to the global list with one global atomic per flush, when the staging could
-//   overflow and at the end.
-// Both bounds are float32 sums of 16 terms, each term at most the exact term of the series
-// (entries rounded toward zero; a coarse entry is the minimum over its region's fine entries), so
-// either bound is at most (1 + gamma_15) times the exact bound and pruning on either is covered
-// by the threshold's margin.
+// lbscan (LBC workers) over runs of kEnvRun consecutive positions of the leaf order, in two
+// steps per run:
+//   run bound: every run's symbol envelope (the smallest and the largest symbol of each segment
+//   over its series, stored at build) gives the bound sum_s T8[s][clamp(qsym_s, min_s, max_s)]
+//   in the fine bound's summation tree. T8[s][c] is the rounded L d^2 of the distance from the
+//   query's mean to region c and does not decrease moving away from the query's own symbol, so
+//   each term is the smallest of the run's series' terms and the sum (monotone float additions,
+//   one fixed tree) is at most every series' fine bound: a run whose bound exceeds the threshold
+//   holds no survivor and its words are never read;
+//   fine bound: the 16-byte words of the runs that pass (contiguous in the leaf-order copy),
+//   kE per thread at once; survivors (fine bound <= threshold) are staged in LDS and flushed to
+//   the global list with their series index (perm) and one global atomic per flush.
+// The survivors are exactly the series whose fine bound is at most the threshold, as with a scan
+// of every word. Runs go to the blocks round-robin (run r to block r mod grid): the runs that pass
+// cluster in leaf order around the query's key, and are spread over all blocks that way.
 // ------------------------------------------------------------------------------------------
-__device__ __forceinline__ float coarse4(const uint32_t c, const float* __restrict__ tc)
+__device__ __forceinline__ float env_lb(const uint4 lo, const uint4 hi, const uint32_t* qsym,
+                                        const float* __restrict__ t8)
 {
-    return (tc[0 * kGroupCodes + (c & 255u)] + tc[1 * kGroupCodes + ((c >> 8) & 255u)]) +
-           (tc[2 * kGroupCodes + ((c >> 16) & 255u)] + tc[3 * kGroupCodes + (c >> 24)]);
+    const uint32_t wl[4] = {lo.x, lo.y, lo.z, lo.w};
+    const uint32_t wh[4] = {hi.x, hi.y, hi.z, hi.w};
+    float part[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+        float t[4];
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int sg = 4 * k + i;
+            const uint32_t mn = (wl[k] >> (8 * i)) & 255u, mx = (wh[k] >> (8 * i)) & 255u;
+            const uint32_t c = min(max(qsym[sg], mn), mx);
+            t[i] = t8[sg * 256 + c];
+        }
+        part[k] = (t[0] + t[1]) + (t[2] + t[3]);
+    }
+    return (part[0] + part[1]) + (part[2] + part[3]);
 }
 
 template <int U, int BS>
 __global__ __launch_bounds__(BS) void k_lbscan(QueryArgs A, float fixed_thr)
 {
-    constexpr int kE = 4;                      // staged series per thread and fine step
-    constexpr int kPass = kE * BS;             // staged coarse passers handled per fine step
-    constexpr int kCap = kPass + 4 * BS * U;   // a step of the coarse pass adds at most 4 BS U
-    constexpr int kSurv = 2 * kPass;           // staged survivors (flushed beyond kSurv - kPass)
-    __shared__ float tc[kGroups * kGroupCodes];
+    constexpr int kE = 4;                          // series per thread and fine step
+    constexpr int kRunPass = kE * BS / kEnvRun;    // staged runs handled per fine step
+    constexpr int kRunCap = kRunPass + BS * U;     // a run step adds at most BS U runs
+    constexpr int kSurv = 2 * kE * BS;             // staged survivors (flushed beyond kSurv - kE BS)
+    static_assert(kEnvRun == 32, "32 positions per run");
     __shared__ float t8[kSeg * kSym];
-    __shared__ uint32_t cbuf[kCap];
+    __shared__ uint32_t qsym[kSeg];
+    __shared__ uint32_t rbuf[kRunCap];
     __shared__ uint2 sbuf[kSurv];
-    __shared__ uint32_t ccount, scount, sbase, ctotal;
+    __shared__ uint32_t rcount, scount, sbase, nread;
     __shared__ unsigned long long shead;
     const int tid = threadIdx.x, lane = tid & 63;
-    const uint4* __restrict__ cw = reinterpret_cast<const uint4*>(A.csax);
-    const uint4* __restrict__ sax = reinterpret_cast<const uint4*>(A.sax);
+    const uint4* __restrict__ env = reinterpret_cast<const uint4*>(A.env);
+    const uint4* __restrict__ saxs = reinterpret_cast<const uint4*>(A.saxs);
     const long long N = A.N;
-    const long long NG = (N + 3) / 4;          // groups of 4 series (one 16-byte load)
-    const long long stride = (long long)gridDim.x * BS;
-    long long base = (long long)blockIdx.x * BS;
-    if (tid == 0) { ccount = 0; scount = 0; ctotal = 0; shead = ~0ull; }
+    const long long NR = (N + kEnvRun - 1) / kEnvRun;
+    const long long G = gridDim.x;
+    // this block's runs: blockIdx.x + G j, j = 0 .. nmine - 1
+    const long long nmine = NR > (long long)blockIdx.x ? (NR - blockIdx.x + G - 1) / G : 0;
+    if (tid == 0) { rcount = 0; scount = 0; nread = 0; shead = ~0ull; }
 
-    uint4 nxt[U];
+    uint4 nlo[U], nhi[U];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {  // first words are in flight while the tables load
-        const long long g = base + u * stride + tid;
-        nxt[u] = (g < NG) ? cw[g] : make_uint4(0, 0, 0, 0);
+    for (int u = 0; u < U; ++u) {  // first envelopes are in flight while the tables load
+        const long long j = u * BS + tid;
+        const long long r = blockIdx.x + G * j;
+        nlo[u] = j < nmine ? env[2 * r] : make_uint4(0, 0, 0, 0);
+        nhi[u] = j < nmine ? env[2 * r + 1] : make_uint4(0, 0, 0, 0);
     }
     {
-        const float4* s4 = reinterpret_cast<const float4*>(A.tc);
-        float4* d4 = reinterpret_cast<float4*>(tc);
-        for (int e = tid; e < kGroups * kGroupCodes / 4; e += BS) d4[e] = s4[e];
         const float4* s8 = reinterpret_cast<const float4*>(A.t8);
         float4* d8 = reinterpret_cast<float4*>(t8);
         for (int e = tid; e < kSeg * kSym / 4; e += BS) d8[e] = s8[e];
+        if (tid < kSeg) qsym[tid] = A.qs->sym[tid];
     }
     float thr;
     if (fixed_thr >= 0.f) {
@@ -739,134 +734,131 @@ __global__ __launch_bounds__(BS) void k_lbscan(QueryArgs A, float fixed_thr)
     }
     __syncthreads();
 
-    // survivors staged in LDS to the global list (one global atomic per flush); whole block
+    // survivors staged in LDS (sorted position, bound) to the global list as (series, bound),
+    // one global atomic per flush; the smallest (bound, series) key is the head; whole block
     auto flush = [&]() {
         __syncthreads();
         const uint32_t cnt = scount;
         if (tid == 0) sbase = cnt ? atomicAdd(&A.qs->n_surv, cnt) : 0u;
         __syncthreads();
         const uint32_t b = sbase;
-        for (uint32_t k = tid; k < cnt; k += BS)
-            if (b + k < A.surv_cap) A.surv[b + k] = sbuf[k];
+        unsigned long long mh = ~0ull;
+        for (uint32_t k = tid; k < cnt; k += BS) {
+            const uint2 e = sbuf[k];
+            const uint32_t row = A.perm[e.x];
+            const unsigned long long hk = pack_key(__uint_as_float(e.y), row);
+            mh = hk < mh ? hk : mh;
+            if (b + k < A.surv_cap) A.surv[b + k] = make_uint2(row, e.y);
+        }
+        if (mh != ~0ull) atomicMin(&shead, mh);
         __syncthreads();
         if (tid == 0) scount = 0;
         __syncthreads();
     };
-    // fine bound of the staged series [0, count), kE per thread at a time with all their words in
-    // flight; survivors are staged and flushed only when the staging could overflow
-    auto fine = [&](uint32_t count) {
-        for (uint32_t a = 0; a < count; a += kPass) {
-            uint32_t idx[kE];
+    // fine bound of the series of staged runs [0, nruns): kE per thread at a time, all their
+    // words in flight; the wave's survivors of a step take their slots with one LDS atomic
+    auto fine = [&](uint32_t nruns) {
+        const uint32_t total = nruns * kEnvRun;
+        for (uint32_t a = 0; a < total; a += kE * BS) {
+            uint32_t pos[kE];
             uint4 w[kE];
 #pragma unroll
             for (int k = 0; k < kE; ++k) {   // every load issued before any is used
                 const uint32_t e = a + (uint32_t)(tid + k * BS);
-                idx[k] = e < count ? cbuf[e] : 0xFFFFFFFFu;
-                w[k] = idx[k] != 0xFFFFFFFFu ? sax[idx[k]] : make_uint4(0u, 0u, 0u, 0u);
+                const long long p = e < total ? (long long)rbuf[e / kEnvRun] * kEnvRun + (e % kEnvRun) : N;
+                pos[k] = p < N ? (uint32_t)p : 0xFFFFFFFFu;   // n_series <= 2^32 - 2
+                w[k] = p < N ? saxs[p] : make_uint4(0u, 0u, 0u, 0u);
             }
-            // the wave's survivors of the kE series per lane: one ballot per k, one LDS atomic
-            // for all of them, ranks from mbcnt (at most kPass appends per step, onto at most
-            // kSurv - kPass staged)
             float lb8[kE];
             bool pass[kE];
             unsigned long long m[kE];
-            uint32_t tot = 0;
+            uint32_t tot = 0, valid = 0;
 #pragma unroll
             for (int k = 0; k < kE; ++k) {
                 lb8[k] = fine_lb(w[k], t8);
-                pass[k] = idx[k] != 0xFFFFFFFFu && lb8[k] <= thr;
+                pass[k] = pos[k] != 0xFFFFFFFFu && lb8[k] <= thr;
                 m[k] = __ballot(pass[k]);
                 tot += (uint32_t)__popcll(m[k]);
+                valid += (uint32_t)__popcll(__ballot(pos[k] != 0xFFFFFFFFu));
             }
-            if (tot) {   // uniform
+            if (lane == 0) atomicAdd(&nread, valid);
+            if (tot) {   // uniform; at most kE BS appends per step, onto at most kSurv - kE BS staged
                 uint32_t bp = 0;
                 if (lane == 0) bp = atomicAdd(&scount, tot);
                 bp = __shfl(bp, 0);
-                unsigned long long mhead = ~0ull;
 #pragma unroll
                 for (int k = 0; k < kE; ++k) {
                     if (pass[k]) {
                         const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
                             (uint32_t)(m[k] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m[k], 0u));
-                        sbuf[bp + rank] = make_uint2(idx[k], __float_as_uint(lb8[k]));
-                        const unsigned long long hk = pack_key(lb8[k], idx[k]);
-                        mhead = hk < mhead ? hk : mhead;
+                        sbuf[bp + rank] = make_uint2(pos[k], __float_as_uint(lb8[k]));
                     }
                     bp += (uint32_t)__popcll(m[k]);
                 }
-                if (mhead != ~0ull) atomicMin(&shead, mhead);
             }
             __syncthreads();
-            if (scount > (uint32_t)(kSurv - kPass)) flush();   // uniform
+            if (scount > (uint32_t)(kSurv - kE * BS)) flush();   // uniform
         }
     };
 
-    for (; base < NG; base += stride * U) {
-        uint4 cur[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) cur[u] = nxt[u];
-        const long long nb = base + stride * U;
-        if (nb < NG) {
-#pragma unroll
-            for (int u = 0; u < U; ++u) {
-                const long long g = nb + u * stride + tid;
-                nxt[u] = (g < NG) ? cw[g] : make_uint4(0, 0, 0, 0);
-            }
-        }
+    for (long long j0 = 0; j0 < nmine; j0 += (long long)BS * U) {
+        uint4 clo[U], chi[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const long long i0 = 4 * (base + u * stride + tid);
-            // series of this load inside the collection (the padding of the last load is not)
-            const long long left = N - i0;
-            const int lim = left >= 4 ? 4 : (left > 0 ? (int)left : 0);
-            float c[4];
+            clo[u] = nlo[u];
+            chi[u] = nhi[u];
+        }
+        const long long jn = j0 + (long long)BS * U;
+        if (jn < nmine) {
 #pragma unroll
-            for (int k = 0; k < 4; ++k) c[k] = coarse4(word_at(cur[u], k), tc);   // 16 reads in flight
-            // the wave's passers of this load: one ballot per series of the 4, one LDS atomic
-            // for all of them, ranks from mbcnt (at most 4 BS U appends per step: the staging
-            // holds kCap)
-            bool pass[4];
-            unsigned long long m[4];
-            uint32_t tot = 0;
-#pragma unroll
-            for (int k = 0; k < 4; ++k) {
-                pass[k] = (c[k] <= thr) & (k < lim);
-                m[k] = __ballot(pass[k]);
-                tot += (uint32_t)__popcll(m[k]);
+            for (int u = 0; u < U; ++u) {
+                const long long j = jn + u * BS + tid;
+                const long long r = blockIdx.x + G * j;
+                nlo[u] = j < nmine ? env[2 * r] : make_uint4(0, 0, 0, 0);
+                nhi[u] = j < nmine ? env[2 * r + 1] : make_uint4(0, 0, 0, 0);
             }
-            if (tot) {   // uniform
-                uint32_t bp = 0;
-                if (lane == 0) bp = atomicAdd(&ccount, tot);
-                bp = __shfl(bp, 0);
+        }
+        // the wave's runs that pass: one ballot per load, one LDS atomic for all of them
+        bool keep[U];
+        unsigned long long m[U];
+        uint32_t tot = 0;
 #pragma unroll
-                for (int k = 0; k < 4; ++k) {
-                    if (pass[k]) {
-                        const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
-                            (uint32_t)(m[k] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m[k], 0u));
-                        cbuf[bp + rank] = (uint32_t)(i0 + k);
-                    }
-                    bp += (uint32_t)__popcll(m[k]);
+        for (int u = 0; u < U; ++u) {
+            const long long j = j0 + u * BS + tid;
+            keep[u] = j < nmine && env_lb(clo[u], chi[u], qsym, t8) <= thr;
+            m[u] = __ballot(keep[u]);
+            tot += (uint32_t)__popcll(m[u]);
+        }
+        if (tot) {   // uniform; at most BS U appends per step: the staging holds kRunCap
+            uint32_t bp = 0;
+            if (lane == 0) bp = atomicAdd(&rcount, tot);
+            bp = __shfl(bp, 0);
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                if (keep[u]) {
+                    const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
+                        (uint32_t)(m[u] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m[u], 0u));
+                    rbuf[bp + rank] = (uint32_t)(blockIdx.x + G * (j0 + u * BS + tid));
                 }
+                bp += (uint32_t)__popcll(m[u]);
             }
         }
         __syncthreads();
-        const uint32_t cc = ccount;
-        if (cc >= (uint32_t)kPass) {   // uniform
-            if (tid == 0) ctotal += cc;
-            fine(cc);
-            if (tid == 0) ccount = 0;
+        const uint32_t rc = rcount;
+        if (rc >= (uint32_t)kRunPass) {   // uniform
+            fine(rc);
+            if (tid == 0) rcount = 0;
             __syncthreads();
         }
     }
     __syncthreads();
-    const uint32_t cc = ccount;
-    if (cc) fine(cc);
+    const uint32_t rc = rcount;
+    if (rc) fine(rc);
     __syncthreads();
     if (scount) flush();   // uniform
     if (tid == 0 && shead != ~0ull) atomicMin(&A.qs->head_key, shead);
-    if (tid == 0 && ctotal + cc) atomicAdd(&A.qs->n_coarse, ctotal + cc);
+    if (tid == 0 && nread) atomicAdd(&A.qs->n_read, nread);
 }
-
 // Streams `bytes` of a buffer through the caches (a read-only sweep). The launch-shape tuner
 // runs it between timed scans so that they start from caches holding other, clean lines, as
 // they would after a query's refinement has read rows of the raw collection.
@@ -892,8 +884,8 @@ template <int U, int BS>
 static hipError_t launch_scan_t(const QueryArgs& a, float thr, int per_cu, int cus, hipStream_t st,
                                 hipEvent_t e0, hipEvent_t e1)
 {
-    const long long groups = (a.N + 3) / 4;
-    const long long need = (groups + (long long)BS * U - 1) / ((long long)BS * U);
+    const long long runs = (a.N + kEnvRun - 1) / kEnvRun;
+    const long long need = runs;   // a block takes at least one run
     long long grid = (long long)cus * (per_cu > 0 ? per_cu : 4);
     if (grid > need) grid = need;
     if (grid < 1) grid = 1;
@@ -1034,7 +1026,7 @@ __device__ void resolve_block(const QueryArgs& A, const float* __restrict__ q, l
         r.win_lo = qs->win_lo;
         r.win_hi = qs->win_hi;
         r.n_surv = qs->n_surv;
-        r.n_coarse = qs->n_coarse;
+        r.n_read = qs->n_read;
         r.n_refined = qs->n_refined;
         r.n_abandon = qs->n_abandon;
         r.n_bsf_upd = qs->n_bsf_upd;
@@ -1129,7 +1121,7 @@ __device__ void resolve_knn_block(const QueryArgs& A, const float* __restrict__ 
         r.win_lo = qs->win_lo;
         r.win_hi = qs->win_hi;
         r.n_surv = qs->n_surv;
-        r.n_coarse = qs->n_coarse;
+        r.n_read = qs->n_read;
         r.n_refined = qs->n_refined;
         r.n_abandon = qs->n_abandon;
         r.n_bsf_upd = qs->n_bsf_upd;
