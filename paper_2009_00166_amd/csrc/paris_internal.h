@@ -90,7 +90,6 @@ hipError_t launch_sort_keys(unsigned long long* keys, uint32_t* perm, unsigned l
 hipError_t launch_root_offsets(const unsigned long long* keys, long long N, uint32_t* roff,
                                hipStream_t st);
 hipError_t launch_gather_sax(const uint8_t* sax, const uint32_t* perm, long long N, uint8_t* saxs, hipStream_t st);
-// the words at cardinality 4 (the top 2 bits of every symbol), 4 bytes per series
 
 // ---- ADS+ tree (leaf mode 2) ----
 constexpr int kRoots = 65536;       // root subtrees: node r is root key r

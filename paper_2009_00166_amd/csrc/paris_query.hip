@@ -174,6 +174,15 @@ hipError_t launch_knn_reset(const QueryArgs& a, hipStream_t st)
 // chunk b (kSeedChunk sorted positions), finds the member with the smallest fine bound, computes
 // its float32 squared distance with one wave and folds it into the best-so-far (atomicMin).
 // ------------------------------------------------------------------------------------------
+// float32 of a non-negative float64 rounded toward zero: the nearest float32, one step toward
+// zero when that is above x (the float32 grid is monotone, so the step lands on the largest
+// float32 not above x; x above the largest finite float32 gives that float32)
+__device__ __forceinline__ float f32_toward_zero(double x)
+{
+    const float f = (float)x;
+    return (double)f > x ? __uint_as_float(__float_as_uint(f) - 1u) : f;
+}
+
 // Lower bound of key in sorted keys[a, b) found by the whole block with 256-way splits.
 __device__ long long block_lower_bound(const unsigned long long* __restrict__ keys, long long a, long long b,
                                        unsigned long long key, int* s_cnt)
@@ -255,14 +264,22 @@ __global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* 
         qsym[tid] = c;
         if (bad) atomicOr(&s_bad, 1u);
     }
-    __syncthreads();
-    if (tid == 0) {
+    if (tid < 64) {
+        // the leaf key: bit planes 7..4 of the 16 symbols, segment 0 first within a plane. The
+        // ballot of plane p over lanes 0..15 has segment s at bit s; reversed, at bit 15 - s.
+        const int c = tid < kSeg ? qsym[tid] : 0;
         unsigned long long k = 0;
-        for (int p = 7; p >= 4; --p)
-            for (int s = 0; s < kSeg; ++s) k = (k << 1) | (unsigned long long)((qsym[s] >> p) & 1);
-        s_k64 = k;
-        s_root = (uint32_t)(k >> 48);
+#pragma unroll
+        for (int p = 7; p >= 4; --p) {
+            const uint32_t m = (uint32_t)__ballot(tid < kSeg && ((c >> p) & 1)) & 0xFFFFu;
+            k = (k << 16) | (unsigned long long)(__builtin_bitreverse32(m) >> 16);
+        }
+        if (tid == 0) {
+            s_k64 = k;
+            s_root = (uint32_t)(k >> 48);
+        }
     }
+    __syncthreads();
     {
         // thread tid owns symbol c = tid of every segment: its region's breakpoints are read
         // once, the 16 means all at once. The distance from the mean to the region, branch-free:
@@ -276,7 +293,7 @@ __global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* 
 #pragma unroll
         for (int s = 0; s < kSeg; ++s) {
             const double d = fmax(lo - xs[s], 0.0) + fmax(xs[s] - hi, 0.0);
-            t8[s * kSym + c] = __double2float_rz((double)L * (d * d));
+            t8[s * kSym + c] = f32_toward_zero((double)L * (d * d));
         }
     }
     __syncthreads();
@@ -662,8 +679,9 @@ hipError_t launch_prepare_seed_batch(const QueryArgs& a, const SeedBatch& b_in, 
 //   kE per thread at once; survivors (fine bound <= threshold) are staged in LDS and flushed to
 //   the global list with their series index (perm) and one global atomic per flush.
 // The survivors are exactly the series whose fine bound is at most the threshold, as with a scan
-// of every word. Runs go to the blocks round-robin (run r to block r mod grid): the runs that pass
-// cluster in leaf order around the query's key, and are spread over all blocks that way.
+// of every word. Runs go to the blocks round-robin in groups of 4 (the 4 envelopes of a 128-byte
+// line; group g to block g mod grid): the runs that pass cluster in leaf order around the
+// query's key, and are spread over all blocks that way.
 // ------------------------------------------------------------------------------------------
 __device__ __forceinline__ float env_lb(const uint4 lo, const uint4 hi, const uint32_t* qsym,
                                         const float* __restrict__ t8)
@@ -705,18 +723,23 @@ __global__ __launch_bounds__(BS) void k_lbscan(QueryArgs A, float fixed_thr)
     const uint4* __restrict__ saxs = reinterpret_cast<const uint4*>(A.saxs);
     const long long N = A.N;
     const long long NR = (N + kEnvRun - 1) / kEnvRun;
+    const long long NL = (NR + 3) / 4;   // 128-byte lines of 4 envelopes
     const long long G = gridDim.x;
-    // this block's runs: blockIdx.x + G j, j = 0 .. nmine - 1
-    const long long nmine = NR > (long long)blockIdx.x ? (NR - blockIdx.x + G - 1) / G : 0;
+    // This block's runs: the 4 runs of every line blockIdx.x + G i, numbered j = 4 i + k. A line
+    // is read by one block only, so by one XCD's L2 (blocks are spread over the XCDs round-robin:
+    // a line shared by neighbouring blocks would be fetched once per XCD).
+    const long long nmine = NL > (long long)blockIdx.x ? 4 * ((NL - blockIdx.x + G - 1) / G) : 0;
+    auto run_of = [&](long long j) -> long long { return 4 * (blockIdx.x + G * (j >> 2)) + (j & 3); };
     if (tid == 0) { rcount = 0; scount = 0; nread = 0; shead = ~0ull; }
 
     uint4 nlo[U], nhi[U];
 #pragma unroll
     for (int u = 0; u < U; ++u) {  // first envelopes are in flight while the tables load
         const long long j = u * BS + tid;
-        const long long r = blockIdx.x + G * j;
-        nlo[u] = j < nmine ? env[2 * r] : make_uint4(0, 0, 0, 0);
-        nhi[u] = j < nmine ? env[2 * r + 1] : make_uint4(0, 0, 0, 0);
+        const long long r = run_of(j);
+        const bool ok = j < nmine && r < NR;
+        nlo[u] = ok ? env[2 * r] : make_uint4(0, 0, 0, 0);
+        nhi[u] = ok ? env[2 * r + 1] : make_uint4(0, 0, 0, 0);
     }
     {
         const float4* s8 = reinterpret_cast<const float4*>(A.t8);
@@ -735,17 +758,20 @@ __global__ __launch_bounds__(BS) void k_lbscan(QueryArgs A, float fixed_thr)
     __syncthreads();
 
     // survivors staged in LDS (sorted position, bound) to the global list as (series, bound),
-    // one global atomic per flush; the smallest (bound, series) key is the head; whole block
+    // one global atomic per flush; the smallest (bound, series) key is the head; whole block.
+    // The series indices of the first BS staged entries are loaded while the atomic that claims
+    // the block's slots is in flight (one memory round trip for both).
     auto flush = [&]() {
         __syncthreads();
         const uint32_t cnt = scount;
+        const uint32_t row0 = (uint32_t)tid < cnt ? A.perm[sbuf[tid].x] : 0u;
         if (tid == 0) sbase = cnt ? atomicAdd(&A.qs->n_surv, cnt) : 0u;
         __syncthreads();
         const uint32_t b = sbase;
         unsigned long long mh = ~0ull;
         for (uint32_t k = tid; k < cnt; k += BS) {
             const uint2 e = sbuf[k];
-            const uint32_t row = A.perm[e.x];
+            const uint32_t row = k == (uint32_t)tid ? row0 : A.perm[e.x];
             const unsigned long long hk = pack_key(__uint_as_float(e.y), row);
             mh = hk < mh ? hk : mh;
             if (b + k < A.surv_cap) A.surv[b + k] = make_uint2(row, e.y);
@@ -813,9 +839,10 @@ __global__ __launch_bounds__(BS) void k_lbscan(QueryArgs A, float fixed_thr)
 #pragma unroll
             for (int u = 0; u < U; ++u) {
                 const long long j = jn + u * BS + tid;
-                const long long r = blockIdx.x + G * j;
-                nlo[u] = j < nmine ? env[2 * r] : make_uint4(0, 0, 0, 0);
-                nhi[u] = j < nmine ? env[2 * r + 1] : make_uint4(0, 0, 0, 0);
+                const long long r = run_of(j);
+                const bool ok = j < nmine && r < NR;
+                nlo[u] = ok ? env[2 * r] : make_uint4(0, 0, 0, 0);
+                nhi[u] = ok ? env[2 * r + 1] : make_uint4(0, 0, 0, 0);
             }
         }
         // the wave's runs that pass: one ballot per load, one LDS atomic for all of them
@@ -825,7 +852,7 @@ __global__ __launch_bounds__(BS) void k_lbscan(QueryArgs A, float fixed_thr)
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const long long j = j0 + u * BS + tid;
-            keep[u] = j < nmine && env_lb(clo[u], chi[u], qsym, t8) <= thr;
+            keep[u] = j < nmine && run_of(j) < NR && env_lb(clo[u], chi[u], qsym, t8) <= thr;
             m[u] = __ballot(keep[u]);
             tot += (uint32_t)__popcll(m[u]);
         }
@@ -838,7 +865,7 @@ __global__ __launch_bounds__(BS) void k_lbscan(QueryArgs A, float fixed_thr)
                 if (keep[u]) {
                     const uint32_t rank = __builtin_amdgcn_mbcnt_hi(
                         (uint32_t)(m[u] >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m[u], 0u));
-                    rbuf[bp + rank] = (uint32_t)(blockIdx.x + G * (j0 + u * BS + tid));
+                    rbuf[bp + rank] = (uint32_t)run_of(j0 + u * BS + tid);
                 }
                 bp += (uint32_t)__popcll(m[u]);
             }
@@ -885,7 +912,7 @@ static hipError_t launch_scan_t(const QueryArgs& a, float thr, int per_cu, int c
                                 hipEvent_t e0, hipEvent_t e1)
 {
     const long long runs = (a.N + kEnvRun - 1) / kEnvRun;
-    const long long need = runs;   // a block takes at least one run
+    const long long need = (runs + 3) / 4;   // a block takes at least one line of 4 runs
     long long grid = (long long)cus * (per_cu > 0 ? per_cu : 4);
     if (grid > need) grid = need;
     if (grid < 1) grid = 1;
@@ -949,14 +976,30 @@ __device__ void resolve_block(const QueryArgs& A, const float* __restrict__ q, l
     __shared__ long long ri[256];
     const int tid = threadIdx.x, n = A.n;
     QState* qs = A.qs;
+    // the final best, the candidate count and the first 256 candidate entries in one round trip
+    // (an entry at or past the count is never used)
     const unsigned long long key = load_key(&qs->bsf_key);
-    const double band = (double)key_dist(key) * (1.0 + A.mg.band_rel) + 1e-25;
     const uint32_t ndone = __hip_atomic_load(&qs->n_done, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    const uint2 v_first = (uint32_t)tid < A.done_cap ? A.done[tid] : make_uint2(0u, 0u);
+    // the fields of the result that the refinement left final, loaded alongside by thread 0
+    QResult snap{};
+    if (tid == 0) {
+        snap.seed_key = qs->seed_key;
+        snap.win_lo = qs->win_lo;
+        snap.win_hi = qs->win_hi;
+        snap.n_surv = qs->n_surv;
+        snap.n_read = qs->n_read;
+        snap.n_refined = qs->n_refined;
+        snap.n_abandon = qs->n_abandon;
+        snap.n_bsf_upd = qs->n_bsf_upd;
+        snap.err = qs->err;
+    }
+    const double band = (double)key_dist(key) * (1.0 + A.mg.band_rel) + 1e-25;
     const uint32_t count = min(ndone, A.done_cap);
     if (tid == 0) { ncand = 0; nres = 0; }
     __syncthreads();
     for (uint32_t e = tid; e < count; e += 256) {
-        const uint2 v = A.done[e];
+        const uint2 v = e == (uint32_t)tid ? v_first : A.done[e];
         if ((double)__uint_as_float(v.y) <= band) {
             const uint32_t p = atomicAdd(&ncand, 1u);
             if (p < kResolveList) cand[p] = v;
@@ -1015,23 +1058,16 @@ __device__ void resolve_block(const QueryArgs& A, const float* __restrict__ q, l
         }
     }   // otherwise thread 0 alone scored the candidates
     if (tid == 0) {
-        uint32_t err = qs->err;
-        if (qs->n_surv > A.surv_cap) err |= kErrSurvOverflow;
+        uint32_t err = snap.err;
+        if (snap.n_surv > A.surv_cap) err |= kErrSurvOverflow;
         if (ndone > A.done_cap) err |= kErrDoneOverflow;
         const bool found = ri[0] != 0x7FFFFFFFFFFFFFFFll && (err & kErrNonFinite) == 0u;
-        QResult& r = qs->res;
+        QResult r = snap;
         r.idx = found ? ri[0] : -1;
         r.d2 = found ? rd[0] : __builtin_nan("");
-        r.seed_key = qs->seed_key;
-        r.win_lo = qs->win_lo;
-        r.win_hi = qs->win_hi;
-        r.n_surv = qs->n_surv;
-        r.n_read = qs->n_read;
-        r.n_refined = qs->n_refined;
-        r.n_abandon = qs->n_abandon;
-        r.n_bsf_upd = qs->n_bsf_upd;
         r.n_resolved = nres;
         r.err = err;
+        qs->res = r;
         if (A.host_res) {
             // the host polls idx (set to -2 before the launch): every other field first, then a
             // system-scope fence, then idx
@@ -1157,8 +1193,22 @@ __global__ __launch_bounds__(256) void k_refine_resolve(QueryArgs A, const float
     constexpr int GPB = 256 / G;         // lane groups per block
     __shared__ bool s_last;
     __shared__ __attribute__((aligned(16))) float qs_l[kMaxLength];
+    constexpr int QR = kMaxLength / 256;   // query points per thread
     const int tid = threadIdx.x, l = tid & (G - 1), lane = tid & 63, lead = lane & ~(G - 1);
-    const uint32_t count = min(A.qs->n_surv, A.surv_cap);
+    const bool priv = !KNN && A.bsf_private != 0;
+    const uint32_t grp = blockIdx.x * (uint32_t)GPB + (uint32_t)(tid / G);
+    // Issued together, in one memory round trip: the survivor count, the pruning key, the head
+    // key, the query and this group's first survivor entry (its slot, grp, does not depend on
+    // how many blocks take part; an entry at or past the count is never used).
+    const uint32_t n_surv = A.qs->n_surv;
+    // (taken from the group's first lane, so that a concurrent update cannot split a group)
+    const unsigned long long key0 = __shfl(load_key(priv ? &A.qs->seed_key : &A.qs->bsf_key), lead);
+    const unsigned long long hk = KNN ? ~0ull : A.qs->head_key;
+    const uint2 e_first = grp < A.surv_cap ? A.surv[grp] : make_uint2(0xFFFFFFFFu, 0u);
+    float qr[QR];
+#pragma unroll
+    for (int i = 0; i < QR; ++i) qr[i] = tid + 256 * i < A.n ? q[tid + 256 * i] : 0.f;
+    const uint32_t count = min(n_surv, A.surv_cap);
     // Blocks taking part: one per kRefinePerBlock survivors, at least kRefineMinBlocks, at most the
     // grid. Every block derives the same number from the same count; the others leave at once
     // (a large grid serves queries with many survivors, a small one keeps the few-survivor case
@@ -1167,10 +1217,11 @@ __global__ __launch_bounds__(256) void k_refine_resolve(QueryArgs A, const float
     active = active < (uint32_t)kRefineMinBlocks ? (uint32_t)kRefineMinBlocks : active;
     active = active > gridDim.x ? gridDim.x : active;
     if (blockIdx.x >= active) return;
-    const uint32_t grp = blockIdx.x * (uint32_t)GPB + (uint32_t)(tid / G);
     const uint32_t ngrp = active * (uint32_t)GPB;
     const int nv = A.n >> 2;
-    for (int j = tid; j < A.n; j += 256) qs_l[j] = q[j];
+#pragma unroll
+    for (int i = 0; i < QR; ++i)
+        if (tid + 256 * i < A.n) qs_l[tid + 256 * i] = qr[i];
     __syncthreads();
     const float4* q4 = reinterpret_cast<const float4*>(qs_l);
     uint32_t refined = 0, abandoned = 0;
@@ -1180,7 +1231,6 @@ __global__ __launch_bounds__(256) void k_refine_resolve(QueryArgs A, const float
     // waiting for other groups' atomicMin; group 0 also publishes it.
     float local_best = __builtin_inff();
     if (!KNN && count > ngrp) {
-        const unsigned long long hk = A.qs->head_key;
         if (hk != ~0ull) {
             const uint32_t hrow = (uint32_t)(hk & 0xFFFFFFFFu);
             const float4* h4 = reinterpret_cast<const float4*>(A.X + (long long)hrow * A.n);
@@ -1200,11 +1250,7 @@ __global__ __launch_bounds__(256) void k_refine_resolve(QueryArgs A, const float
             }
         }
     }
-    const bool priv = !KNN && A.bsf_private != 0;
     constexpr int CV = 4 * F;            // float4 per lane per chunk
-    unsigned long long key0 = 0;
-    if (l == 0) key0 = load_key(priv ? &A.qs->seed_key : &A.qs->bsf_key);
-    key0 = __shfl(key0, lead);
     float thr = prune_threshold(fminf(key_dist(key0), local_best), A.mg.prune_rel);
     // The points of a row after its first 64: the rest of its first 256 points (3 steps) loaded
     // together, then 256 at a time, the partial sum compared with the threshold after every step
@@ -1260,7 +1306,7 @@ __global__ __launch_bounds__(256) void k_refine_resolve(QueryArgs A, const float
         for (int d = 0; d < kRefineBatch; ++d) {
             const uint32_t c = cb + (uint32_t)d * ngrp;
             // past the list: index 0xFFFFFFFF (never a series: n_series <= 2^32 - 2), never taken
-            eb[d] = c < count ? A.surv[c] : make_uint2(0xFFFFFFFFu, 0u);
+            eb[d] = c >= count ? make_uint2(0xFFFFFFFFu, 0u) : (c == grp ? e_first : A.surv[c]);
         }
         if (!priv) {
             unsigned long long key = 0ull;
