@@ -452,6 +452,24 @@ def main() -> int:
     phase_ms, phased = index.timing()
     index.set_timing(False)
 
+    # the same queries queued on the stream: the per-query kernels of query m + 1 enqueued behind
+    # those of query m without waiting for its answer on the host (answers to device arrays)
+    Iq = torch.empty(M, dtype=torch.int64, device=dev)
+    Dq = torch.empty(M, dtype=torch.float64, device=dev)
+    index.query_batch(Qd, out=(Iq, Dq))
+    torch.cuda.synchronize()
+    tq = time.perf_counter()
+    for k in range(args.steps):
+        index.query_batch(Qd, out=(Iq, Dq))
+    torch.cuda.synchronize()
+    queued = {"queries_per_s": M * args.steps / (time.perf_counter() - tq),
+              "answers_identical": bool(np.array_equal(Iq.cpu().numpy(), answers)),
+              "note": "the same queries and kernels, each query's seed, scan and refine enqueued "
+                      "behind the previous query's without its answer being read back in between "
+                      "(paris_query_batch with no batch workspace attached); value answers one query "
+                      "at a time, each answer read back before the next query is issued"}
+    log(f"queued per-query path: {queued['queries_per_s']:.0f} queries/s")
+
     cold = cold_scan_section(index, rows, N, args) if args.cold_queries > 0 else None
 
     # counters of one pass (not timed)
@@ -515,6 +533,7 @@ def main() -> int:
                                 "a 1 GiB read-only sweep before every query)" if ENV_BYTES_PER_SERIES * N < 256e6
                                 else "exceed the 256 MB Infinity Cache (streamed from HBM)")},
         "lbscan_cold": cold,
+        "queued": queued,
         "phases_ms_per_query": dict(zip(["prepare_seed", "lbscan", "refine_resolve"],
                                         [p / max(phased, 1) for p in phase_ms])),
         "build_ms": build_s * 1e3,
