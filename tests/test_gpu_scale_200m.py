@@ -1,6 +1,6 @@
 """GPU parity at the top of the paper's dataset-size range (Section 4, query answering versus
 dataset size, 50-250 GB): 200,000,000 random walks of length 256, 204.8 GB of float32 resident
-on one GPU next to the 12.8 GB index (217.6 GB of the 288 GB). The collection is generated in
+on one GPU next to the 12.2 GB index (217.0 GB of the 288 GB). The collection is generated in
 eight seeded chunks of 25M rows; each chunk is copied into the device tensor and brute-forced by
 the C oracle while it is in host memory, so the host holds one chunk at a time. Per-chunk exact
 answers merge into the exact answer over the whole collection (smallest squared distance, ties
