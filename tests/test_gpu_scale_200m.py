@@ -24,6 +24,9 @@ N_FULL, LEN, CHUNK = 200_000_000, 256, 25_000_000
 def coll200(oracle_native):
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
+    import gc
+    gc.collect()                 # earlier modules' collections, once their fixtures are gone
+    torch.cuda.empty_cache()
     free, total = torch.cuda.mem_get_info()
     if free < 230e9:
         pytest.skip(f"needs 230 GB of free device memory, {free / 1e9:.0f} GB free")
