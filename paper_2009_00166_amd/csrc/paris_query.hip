@@ -88,7 +88,7 @@ hipError_t launch_reset(const QueryArgs& a, hipStream_t st)
     return hipGetLastError();
 }
 
-// Before the lower-bound scan of the same query runs again: its survivor and first-pass counts
+// Before the lower-bound scan of the same query runs again: its survivor and word counts
 // start from zero (its other outputs, head_key and seed_key, come out the same every run).
 __global__ void k_scan_again(QState* qs)
 {
