@@ -70,7 +70,7 @@ void make_plan(long long N, Plan* p, const paris_config* cfg)
     p->roff = take(65537 * 4);
     p->qs = take(sizeof(QState));
     p->t8 = take(kSeg * kSym * 4);
-    p->knn = take(kKnnMax * 8);
+    p->knn = take((size_t)(kKnnMax + kKnnSeedCap) * 8);
     p->surv = take((size_t)N * 8);
     // every survivor completes at most once, plus the head survivor computed first (it is also
     // met again in the list): N + 1 entries
@@ -285,6 +285,7 @@ QueryArgs args_for(const paris_index* h)
     a.knn_k = 0;
     a.knn_r = 0;
     a.knn_slots = reinterpret_cast<unsigned long long*>(ws + h->plan.knn);
+    a.knn_seed = a.knn_slots + kKnnMax;
     a.knn_out = nullptr;
     a.tree = h->cfg.leaf_mode == PARIS_LEAF_ADS ? reinterpret_cast<const AdsNode*>(ws + h->plan.tree) : nullptr;
     a.tree_window = (int)(h->tree_max_leaf < 0x7FFFFFFF ? h->tree_max_leaf : 0x7FFFFFFF);
@@ -1604,6 +1605,7 @@ extern "C" paris_status paris_query_knn(paris_index* h, const float* query_dev, 
         HIP_TRY(launch_mlp_query(net_of(m), query_dev, h->n, sc, st));
     }
     HIP_TRY(launch_prepare_seed(a, query_dev, st));
+    HIP_TRY(launch_knn_select(a, st));
     HIP_TRY(launch_lbscan(a, -1.f, h->scan, st));
     HIP_TRY(launch_refine_resolve(a, query_dev, nullptr, nullptr, 0, st));
     int64_t top_i = -1;

@@ -36,6 +36,7 @@ enum ErrBits : uint32_t {
 constexpr int kKnnMax = 64;          // largest k of the exact k-NN
 constexpr int kKnnResolve = 2048;    // k-NN: completed candidates re-scored in float64 at most
 constexpr int kKnnWindow = 16384;    // k-NN: sorted positions of the approximate search's window
+constexpr int kKnnSeedCap = 4096;    // k-NN: seed distances kept for the selection of the k best
 
 // One answer of the exact k-NN: series index and float64 squared distance.
 struct KnnHit {
@@ -169,6 +170,7 @@ struct QueryArgs {
     int knn_k;
     int knn_r;
     unsigned long long* knn_slots;  // [kKnnMax] (float32 bits of ED^2, index) keys
+    unsigned long long* knn_seed;   // [kKnnSeedCap] the seed blocks' keys (slot = block r + t)
     KnnHit* knn_out;                // [kKnnMax] answers of the last block (mapped host memory)
     // leaf mode 2 (ADS+ tree): the nodes, and the largest window the approximate search reaches
     const AdsNode* tree;
@@ -391,5 +393,7 @@ hipError_t launch_refine_resolve(const QueryArgs& a, const float* q, long long* 
 int seed_grid(const QueryArgs& a);
 // exact k-NN: the k best slots set to (+inf, no index) and the state's k-th key to +inf
 hipError_t launch_knn_reset(const QueryArgs& a, hipStream_t st);
+// the k smallest seed keys into the slots, the k-th of them as the best-so-far
+hipError_t launch_knn_select(const QueryArgs& a, hipStream_t st);
 
 }  // namespace paris

@@ -155,14 +155,50 @@ __device__ bool knn_insert_group(unsigned long long* slots, int k, unsigned long
     }
 }
 
-__global__ void k_knn_reset(unsigned long long* slots)
+// empties the k slots and the seed keys (the slots and the seed keys are one array)
+__global__ __launch_bounds__(256) void k_knn_reset(unsigned long long* slots)
 {
-    if (threadIdx.x < kKnnMax) slots[threadIdx.x] = kBsfInit;
+    for (int i = threadIdx.x; i < kKnnMax + kKnnSeedCap; i += 256) slots[i] = kBsfInit;
 }
 
 hipError_t launch_knn_reset(const QueryArgs& a, hipStream_t st)
 {
-    k_knn_reset<<<1, kKnnMax, 0, st>>>(a.knn_slots);
+    k_knn_reset<<<1, 256, 0, st>>>(a.knn_slots);
+    return hipGetLastError();
+}
+
+// The seed blocks leave their keys in the seed array (no insertion races between them); one
+// block then places the k smallest keys into slots 0 .. k - 1 in ascending order: the set keys
+// are compacted in LDS and each one's rank is the number of smaller keys (keys are distinct:
+// distinct series). The best-so-far becomes the k-th smallest, or stays at its initial value
+// (no pruning) when fewer than k seeds exist — as k insertions into the slots would leave them.
+__global__ __launch_bounds__(256) void k_knn_select(QueryArgs A)
+{
+    __shared__ unsigned long long keys[kKnnSeedCap];
+    __shared__ uint32_t cnt;
+    const int tid = threadIdx.x;
+    if (tid == 0) cnt = 0;
+    __syncthreads();
+    for (int i = tid; i < kKnnSeedCap; i += 256) {
+        const unsigned long long x = A.knn_seed[i];
+        if (x != kBsfInit) keys[atomicAdd(&cnt, 1u)] = x;
+    }
+    __syncthreads();
+    const uint32_t n = cnt;
+    const uint32_t k = (uint32_t)A.knn_k;
+    for (uint32_t i = tid; i < n; i += 256) {
+        const unsigned long long x = keys[i];
+        uint32_t rank = 0;
+        for (uint32_t j = 0; j < n; ++j) rank += keys[j] < x ? 1u : 0u;
+        if (rank < k) A.knn_slots[rank] = x;
+        if (rank + 1 == k) A.qs->bsf_key = x;
+    }
+    if (tid == 0 && n < k) A.qs->bsf_key = kBsfInit;
+}
+
+hipError_t launch_knn_select(const QueryArgs& a, hipStream_t st)
+{
+    k_knn_select<<<1, 256, 0, st>>>(a);
     return hipGetLastError();
 }
 
@@ -542,9 +578,9 @@ __global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* 
         if (c0 >= c1) return;  // uniform
         if (A.knn_k > 0) {
             // exact k-NN: the chunk's r smallest-bound members, each round the smallest key above
-            // the previous round's, their distances offered to the k best slots. r spreads the
-            // knn_r * k seed distances over the window's chunks (knn_r: seeds per answer); the
-            // learned seed's chunk count comes from the host.
+            // the previous round's, their distances left for the selection of the k best. r
+            // spreads the knn_r * k seed distances over the window's chunks (knn_r: seeds per
+            // answer); the learned seed's chunk count comes from the host.
             long long nch = learned ? (long long)gridDim.x - 1 : (hi - lo + kSeedChunk - 1) / kSeedChunk;
             if (nch < 1) nch = 1;
             long long r = ((long long)A.knn_r * A.knn_k + nch - 1) / nch;
@@ -559,10 +595,13 @@ __global__ __launch_bounds__(256) void k_prepare_seed(QueryArgs A, const float* 
                 ++nsel;
             }
             __syncthreads();
-            for (int t = tid >> 6; t < nsel; t += 4) {   // one wave per selected member
+            // one wave per selected member; its key goes to this block's part of the seed array
+            // (k_knn_select takes the k best of them)
+            for (int t = tid >> 6; t < nsel; t += 4) {
                 const uint32_t row = (uint32_t)(s_best[t] & 0xFFFFFFFFu);
                 const float acc = wave_dist(row);
-                knn_insert_group<64>(A.knn_slots, A.knn_k, pack_key(acc, row), bsf, lane, 0);
+                const long long slot = (long long)blockIdx.x * r + t;
+                if (lane == 0 && slot < kKnnSeedCap) A.knn_seed[slot] = pack_key(acc, row);
             }
             return;
         }
@@ -966,6 +1005,40 @@ __device__ __forceinline__ float sqdiff4(const float4 a, const float4 b)
     return (dx * dx + dy * dy) + (dz * dz + dw * dw);
 }
 
+// float64 squared distance of one row by one thread, in the fixed order (ascending j:
+// d = q_j - x_j; t = d * d; acc = acc + t); the row and the query are read 16 float4 at a time,
+// all in flight before the sums (rows and queries are 16-byte aligned, n a multiple of 4)
+__device__ __forceinline__ double row_d2_f64(const float* __restrict__ x, const float* __restrict__ q, int n)
+{
+    const float4* x4 = reinterpret_cast<const float4*>(x);
+    const float4* q4 = reinterpret_cast<const float4*>(q);
+    const int nv = n >> 2;
+    double acc = 0.0;
+    for (int v0 = 0; v0 < nv; v0 += 16) {
+        float4 xb[16], qb[16];
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const bool ok = v0 + u < nv;
+            xb[u] = ok ? x4[v0 + u] : make_float4(0.f, 0.f, 0.f, 0.f);
+            qb[u] = ok ? q4[v0 + u] : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            if (v0 + u < nv) {
+                const double dx = (double)qb[u].x - (double)xb[u].x;
+                acc = acc + dx * dx;
+                const double dy = (double)qb[u].y - (double)xb[u].y;
+                acc = acc + dy * dy;
+                const double dz = (double)qb[u].z - (double)xb[u].z;
+                acc = acc + dz * dz;
+                const double dw = (double)qb[u].w - (double)xb[u].w;
+                acc = acc + dw * dw;
+            }
+        }
+    }
+    return acc;
+}
+
 __device__ void resolve_block(const QueryArgs& A, const float* __restrict__ q, long long* out_idx,
                               double* out_dist, long long qi)
 {
@@ -1032,13 +1105,7 @@ __device__ void resolve_block(const QueryArgs& A, const float* __restrict__ q, l
         for (uint32_t e = tid; e < count; e += 256) {
             const uint2 v = A.done[e];
             if ((double)__uint_as_float(v.y) > band) continue;
-            const float* x = A.X + (long long)v.x * n;
-            double acc = 0.0;
-            for (int j = 0; j < n; ++j) {
-                const double d = (double)q[j] - (double)x[j];
-                const double t = d * d;
-                acc = acc + t;
-            }
+            const double acc = row_d2_f64(A.X + (long long)v.x * n, q, n);
             ++mine;
             if (acc < bd || (acc == bd && (long long)v.x < bi)) { bd = acc; bi = v.x; }
         }
@@ -1114,16 +1181,7 @@ __device__ void resolve_knn_block(const QueryArgs& A, const float* __restrict__ 
     const uint32_t nc = ncand;
     const bool over = nc > (uint32_t)kKnnResolve;
     const uint32_t m = over ? 0u : nc;
-    for (uint32_t c = tid; c < m; c += 256) {
-        const float* x = A.X + (long long)c_idx[c] * n;
-        double acc = 0.0;
-        for (int j = 0; j < n; ++j) {
-            const double d = (double)q[j] - (double)x[j];
-            const double t = d * d;
-            acc = acc + t;
-        }
-        c_d[c] = acc;
-    }
+    for (uint32_t c = tid; c < m; c += 256) c_d[c] = row_d2_f64(A.X + (long long)c_idx[c] * n, q, n);
     __syncthreads();
     bool wrote = false;
     for (uint32_t c = tid; c < m; c += 256) {
@@ -1385,15 +1443,12 @@ __global__ __launch_bounds__(256) void k_refine_resolve(QueryArgs A, const float
         if (r) atomicAdd(&A.qs->n_refined, r);
         if (ab) atomicAdd(&A.qs->n_abandon, ab);
     }
-    // The last block to finish resolves. Only blocks that stored candidates need a release
-    // fence (a device-scope fence writes back this XCD's L2, which is costly when every block
-    // does it); the counters above are device-scope atomics.
-    __shared__ int s_wrote;
-    if (tid == 0) s_wrote = 0;
+    // The last block to finish resolves. Only the waves that stored candidates need a release
+    // fence, each for its own stores, before the block's barrier (a device-scope fence writes
+    // back this XCD's L2, which is costly when many waves do it); the counters above are
+    // device-scope atomics.
+    if (__ballot(wrote) != 0ull) __threadfence();
     __syncthreads();
-    if (wrote) s_wrote = 1;
-    __syncthreads();
-    if (s_wrote) __threadfence();
     if (tid == 0) s_last = atomicAdd(&A.qs->blocks_done, 1u) == active - 1;
     __syncthreads();
     if (!s_last) return;
