@@ -66,13 +66,15 @@ struct alignas(256) QState {
     unsigned long long k64;
     long long win_lo, win_hi;
     // working fields (reset after every query)
-    unsigned long long bsf_key;
     unsigned long long seed_key;
     unsigned long long head_key;   // (fine bound bits, index) of the survivor with the smallest bound
     uint32_t n_surv, n_refined, n_abandon, n_bsf_upd, n_done, n_read;
     uint32_t err;
     uint32_t blocks_done;
     uint32_t pad1;
+    // the best-so-far on a line of its own: the seed's and refine's atomics and the refine's
+    // re-reads of it do not queue behind the counters' atomics on one memory channel line
+    alignas(128) unsigned long long bsf_key;
     QResult res;
 };
 
