@@ -159,6 +159,30 @@ def test_lb_scan_survivor_sandwich(small):
             assert np.all(bd <= ref[got] * (1 + 2e-6) + 1e-30)   # table terms are rounded down
 
 
+@pytest.mark.parametrize("N", [33, 129, 4095, 10_007])
+def test_lb_scan_ragged_sizes(N, oracle_native):
+    """The scan's runs of 32 and lines of 4 runs with a partial last run and a partial last
+    line (and fewer lines than a full grid): the survivors are still every series whose bound
+    is within the threshold, as a scan of every word gives."""
+    _need_gpu()
+    import paper_2009_00166_amd as paris
+    X = synth.random_walks(N, 256, seed=N)
+    idx = paris.build(torch.from_numpy(X).cuda())
+    _, S = oracle_native.summarise(X)
+    Qn, _, _ = synth.noisy_queries(X, 3, seed=N + 1, sigma=0.3)
+    for q in list(Qn) + list(synth.fresh_walk_queries(2, 256, seed=N + 2)):
+        ref = lower_bound_sq(paa(q), S, 16)
+        for frac in (0.0, 0.01, 0.3, 1.0):
+            thr = float(np.quantile(ref, frac))
+            I, Bd, cnt, st = idx.lb_scan(torch.from_numpy(q).cuda(), thr)
+            got = I.cpu().numpy().astype(np.int64)
+            assert len(np.unique(got)) == len(got) == cnt
+            strict = set(np.nonzero(ref < thr * (1 - REL))[0].tolist())
+            loose = set(np.nonzero(ref <= thr * (1 + REL))[0].tolist())
+            assert strict <= set(got.tolist()) <= loose
+    idx.close()
+
+
 def test_lb_scan_overflow_reports_count(small):
     idx = small["index"]
     q = torch.from_numpy(small["Q"][1]).cuda()
